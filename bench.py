@@ -1,0 +1,153 @@
+#!/usr/bin/env python3
+"""Benchmark of the SIPF-W step on one MI355X: particle-steps/s and the HBM roofline fraction
+of the dominant kernel, float32 form (float64 masses and sums) beside the plain float64 form,
+on the 128^3-grid / 2^23-particle four-blob workload (dt = 5e-4).
+
+One "step" is the whole hot path: reaction + 3D FFT solves for m and w + spectral gradient of
+v + gather / Euler-Maruyama push / mass update / deposit + diagnostics reductions.  Inputs are
+resident in HBM before the timed region; the timed region replays the captured step graph.
+
+Prints one JSON line.  `python bench.py --gpus N --steps K --warmup W`.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+METRIC = ("particle-steps/s + HBM GB/s fraction at 128^3/2^23 (FP32 vs FP64); "
+          "p50/p99 served")
+
+
+def stage_bytes(N, P, s):
+    """Bytes each stage must move per step by design (reads + writes), s = 4 or 8."""
+    G = N ** 3
+    half = (N // 2 + 1) * N * N * 2 * s  # one half spectrum
+    return {
+        "zfwd": G * 4 * s + G * 2 * s + 3 * half,
+        "yfwd": 6 * half,
+        "xpass": 6 * half,
+        "yinv": 9 * half,
+        "zinv": 5 * half + G * s + G * 6 * s,
+        # particles: read x,y,z,a; write x,y,z,a (SURVEY per-particle figure; the 4-byte
+        # noise key is not counted) + gather array read once + deposit target written once
+        "particles": P * (6 * s + 16) + G * 5 * s,
+        "diag": P * (3 * s + 8 + 4) + G * 4 * s,
+    }
+
+
+def run_form(ic, precision, steps, warmup, profile_steps):
+    import torch
+    from paper_2605_20140_amd import sipf
+    prm = ic["params"]
+    p = sipf.make_params(precision=precision, **prm)
+    sim = sipf.Simulation(p, ic["X0"], ic["a0"], ic["v0"], ic["m0"], ic["w0"], device="cuda:0")
+    stream = torch.cuda.current_stream()
+    sim.step(warmup)
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    wall0 = time.perf_counter()
+    t0.record(stream)
+    sim.step(steps)
+    t1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = t0.elapsed_time(t1)
+    stage_ms = sim.step_timed(profile_steps)
+    out = sim.fields(particles=False)
+    sim.close()
+    d = out["diag"]
+    s = 4 if precision == 1 else 8
+    sb = stage_bytes(prm["N"], prm["P"], s)
+    stages = {}
+    for k, tot in stage_ms.items():
+        avg = tot / profile_steps
+        stages[k] = dict(ms=round(avg, 5), GBs=round(sb[k] / (avg * 1e-3) / 1e9, 1))
+    dominant = max(stages, key=lambda k: stages[k]["ms"])
+    ach = sb[dominant] / (stages[dominant]["ms"] * 1e-3) / 1e9
+    return dict(
+        value=prm["P"] * steps / (ms * 1e-3),
+        ms_per_step=ms / steps,
+        wall_ms_per_step=wall * 1e3 / steps,
+        stages=stages,
+        roofline=dict(bound="hbm", kernel=dominant, achieved=round(ach, 1), peak=HBM_PEAK_GBS,
+                      unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4), traffic=None,
+                      algorithmic_bytes=sb[dominant]),
+        check=dict(n_nan=d["n_nan"], step=d["step"],
+                   mass_rel_gap=abs(d["mass_grid"] / d["mass_particles"] - 1.0)),
+    )
+
+
+def cpu_baseline(ic):
+    """FP64 numpy oracle, one step of the same workload on the host (bounded sample)."""
+    from oracle import step as S
+    prm = ic["params"]
+    op = S.Params(N=prm["N"], dt=prm["dt"], L=prm["L"], D_u=prm["D_u"], chi=prm["chi"],
+                  D_m=prm["D_m"], D_w=prm["D_w"], alpha=prm["alpha"], beta=prm["beta"],
+                  gamma=prm["gamma"], seed=prm["seed"])
+    st = S.State(ic["X0"], ic["a0"], ic["v0"], ic["m0"], ic["w0"], 0)
+    t = time.perf_counter()
+    S.step(st, op)
+    dt = time.perf_counter() - t
+    return dict(value=prm["P"] / dt, unit="particle-steps/s", cores=1, kind="oracle",
+                sample=f"1 step of the full workload ({prm['N']}^3 grid, {prm['P']} particles), "
+                       "float64 numpy oracle, single thread", seconds=round(dt, 2))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="blobs128")
+    ap.add_argument("--profile-steps", type=int, default=20)
+    ap.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has no "
+              "multi-GPU path; the sharding design is described in DESIGN.md.", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    from paper_2605_20140_amd import workloads as W
+    ic = W.make_initial_state(args.workload)
+    prm = ic["params"]
+    r32 = run_form(ic, 1, args.steps, args.warmup, args.profile_steps)
+    r64 = None if args.no_fp64 else run_form(ic, 0, args.steps, args.warmup, args.profile_steps)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(ic)
+    line = {
+        "metric": METRIC,
+        "value": r32["value"],
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r32["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "N": prm["N"], "P": prm["P"], "dt": prm["dt"],
+                   "form": "fp32 positions/fields/FFT, fp64 masses and sums",
+                   "parallelism": "single GPU"},
+        "roofline": r32["roofline"],
+        "cpu_baseline": cpu,
+        "stages": r32["stages"],
+        "check": r32["check"],
+        "fp64": None if r64 is None else {
+            "value": r64["value"], "ms_per_step": r64["ms_per_step"], "dtype": "f64",
+            "roofline": r64["roofline"], "stages": r64["stages"], "check": r64["check"]},
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,174 @@
+/*
+ * sipf.h -- C ABI of libsipf: one time step of the SIPF-W method (stochastic interacting
+ * particle-field method with weighted particles) for the 3D haptotaxis
+ * reaction-diffusion-advection system, on one AMD Instinct MI355X (gfx950).
+ *
+ * Method: Hu, Wang, Xin, Zhang, "A Novel Stochastic Particle-Field Algorithm for a
+ * Reaction-Diffusion-Advection Cancer Invasion Model".
+ *
+ * Model (eq. haptotaxis-system): cell density u carried by P weighted particles (X_p, a_p)
+ * (eq. u_hat); ECM v, enzyme m, oxygen w on a periodic N^3 grid of the cube [0, L)^3, nodes
+ * at q h, h = L / N (eq. vmw_hat: nodal values and Fourier coefficients are equivalent).
+ *
+ * One step n -> n+1 (Alg. sipf-pic), all right-hand sides at time n:
+ *   ubar  = sum_p a_p R_h(X_p, .)                         P2G, trilinear   (Alg. p2g)
+ *   m*    = m + tau ubar,  w* = w + tau (gamma v - eta(ubar) w)   explicit reaction
+ *   v'    = v exp(-alpha tau m)                            pointwise ECM update
+ *   m', w'= IFFT( FFT(m*, w*) / (1 + tau (R + D |k|^2)) ) implicit spectral solves
+ *                                                          (eq. k_q_tilde_update)
+ *   grad v= IFFT(i k FFT(v))                               spectral gradient (eq. gradv)
+ *   X'    = X + chi tau (grad v)_H(X) + sqrt(2 D_u tau) Z  Euler-Maruyama (eq. u_hat_update)
+ *   a'    = a exp(tau (rho(w_H(X)) - 1))                   mass update (eq. SDE)
+ * with rho(w) = 2w/(1+w), eta(u) = 2u/(1+u), G2P by K_h = h^3 R_h (Alg. g2p), and Z drawn from
+ * Philox4x32-10 with counter (p, n, sim_id_lo, sim_id_hi) and key (seed_lo, seed_hi)
+ * followed by Box-Muller (z1, z2 from words 0-1, z3 from words 2-3; u = (r + 1/2) 2^-32).
+ *
+ * Conventions for every entry point:
+ *   - return 0 on success or a negative SIPF_E* code; sipf_last_error() then holds a message
+ *     (thread-local, valid until the next failing call on that thread); no C++ exception
+ *     crosses the ABI;
+ *   - host arrays are float64, owned by the caller, read (or written) during the call only;
+ *   - grid arrays are row-major [i1][i2][i3] (i3 fastest), N^3 entries; particle positions
+ *     are structure-of-arrays X[0..P) = x1, X[P..2P) = x2, X[2P..3P) = x3;
+ *   - the device workspace is owned by the caller (for example a torch uint8 tensor); the
+ *     library owns the layout inside it and keeps all state there, so several simulations
+ *     can be resident at once, each in its own workspace;
+ *   - calls on one sipf_sim must not overlap; the stream given at init orders all work.
+ */
+#ifndef SIPF_H
+#define SIPF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* error codes */
+#define SIPF_OK 0
+#define SIPF_EINVAL (-1) /* invalid parameter or input array                              */
+#define SIPF_ENOMEM (-2) /* workspace smaller than sipf_state_bytes() or misaligned host   */
+#define SIPF_EHIP (-3)   /* HIP runtime error (message names the call)                     */
+#define SIPF_EPOS (-4)   /* positivity / finiteness violated (only with SIPF_FLAG_STRICT)  */
+
+/* precision of positions, grid fields and FFTs; particle masses and all mass sums are
+ * float64 in both forms */
+#define SIPF_FP64 0
+#define SIPF_FP32 1
+
+/* flags (bitwise or) -- test hooks and variants of the step */
+#define SIPF_FLAG_FREEZE_W 0x01u    /* keep w^{n+1} = w^n                                    */
+#define SIPF_FLAG_FREEZE_V 0x02u    /* keep v^{n+1} = v^n                                    */
+#define SIPF_FLAG_FREEZE_M 0x04u    /* keep m^{n+1} = m^n                                    */
+#define SIPF_FLAG_NO_NOISE 0x08u    /* Wiener increments set to zero                          */
+#define SIPF_FLAG_LINEAR_MASS 0x10u /* a' = a (1 + tau rho - tau), eq. u_hat_update           */
+#define SIPF_FLAG_IMPLICIT_V 0x20u  /* v' = v / (1 + alpha tau m), positivity section          */
+#define SIPF_FLAG_STRICT 0x40u      /* sipf_fields returns SIPF_EPOS on a violated invariant  */
+#define SIPF_FLAG_EXP_DIFFUSION 0x80u   /* multiplier exp(-tau (R + D k^2)), eq. k_q_update   */
+#define SIPF_FLAG_ALIASED_DIFFUSION 0x100u /* aliased positive multiplier, Lemma kernel      */
+
+/* Parameters (eq. haptotaxis-system, eq. g_t: D = diag(0, D_m, D_w), R = diag(0, beta, 1)). */
+typedef struct {
+  double L;              /* period of the cube, > 0                                      */
+  int32_t N;             /* grid nodes per axis: power of two in [4, 512]                 */
+  int32_t reserved0;     /* must be 0                                                     */
+  int64_t P;             /* particles, 0 <= P < 2^32                                      */
+  double dt;             /* time step tau, 0 < dt <= 0.5 (positivity lemma)               */
+  double D_u, chi, D_m, D_w, alpha, beta, gamma; /* model constants, all >= 0             */
+  uint64_t seed;         /* Philox key                                                    */
+  uint64_t sim_id;       /* Philox counter words 2-3: distinct per simulation              */
+  uint64_t step0;        /* absolute index n of the first step (restart from a checkpoint)*/
+  int32_t precision;     /* SIPF_FP64 or SIPF_FP32                                         */
+  int32_t deposit_order; /* 2: trilinear assignment; 4: fourth-order assignment R_h^(4)    */
+  uint32_t flags;        /* SIPF_FLAG_*                                                    */
+  int32_t resort_every;  /* particle tile re-binning period in steps (0: library default)  */
+  double H0;             /* low-pass cutoff exp(-2 pi^2 |q|^2 / H0^2); 0 = off             */
+} sipf_params;
+
+/* Diagnostics of the current state (Lemma mass, Corollary mass, positivity lemma). */
+typedef struct {
+  double mass_particles; /* sum_p a_p (float64 accumulation)                               */
+  double mass_grid;      /* h^3 sum_q ubar_q of the current particles                      */
+  double mass_m;         /* h^3 sum_q m_q                                                  */
+  double min_v, min_m, min_w, max_m, max_w;
+  double min_a, max_a;
+  double min_u;          /* min_q ubar_q                                                    */
+  int64_t n_nan;         /* non-finite values among particles and fields                   */
+  int64_t n_neg_m, n_neg_w;
+  int64_t step;          /* absolute step index n of the state                             */
+} sipf_diag;
+
+typedef struct sipf_sim sipf_sim; /* opaque, library-owned host handle */
+
+/* Device workspace bytes a simulation with these parameters needs (alignment 256 B).
+ * Errors: SIPF_EINVAL for invalid parameters. */
+int sipf_state_bytes(const sipf_params* prm, size_t* bytes);
+
+/* Create a simulation in the caller's device workspace and upload the initial state
+ * (Alg. sipf-pic initialisation: particles X0 ~ u(., 0) with masses a0; v0, m0, w0 sampled
+ * at the nodes).  d_workspace: device pointer, 256-byte aligned, at least
+ * sipf_state_bytes() long, owned by the caller and not used by anything else while the
+ * simulation exists.  hip_stream: hipStream_t on which all later work of this simulation is
+ * ordered (NULL = the default stream).  X0: 3P float64 (SoA), a0: P float64 > 0, v0/m0/w0:
+ * N^3 float64 each, finite, >= 0.  Positions are wrapped into [0, L).  In SIPF_FP32
+ * precision, positions and fields are rounded to float32; a0 stays float64.
+ * The call is synchronous.  On success *out receives the handle.
+ * Errors: SIPF_EINVAL (parameters or inputs), SIPF_ENOMEM (workspace), SIPF_EHIP. */
+int sipf_init(const sipf_params* prm, void* d_workspace, size_t bytes, void* hip_stream,
+              const double* X0, const double* a0, const double* v0, const double* m0,
+              const double* w0, sipf_sim** out);
+
+/* Enqueue nsteps >= 0 steps (Alg. sipf-pic loop body) on the simulation's stream; returns
+ * without waiting.  Each step also recomputes the diagnostics.  Errors: SIPF_EINVAL,
+ * SIPF_EHIP. */
+int sipf_step(sipf_sim* sim, int32_t nsteps);
+
+/* Served form: enqueue nsteps steps of nsims resident simulations as one set of batched
+ * launches (each kernel launch covers the work of all listed simulations).  All must share
+ * the precision, deposit order and device; they run on the stream of sims[0].  Results are
+ * identical to stepping each simulation alone (up to the order of floating-point atomic
+ * additions).  Errors: SIPF_EINVAL (empty list, mixed precision, a repeated simulation),
+ * SIPF_EHIP. */
+int sipf_step_batch(sipf_sim* const* sims, int32_t nsims, int32_t nsteps);
+
+/* Wait for the simulation's stream and copy the state to the host: any pointer may be NULL.
+ * v, m, w: N^3 float64; X: 3P float64 SoA in the particle order given at init; a: P float64;
+ * diag: diagnostics of the state.  With SIPF_FLAG_STRICT, returns SIPF_EPOS (after filling
+ * the outputs) if a hard invariant fails: a non-finite value, ubar < 0, v <= 0, a <= 0.
+ * Errors: SIPF_EHIP, SIPF_EPOS. */
+int sipf_fields(sipf_sim* sim, double* v, double* m, double* w, double* X, double* a,
+                sipf_diag* diag);
+
+/* Intermediate grids of the last step, for checks of single stages: u_bar (N^3, the P2G
+ * deposit of the current particles) and grad_v (3 N^3: d1 v, d2 v, d3 v of the field v
+ * that drove the last push).  Either pointer may be NULL.  Synchronous.
+ * Errors: SIPF_EHIP. */
+int sipf_aux(sipf_sim* sim, double* u_bar, double* grad_v);
+
+/* Profiling hook: run nsteps steps eagerly (kernel launches, not the captured graph) with HIP
+ * events between the stages, and add each stage's elapsed milliseconds to stage_ms[k]
+ * (caller-owned, SIPF_NUM_STAGES floats; stage order: SIPF_STAGE_*).  Synchronous.
+ * Results are identical to sipf_step.  Errors: SIPF_EINVAL, SIPF_EHIP. */
+#define SIPF_NUM_STAGES 7
+#define SIPF_STAGE_ZFWD 0      /* reaction + forward z transforms            */
+#define SIPF_STAGE_YFWD 1      /* forward y transforms                       */
+#define SIPF_STAGE_XPASS 2     /* x transforms + spectral solves + d1 v      */
+#define SIPF_STAGE_YINV 3      /* inverse y transforms + d2 v                */
+#define SIPF_STAGE_ZINV 4      /* inverse z transforms + d3 v, field writes  */
+#define SIPF_STAGE_PARTICLES 5 /* gather + push + mass update + deposit      */
+#define SIPF_STAGE_DIAG 6      /* reductions                                 */
+int sipf_step_timed(sipf_sim* sim, int32_t nsteps, float* stage_ms);
+
+/* Free the host handle and the library's HIP objects (graphs, events); the workspace
+ * stays the caller's.  Waits for the simulation's outstanding work.  NULL is a no-op. */
+void sipf_destroy(sipf_sim* sim);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char* sipf_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SIPF_H */

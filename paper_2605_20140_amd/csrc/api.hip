@@ -1,0 +1,664 @@
+// C ABI of libsipf (declared in include/sipf.h): validation, the workspace layout, upload of
+// the initial state (Alg. sipf-pic initialisation), the per-step launch sequence captured
+// once as a HIP graph, the batched launch set of the served form, and state export.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "sipf_internal.h"
+
+using namespace sipf;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(call)                                                                      \
+  do {                                                                                    \
+    hipError_t e_ = (call);                                                               \
+    if (e_ != hipSuccess)                                                                 \
+      return fail(SIPF_EHIP, std::string(#call) + ": " + hipGetErrorString(e_));          \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+struct Layout {
+  size_t total = 0;
+  size_t desc, blk, step, diag;
+  size_t x, y, z, a, id;
+  size_t ubar, v, m, w, g4;
+  size_t SM, SW, SV, SGx, SGy;
+  size_t tw, mtab;
+};
+
+bool is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
+
+int validate_params(const sipf_params* p) {
+  if (!p) return fail(SIPF_EINVAL, "params is NULL");
+  if (!(p->N >= 4 && p->N <= 512 && is_pow2(p->N)))
+    return fail(SIPF_EINVAL, "N must be a power of two in [4, 512]");
+  if (p->reserved0 != 0) return fail(SIPF_EINVAL, "reserved0 must be 0");
+  if (p->P < 0 || p->P >= (int64_t(1) << 32))
+    return fail(SIPF_EINVAL, "P must satisfy 0 <= P < 2^32");
+  if (!(isfinite(p->L) && p->L > 0)) return fail(SIPF_EINVAL, "L must be finite and > 0");
+  if (!(p->dt > 0 && p->dt <= 0.5)) return fail(SIPF_EINVAL, "dt must be in (0, 0.5]");
+  const double c[] = {p->D_u, p->chi, p->D_m, p->D_w, p->alpha, p->beta, p->gamma};
+  for (double v : c)
+    if (!(isfinite(v) && v >= 0)) return fail(SIPF_EINVAL, "model constants must be finite, >= 0");
+  if (p->precision != SIPF_FP64 && p->precision != SIPF_FP32)
+    return fail(SIPF_EINVAL, "precision must be SIPF_FP64 or SIPF_FP32");
+  if (p->deposit_order != 2)
+    return fail(SIPF_EINVAL, "deposit_order must be 2 (trilinear)");
+  if ((p->flags & SIPF_FLAG_EXP_DIFFUSION) && (p->flags & SIPF_FLAG_ALIASED_DIFFUSION))
+    return fail(SIPF_EINVAL, "EXP_DIFFUSION and ALIASED_DIFFUSION are exclusive");
+  if (p->flags & ~0x1FFu) return fail(SIPF_EINVAL, "unknown flag bits");
+  if (!(isfinite(p->H0) && p->H0 == 0.0))
+    return fail(SIPF_EINVAL, "the low-pass filter (H0 > 0) is not available; use H0 = 0");
+  if (p->resort_every < 0) return fail(SIPF_EINVAL, "resort_every must be >= 0");
+  if (p->flags & SIPF_FLAG_ALIASED_DIFFUSION) {
+    // The aliased multiplier is the DFT of the heat kernel sampled at the nodes (Lemma
+    // kernel); it approximates exp(-tau D k^2) only if the grid resolves that kernel.  Its
+    // largest deviation from the plain exponential is at the Nyquist corner, about
+    // 2 exp(-tau D (2 pi / L)^2 (N/2)^2) per axis.
+    const double Dmin = std::min(p->D_m, p->D_w);
+    const double k = 2.0 * M_PI / p->L * (p->N / 2);
+    if (!(p->dt * Dmin * k * k > 10.0))
+      return fail(SIPF_EINVAL,
+                  "ALIASED_DIFFUSION needs a grid that resolves the heat kernel: "
+                  "dt * min(D_m, D_w) * (pi N / L)^2 must exceed 10");
+  }
+  return SIPF_OK;
+}
+
+Layout make_layout(const sipf_params& p) {
+  const size_t s = p.precision == SIPF_FP32 ? 4 : 8;
+  const size_t N = (size_t)p.N, G = N * N * N, P = (size_t)p.P, H = N / 2 + 1;
+  Layout L;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = o;
+    o = align_up(o + bytes);
+    return r;
+  };
+  L.desc = take(std::max(sizeof(SimDev<double>), sizeof(SimDev<float>)));
+  L.blk = take(sizeof(int) * K_COUNT * 2);
+  L.step = take(sizeof(uint64_t));
+  L.diag = take(sizeof(unsigned long long) * D_COUNT);
+  L.x = take(P * s);
+  L.y = take(P * s);
+  L.z = take(P * s);
+  L.a = take(P * 8);
+  L.id = take(P * 4);
+  L.ubar = take(G * s);
+  L.v = take(G * s);
+  L.m = take(G * s);
+  L.w = take(G * s);
+  L.g4 = take(G * 4 * s);
+  const size_t spec = H * N * N * 2 * s;
+  L.SM = take(spec);
+  L.SW = take(spec);
+  L.SV = take(spec);
+  L.SGx = take(spec);
+  L.SGy = take(spec);
+  L.tw = take((N / 2) * 2 * s);
+  L.mtab = take(3 * N * s);
+  L.total = o;
+  return L;
+}
+
+}  // namespace
+
+struct sipf_sim {
+  sipf_params prm;
+  unsigned char* ws = nullptr;
+  size_t bytes = 0;
+  Layout lay;
+  hipStream_t stream = nullptr;
+  hipStream_t cap = nullptr;
+  int device = 0;
+  int counts[K_COUNT];
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  unsigned char host_desc[std::max(sizeof(SimDev<double>), sizeof(SimDev<float>))];
+};
+
+namespace {
+
+template <typename T>
+Batch<T> single_batch(const sipf_sim* s) {
+  Batch<T> b;
+  b.sims = reinterpret_cast<const SimDev<T>*>(s->ws + s->lay.desc);
+  b.blk = reinterpret_cast<const int*>(s->ws + s->lay.blk);
+  b.nsims = 1;
+  return b;
+}
+
+template <typename T>
+void enqueue_step(const Batch<T>& b, const int* tot, int nsims, hipStream_t st) {
+  launch_zfwd<T>(b, tot[K_ZFWD], st);
+  launch_yfwd<T>(b, tot[K_YFWD], st);
+  launch_xpass<T>(b, tot[K_XPASS], st);
+  launch_yinv<T>(b, tot[K_YINV], st);
+  launch_zinv<T>(b, tot[K_ZINV], st);
+  launch_particles<T>(b, tot[K_PART], st);
+  launch_diag_step<T>(b, tot[K_DIAG], nsims, st);
+}
+
+// float64 multiplier tables of the separable diffusion forms and of the low-pass filter,
+// indexed by the DFT position of one axis.
+void axis_tables(const sipf_params& p, int field, std::vector<double>& tab) {
+  const int N = p.N;
+  tab.assign(N, 1.0);
+  const double D = field == 0 ? p.D_m : p.D_w;
+  const double c = p.dt * D * (2.0 * M_PI / p.L) * (2.0 * M_PI / p.L);
+  for (int k = 0; k < N; ++k) {
+    const double q = k < N / 2 ? k : k - N;
+    if (p.flags & SIPF_FLAG_ALIASED_DIFFUSION) {
+      // lattice sum over q + n N; terms decay like exp(-c (n N)^2)
+      long double acc = 0.0L;
+      for (int n = -64; n <= 64; ++n) {
+        const long double qq = (long double)q + (long double)n * N;
+        const long double t = expl(-(long double)c * qq * qq);
+        acc += t;
+        if (n > 0 && t < 1e-40L) break;
+      }
+      tab[k] = (double)acc;
+    } else {
+      tab[k] = exp(-c * q * q);
+    }
+  }
+}
+
+template <typename T>
+int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
+           const double* m0, const double* w0) {
+  const sipf_params& p = sim->prm;
+  const Layout& L = sim->lay;
+  const int N = p.N;
+  const int64_t P = p.P;
+  const size_t G = (size_t)N * N * N;
+  unsigned char* ws = sim->ws;
+
+  SimDev<T> d;
+  memset(&d, 0, sizeof(d));
+  d.N = N;
+  int lg = 0;
+  while ((1 << lg) < N) ++lg;
+  d.log2N = lg;
+  d.P = P;
+  const int E = elems_per_block<T>();
+  d.rows_per_blk = (int)std::min<int64_t>((int64_t)N * N, E / N);
+  d.lines_per_blk = E / N;
+  d.cols_per_blk = std::min(N, E / N);
+  d.flags = (int)p.flags;
+  d.L = (T)p.L;
+  d.inv_h = (T)(N / p.L);
+  const double h = p.L / N;
+  d.inv_h3 = (T)(1.0 / (h * h * h));
+  d.two_pi_over_L = (T)(2.0 * M_PI / p.L);
+  d.inv_n3 = (T)(1.0 / ((double)N * N * N));
+  d.inv_n2 = (T)(1.0 / ((double)N * N));
+  d.dt = p.dt;
+  d.D_u = p.D_u;
+  d.chi = p.chi;
+  d.D_m = p.D_m;
+  d.D_w = p.D_w;
+  d.alpha = p.alpha;
+  d.beta = p.beta;
+  d.gamma = p.gamma;
+  d.noise_amp = (T)sqrt(2.0 * p.D_u * p.dt);
+  d.drift = (T)(p.chi * p.dt);
+  d.h3 = h * h * h;
+  d.seed_lo = (uint32_t)(p.seed & 0xFFFFFFFFu);
+  d.seed_hi = (uint32_t)(p.seed >> 32);
+  d.sim_lo = (uint32_t)(p.sim_id & 0xFFFFFFFFu);
+  d.sim_hi = (uint32_t)(p.sim_id >> 32);
+  d.mult_kind = (p.flags & (SIPF_FLAG_EXP_DIFFUSION | SIPF_FLAG_ALIASED_DIFFUSION)) ? 1 : 0;
+  d.use_lowpass = p.H0 > 0 ? 1 : 0;
+  d.x = reinterpret_cast<T*>(ws + L.x);
+  d.y = reinterpret_cast<T*>(ws + L.y);
+  d.z = reinterpret_cast<T*>(ws + L.z);
+  d.a = reinterpret_cast<double*>(ws + L.a);
+  d.id = reinterpret_cast<uint32_t*>(ws + L.id);
+  d.ubar = reinterpret_cast<T*>(ws + L.ubar);
+  d.v = reinterpret_cast<T*>(ws + L.v);
+  d.m = reinterpret_cast<T*>(ws + L.m);
+  d.w = reinterpret_cast<T*>(ws + L.w);
+  d.g4 = reinterpret_cast<vec4<T>*>(ws + L.g4);
+  d.SM = reinterpret_cast<cplx<T>*>(ws + L.SM);
+  d.SW = reinterpret_cast<cplx<T>*>(ws + L.SW);
+  d.SV = reinterpret_cast<cplx<T>*>(ws + L.SV);
+  d.SGx = reinterpret_cast<cplx<T>*>(ws + L.SGx);
+  d.SGy = reinterpret_cast<cplx<T>*>(ws + L.SGy);
+  d.tw = reinterpret_cast<cplx<T>*>(ws + L.tw);
+  d.mtab = reinterpret_cast<T*>(ws + L.mtab);
+  d.step = reinterpret_cast<uint64_t*>(ws + L.step);
+  d.diag = reinterpret_cast<unsigned long long*>(ws + L.diag);
+  memcpy(sim->host_desc, &d, sizeof(d));
+
+  block_counts<T>(d, sim->counts);
+  int blk[K_COUNT * 2];
+  for (int k = 0; k < K_COUNT; ++k) {
+    blk[2 * k] = 0;
+    blk[2 * k + 1] = sim->counts[k];
+  }
+
+  // host staging in the working precision
+  std::vector<T> hx(P), hy(P), hz(P);
+  const T LT = (T)p.L;
+  for (int64_t i = 0; i < P; ++i) {
+    double c3[3] = {X0[i], X0[P + i], X0[2 * P + i]};
+    T out[3];
+    for (int j = 0; j < 3; ++j) {
+      double q = c3[j] - p.L * floor(c3[j] / p.L);
+      if (q >= p.L || q < 0) q = 0.0;
+      T t = (T)q;
+      if (t >= LT) t = (T)0;
+      out[j] = t;
+    }
+    hx[i] = out[0];
+    hy[i] = out[1];
+    hz[i] = out[2];
+  }
+  std::vector<uint32_t> hid(P);
+  for (int64_t i = 0; i < P; ++i) hid[i] = (uint32_t)i;
+  std::vector<T> hv(G), hm(G), hw(G);
+  for (size_t i = 0; i < G; ++i) {
+    hv[i] = (T)v0[i];
+    hm[i] = (T)m0[i];
+    hw[i] = (T)w0[i];
+  }
+  std::vector<cplx<T>> htw(N / 2);
+  for (int k = 0; k < N / 2; ++k) {
+    const long double ang = 2.0L * 3.14159265358979323846264338327950288L * k / N;
+    htw[k].x = (T)cosl(ang);
+    htw[k].y = (T)(-sinl(ang));
+  }
+  std::vector<T> hmt(3 * N, (T)1);
+  if (d.mult_kind) {
+    std::vector<double> t;
+    for (int f = 0; f < 2; ++f) {
+      axis_tables(p, f, t);
+      for (int k = 0; k < N; ++k) hmt[f * N + k] = (T)t[k];
+    }
+  }
+  const uint64_t step0 = p.step0;
+
+  hipStream_t st = sim->stream;
+  HIPCHK(hipMemcpyAsync(ws + L.desc, &d, sizeof(d), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(ws + L.blk, blk, sizeof(blk), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(ws + L.step, &step0, sizeof(step0), hipMemcpyHostToDevice, st));
+  if (P > 0) {
+    HIPCHK(hipMemcpyAsync(d.x, hx.data(), P * sizeof(T), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d.y, hy.data(), P * sizeof(T), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d.z, hz.data(), P * sizeof(T), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d.a, a0, P * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d.id, hid.data(), P * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+  }
+  HIPCHK(hipMemcpyAsync(d.v, hv.data(), G * sizeof(T), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d.m, hm.data(), G * sizeof(T), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d.w, hw.data(), G * sizeof(T), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d.tw, htw.data(), (N / 2) * sizeof(cplx<T>), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(d.mtab, hmt.data(), 3 * N * sizeof(T), hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemsetAsync(d.ubar, 0, G * sizeof(T), st));
+  HIPCHK(hipMemsetAsync(d.g4, 0, G * sizeof(vec4<T>), st));
+  const Batch<T> b = single_batch<T>(sim);
+  launch_deposit<T>(b, sim->counts[K_DEPOSIT], st);
+  launch_diag<T>(b, sim->counts[K_DIAG], 1, st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipStreamSynchronize(st));  // host staging buffers are freed on return
+
+  // capture one step as a graph on a private stream; replays go to the caller's stream
+  HIPCHK(hipStreamCreateWithFlags(&sim->cap, hipStreamNonBlocking));
+  HIPCHK(hipStreamBeginCapture(sim->cap, hipStreamCaptureModeThreadLocal));
+  enqueue_step<T>(b, sim->counts, 1, sim->cap);
+  HIPCHK(hipStreamEndCapture(sim->cap, &sim->graph));
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipGraphInstantiate(&sim->exec, sim->graph, nullptr, nullptr, 0));
+  return SIPF_OK;
+}
+
+bool finite_array(const double* a, size_t n, bool nonneg, bool positive) {
+  for (size_t i = 0; i < n; ++i) {
+    const double v = a[i];
+    if (!isfinite(v)) return false;
+    if (nonneg && v < 0) return false;
+    if (positive && !(v > 0)) return false;
+  }
+  return true;
+}
+
+double decode_min(unsigned long long k) {
+  if (k == ~0ull) return 0.0;  // no data
+  const unsigned long long b = (k >> 63) ? (k & 0x7FFFFFFFFFFFFFFFull) : ~k;
+  double d;
+  memcpy(&d, &b, 8);
+  return d;
+}
+double decode_max(unsigned long long k) {
+  if (k == 0ull) return 0.0;  // no data
+  return decode_min(k);
+}
+double as_double(unsigned long long k) {
+  double d;
+  memcpy(&d, &k, 8);
+  return d;
+}
+
+template <typename T>
+int fields_t(sipf_sim* sim, double* v, double* m, double* w, double* X, double* a,
+             sipf_diag* diag) {
+  const sipf_params& p = sim->prm;
+  const SimDev<T>& d = *reinterpret_cast<const SimDev<T>*>(sim->host_desc);
+  const size_t G = (size_t)p.N * p.N * p.N;
+  const int64_t P = p.P;
+  HIPCHK(hipStreamSynchronize(sim->stream));
+  std::vector<T> buf(std::max<size_t>(G, (size_t)P));
+  auto grid = [&](const T* src, double* dst) -> int {
+    if (!dst) return SIPF_OK;
+    HIPCHK(hipMemcpy(buf.data(), src, G * sizeof(T), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < G; ++i) dst[i] = (double)buf[i];
+    return SIPF_OK;
+  };
+  int rc;
+  if ((rc = grid(d.v, v))) return rc;
+  if ((rc = grid(d.m, m))) return rc;
+  if ((rc = grid(d.w, w))) return rc;
+  if ((X || a) && P > 0) {
+    std::vector<uint32_t> id(P);
+    HIPCHK(hipMemcpy(id.data(), d.id, P * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    if (X) {
+      const T* comp[3] = {d.x, d.y, d.z};
+      for (int j = 0; j < 3; ++j) {
+        HIPCHK(hipMemcpy(buf.data(), comp[j], P * sizeof(T), hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < P; ++i) X[(int64_t)j * P + id[i]] = (double)buf[i];
+      }
+    }
+    if (a) {
+      std::vector<double> ha(P);
+      HIPCHK(hipMemcpy(ha.data(), d.a, P * sizeof(double), hipMemcpyDeviceToHost));
+      for (int64_t i = 0; i < P; ++i) a[id[i]] = ha[i];
+    }
+  }
+  unsigned long long acc[D_COUNT];
+  uint64_t step = 0;
+  HIPCHK(hipMemcpy(acc, d.diag, sizeof(acc), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(&step, d.step, sizeof(step), hipMemcpyDeviceToHost));
+  sipf_diag dg;
+  dg.mass_particles = as_double(acc[D_SUM_A]);
+  dg.mass_grid = as_double(acc[D_SUM_U]) * d.h3;
+  dg.mass_m = as_double(acc[D_SUM_M]) * d.h3;
+  dg.min_v = decode_min(acc[D_MIN_V]);
+  dg.min_m = decode_min(acc[D_MIN_M]);
+  dg.min_w = decode_min(acc[D_MIN_W]);
+  dg.max_m = decode_max(acc[D_MAX_M]);
+  dg.max_w = decode_max(acc[D_MAX_W]);
+  dg.min_a = decode_min(acc[D_MIN_A]);
+  dg.max_a = decode_max(acc[D_MAX_A]);
+  dg.min_u = decode_min(acc[D_MIN_U]);
+  dg.n_nan = (int64_t)acc[D_NAN];
+  dg.n_neg_m = (int64_t)acc[D_NEG_M];
+  dg.n_neg_w = (int64_t)acc[D_NEG_W];
+  dg.step = (int64_t)step;
+  if (diag) *diag = dg;
+  if (p.flags & SIPF_FLAG_STRICT) {
+    if (dg.n_nan != 0) return fail(SIPF_EPOS, "non-finite values in the state");
+    if (dg.min_u < 0) return fail(SIPF_EPOS, "negative deposited density");
+    if (!(dg.min_v > 0)) return fail(SIPF_EPOS, "non-positive ECM density v");
+    if (P > 0 && !(dg.min_a > 0)) return fail(SIPF_EPOS, "non-positive particle mass");
+  }
+  return SIPF_OK;
+}
+
+template <typename T>
+int aux_t(sipf_sim* sim, double* u_bar, double* grad_v) {
+  const sipf_params& p = sim->prm;
+  const SimDev<T>& d = *reinterpret_cast<const SimDev<T>*>(sim->host_desc);
+  const size_t G = (size_t)p.N * p.N * p.N;
+  HIPCHK(hipStreamSynchronize(sim->stream));
+  if (u_bar) {
+    std::vector<T> buf(G);
+    HIPCHK(hipMemcpy(buf.data(), d.ubar, G * sizeof(T), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < G; ++i) u_bar[i] = (double)buf[i];
+  }
+  if (grad_v) {
+    std::vector<vec4<T>> buf(G);
+    HIPCHK(hipMemcpy(buf.data(), d.g4, G * sizeof(vec4<T>), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < G; ++i) {
+      grad_v[i] = (double)buf[i].x;
+      grad_v[G + i] = (double)buf[i].y;
+      grad_v[2 * G + i] = (double)buf[i].z;
+    }
+  }
+  return SIPF_OK;
+}
+
+// ---- batched launches (served form) --------------------------------------------------------
+struct BatchSlot {
+  void* dev = nullptr;
+  void* host = nullptr;  // pinned staging
+  size_t cap = 0;
+  hipEvent_t done = nullptr;
+  int device = -1;
+};
+std::mutex g_batch_mu;
+BatchSlot g_slots[4];
+int g_next_slot = 0;
+
+template <typename T>
+int step_batch_t(sipf_sim* const* sims, int nsims, int nsteps) {
+  hipStream_t st = sims[0]->stream;
+  const size_t desc_bytes = sizeof(SimDev<T>) * nsims;
+  const size_t blk_off = align_up(desc_bytes);
+  const size_t bytes = blk_off + sizeof(int) * K_COUNT * (nsims + 1);
+  std::vector<int> tot(K_COUNT, 0);
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  BatchSlot& sl = g_slots[g_next_slot];
+  g_next_slot = (g_next_slot + 1) % 4;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (sl.done) HIPCHK(hipEventSynchronize(sl.done));  // previous use of this slot finished
+  if (sl.cap < bytes || sl.device != dev) {
+    if (sl.dev) HIPCHK(hipFree(sl.dev));
+    if (sl.host) HIPCHK(hipHostFree(sl.host));
+    if (sl.done) HIPCHK(hipEventDestroy(sl.done));
+    sl.dev = sl.host = nullptr;
+    sl.done = nullptr;
+    const size_t cap = std::max<size_t>(bytes * 2, 1 << 16);
+    HIPCHK(hipMalloc(&sl.dev, cap));
+    HIPCHK(hipHostMalloc(&sl.host, cap, hipHostMallocDefault));
+    HIPCHK(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
+    sl.cap = cap;
+    sl.device = dev;
+  }
+  unsigned char* h = static_cast<unsigned char*>(sl.host);
+  int* blk = reinterpret_cast<int*>(h + blk_off);
+  for (int k = 0; k < K_COUNT; ++k) {
+    int acc = 0;
+    for (int i = 0; i < nsims; ++i) {
+      blk[k * (nsims + 1) + i] = acc;
+      acc += sims[i]->counts[k];
+    }
+    blk[k * (nsims + 1) + nsims] = acc;
+    tot[k] = acc;
+  }
+  for (int i = 0; i < nsims; ++i)
+    memcpy(h + sizeof(SimDev<T>) * i, sims[i]->host_desc, sizeof(SimDev<T>));
+  HIPCHK(hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, st));
+  Batch<T> b;
+  b.sims = reinterpret_cast<const SimDev<T>*>(sl.dev);
+  b.blk = reinterpret_cast<const int*>(static_cast<unsigned char*>(sl.dev) + blk_off);
+  b.nsims = nsims;
+  for (int s = 0; s < nsteps; ++s) enqueue_step<T>(b, tot.data(), nsims, st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventRecord(sl.done, st));
+  return SIPF_OK;
+}
+
+template <typename T>
+int step_timed_t(sipf_sim* sim, int nsteps, float* stage_ms) {
+  const Batch<T> b = single_batch<T>(sim);
+  hipStream_t st = sim->stream;
+  const int* c = sim->counts;
+  hipEvent_t ev[SIPF_NUM_STAGES + 1];
+  for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+  int rc = SIPF_OK;
+  for (int s = 0; s < nsteps && rc == SIPF_OK; ++s) {
+    (void)hipEventRecord(ev[0], st);
+    launch_zfwd<T>(b, c[K_ZFWD], st);
+    (void)hipEventRecord(ev[1], st);
+    launch_yfwd<T>(b, c[K_YFWD], st);
+    (void)hipEventRecord(ev[2], st);
+    launch_xpass<T>(b, c[K_XPASS], st);
+    (void)hipEventRecord(ev[3], st);
+    launch_yinv<T>(b, c[K_YINV], st);
+    (void)hipEventRecord(ev[4], st);
+    launch_zinv<T>(b, c[K_ZINV], st);
+    (void)hipEventRecord(ev[5], st);
+    launch_particles<T>(b, c[K_PART], st);
+    (void)hipEventRecord(ev[6], st);
+    launch_diag_step<T>(b, c[K_DIAG], 1, st);
+    (void)hipEventRecord(ev[7], st);
+    hipError_t e = hipEventSynchronize(ev[7]);
+    if (e == hipSuccess) e = hipGetLastError();
+    if (e != hipSuccess) {
+      rc = fail(SIPF_EHIP, std::string("timed step: ") + hipGetErrorString(e));
+      break;
+    }
+    for (int k = 0; k < SIPF_NUM_STAGES; ++k) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+      stage_ms[k] += ms;
+    }
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sipf_step_timed(sipf_sim* sim, int32_t nsteps, float* stage_ms) {
+  if (!sim || !stage_ms) return fail(SIPF_EINVAL, "sim / stage_ms is NULL");
+  if (nsteps < 0) return fail(SIPF_EINVAL, "nsteps must be >= 0");
+  return sim->prm.precision == SIPF_FP64 ? step_timed_t<double>(sim, nsteps, stage_ms)
+                                         : step_timed_t<float>(sim, nsteps, stage_ms);
+}
+
+
+int sipf_state_bytes(const sipf_params* prm, size_t* bytes) {
+  int rc = validate_params(prm);
+  if (rc) return rc;
+  if (!bytes) return fail(SIPF_EINVAL, "bytes is NULL");
+  *bytes = make_layout(*prm).total;
+  return SIPF_OK;
+}
+
+int sipf_init(const sipf_params* prm, void* d_workspace, size_t bytes, void* hip_stream,
+              const double* X0, const double* a0, const double* v0, const double* m0,
+              const double* w0, sipf_sim** out) {
+  int rc = validate_params(prm);
+  if (rc) return rc;
+  if (!out) return fail(SIPF_EINVAL, "out is NULL");
+  *out = nullptr;
+  const sipf_params& p = *prm;
+  const size_t G = (size_t)p.N * p.N * p.N;
+  if (p.P > 0 && (!X0 || !a0)) return fail(SIPF_EINVAL, "X0 / a0 is NULL");
+  if (!v0 || !m0 || !w0) return fail(SIPF_EINVAL, "v0 / m0 / w0 is NULL");
+  if (p.P > 0 && !finite_array(X0, 3 * (size_t)p.P, false, false))
+    return fail(SIPF_EINVAL, "X0 has non-finite entries");
+  if (p.P > 0 && !finite_array(a0, (size_t)p.P, false, true))
+    return fail(SIPF_EINVAL, "a0 must be finite and > 0");
+  if (!finite_array(v0, G, true, false)) return fail(SIPF_EINVAL, "v0 must be finite, >= 0");
+  // m and w may carry the small negative lobes of the implicit solve (a restart from a
+  // checkpoint); they only have to be finite
+  if (!finite_array(m0, G, false, false)) return fail(SIPF_EINVAL, "m0 must be finite");
+  if (!finite_array(w0, G, false, false)) return fail(SIPF_EINVAL, "w0 must be finite");
+  const Layout L = make_layout(p);
+  if (!d_workspace) return fail(SIPF_EINVAL, "workspace is NULL");
+  if (reinterpret_cast<uintptr_t>(d_workspace) % kAlign)
+    return fail(SIPF_EINVAL, "workspace must be 256-byte aligned");
+  if (bytes < L.total)
+    return fail(SIPF_ENOMEM, "workspace has " + std::to_string(bytes) + " bytes, needs " +
+                                 std::to_string(L.total));
+  sipf_sim* sim = new sipf_sim();
+  sim->prm = p;
+  sim->ws = static_cast<unsigned char*>(d_workspace);
+  sim->bytes = bytes;
+  sim->lay = L;
+  sim->stream = static_cast<hipStream_t>(hip_stream);
+  (void)hipGetDevice(&sim->device);
+  rc = p.precision == SIPF_FP64 ? init_t<double>(sim, X0, a0, v0, m0, w0)
+                                : init_t<float>(sim, X0, a0, v0, m0, w0);
+  if (rc) {
+    std::string msg = g_err;
+    sipf_destroy(sim);
+    g_err = msg;
+    return rc;
+  }
+  *out = sim;
+  return SIPF_OK;
+}
+
+int sipf_step(sipf_sim* sim, int32_t nsteps) {
+  if (!sim) return fail(SIPF_EINVAL, "sim is NULL");
+  if (nsteps < 0) return fail(SIPF_EINVAL, "nsteps must be >= 0");
+  for (int32_t s = 0; s < nsteps; ++s) HIPCHK(hipGraphLaunch(sim->exec, sim->stream));
+  return SIPF_OK;
+}
+
+int sipf_step_batch(sipf_sim* const* sims, int32_t nsims, int32_t nsteps) {
+  if (!sims || nsims <= 0) return fail(SIPF_EINVAL, "empty simulation list");
+  if (nsteps < 0) return fail(SIPF_EINVAL, "nsteps must be >= 0");
+  for (int i = 0; i < nsims; ++i) {
+    if (!sims[i]) return fail(SIPF_EINVAL, "NULL simulation in the list");
+    if (sims[i]->prm.precision != sims[0]->prm.precision)
+      return fail(SIPF_EINVAL, "mixed precision in one batch");
+    if (sims[i]->prm.deposit_order != sims[0]->prm.deposit_order)
+      return fail(SIPF_EINVAL, "mixed deposit order in one batch");
+    if (sims[i]->device != sims[0]->device)
+      return fail(SIPF_EINVAL, "simulations on different devices");
+    for (int j = 0; j < i; ++j)
+      if (sims[j] == sims[i]) return fail(SIPF_EINVAL, "simulation listed twice");
+  }
+  if (nsteps == 0) return SIPF_OK;
+  return sims[0]->prm.precision == SIPF_FP64 ? step_batch_t<double>(sims, nsims, nsteps)
+                                             : step_batch_t<float>(sims, nsims, nsteps);
+}
+
+int sipf_fields(sipf_sim* sim, double* v, double* m, double* w, double* X, double* a,
+                sipf_diag* diag) {
+  if (!sim) return fail(SIPF_EINVAL, "sim is NULL");
+  return sim->prm.precision == SIPF_FP64 ? fields_t<double>(sim, v, m, w, X, a, diag)
+                                         : fields_t<float>(sim, v, m, w, X, a, diag);
+}
+
+int sipf_aux(sipf_sim* sim, double* u_bar, double* grad_v) {
+  if (!sim) return fail(SIPF_EINVAL, "sim is NULL");
+  return sim->prm.precision == SIPF_FP64 ? aux_t<double>(sim, u_bar, grad_v)
+                                         : aux_t<float>(sim, u_bar, grad_v);
+}
+
+void sipf_destroy(sipf_sim* sim) {
+  if (!sim) return;
+  (void)hipStreamSynchronize(sim->stream);
+  if (sim->exec) (void)hipGraphExecDestroy(sim->exec);
+  if (sim->graph) (void)hipGraphDestroy(sim->graph);
+  if (sim->cap) (void)hipStreamDestroy(sim->cap);
+  delete sim;
+}
+
+const char* sipf_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

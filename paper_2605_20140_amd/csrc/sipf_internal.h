@@ -1,0 +1,170 @@
+// Internal declarations of libsipf: device-side simulation descriptor, batch tables, device
+// helpers (complex arithmetic, Philox4x32-10, ordered atomics) and the kernel launchers.
+//
+// Every kernel takes a Batch: an array of simulation descriptors in device memory plus, per
+// kernel kind, the prefix sums of the blocks each simulation needs.  A block finds its
+// simulation from blockIdx.x, so one launch can carry the work of many resident simulations
+// (the served form) and a single simulation is the one-entry case.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sipf.h"
+
+namespace sipf {
+
+constexpr int kThreads = 256;  // threads per block of every kernel (4 wavefronts of 64)
+
+template <typename T>
+struct alignas(2 * sizeof(T)) cplx {
+  T x, y;
+};
+
+template <typename T>
+struct alignas(4 * sizeof(T)) vec4 {
+  T x, y, z, w;
+};
+
+// Kernel kinds that need a block table.
+enum KernelKind {
+  K_ZFWD = 0,   // reaction + forward z transform (real -> half spectrum, transposed)
+  K_YFWD,       // forward y transforms of M*, W*, V
+  K_XPASS,      // x transform, spectral solves / gradient multiplier, inverse x transform
+  K_YINV,       // inverse y transforms (forms the y-derivative spectrum)
+  K_ZINV,       // inverse z transform (half spectrum -> real), forms d3 v, writes fields
+  K_PART,       // gather + Euler-Maruyama push + mass update + deposit
+  K_DIAG,       // reductions for the diagnostics
+  K_DEPOSIT,    // standalone deposit (initialisation)
+  K_COUNT
+};
+
+// Diagnostic accumulator slots (uint64 words; sums stored as float64 bit patterns).
+enum DiagSlot {
+  D_SUM_A = 0, D_SUM_U, D_SUM_M,
+  D_MIN_V, D_MIN_M, D_MIN_W, D_MAX_M, D_MAX_W, D_MIN_A, D_MAX_A, D_MIN_U,
+  D_NAN, D_NEG_M, D_NEG_W,
+  D_COUNT
+};
+
+// Device-visible description of one simulation.  All pointers point into its workspace.
+template <typename T>
+struct SimDev {
+  int N, log2N;       // grid nodes per axis
+  int64_t P;          // particles
+  int rows_per_blk;   // z passes: rows (i1, i2) per block
+  int lines_per_blk;  // y passes: lines per block
+  int cols_per_blk;   // x pass: i2 columns per block
+  int flags;
+  T L, inv_h;         // period, 1/h
+  T inv_h3;           // 1/h^3
+  T two_pi_over_L;
+  T inv_n3;           // 1/N^3 (normalisation of a 3D transform round trip)
+  T inv_n2;           // 1/N^2 (round trip of the y and z transforms only)
+  double dt, D_u, chi, D_m, D_w, alpha, beta, gamma;
+  T noise_amp;        // sqrt(2 D_u dt)
+  T drift;            // chi dt
+  double h3;          // h^3 (mass sums)
+  uint32_t seed_lo, seed_hi, sim_lo, sim_hi;
+  int mult_kind;      // 0 implicit, 1 separable tables (exp / aliased)
+  int use_lowpass;
+  // particles, structure of arrays
+  T *x, *y, *z;
+  double* a;
+  uint32_t* id;
+  // grid (real, N^3 row-major)
+  T *ubar, *v, *m, *w;
+  vec4<T>* g4;        // gather field per node: (d1 v, d2 v, d3 v, w^n)
+  // spectra, half-spectrum layout S[k3][i1][i2], k3 in [0, N/2]
+  cplx<T> *SM, *SW, *SV, *SGx, *SGy;
+  cplx<T>* tw;        // exp(-2 pi i k / N), k < N/2
+  T* mtab;            // separable multiplier tables: [field m | field w | lowpass] x N each
+  uint64_t* step;     // absolute step index n (device-resident, advanced once per step)
+  unsigned long long* diag;  // D_COUNT accumulator words
+};
+
+template <typename T>
+struct Batch {
+  const SimDev<T>* sims;  // device array of nsims descriptors
+  const int* blk;         // device array: K_COUNT tables of (nsims + 1) block offsets
+  int nsims;
+};
+
+template <typename T>
+__device__ __forceinline__ int find_sim(const Batch<T>& b, int kind, int& local_block) {
+  const int* off = b.blk + kind * (b.nsims + 1);
+  int lo = 0, hi = b.nsims;  // invariant: off[lo] <= blockIdx.x < off[hi]
+  const int bid = (int)blockIdx.x;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= bid) lo = mid; else hi = mid;
+  }
+  local_block = bid - off[lo];
+  return lo;
+}
+
+// ---- complex arithmetic -------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ cplx<T> cadd(cplx<T> a, cplx<T> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> csub(cplx<T> a, cplx<T> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> cmul(cplx<T> a, cplx<T> b) {
+  return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ __forceinline__ cplx<T> cconj(cplx<T> a) { return {a.x, -a.y}; }
+template <typename T>
+__device__ __forceinline__ cplx<T> cscale(cplx<T> a, T s) { return {a.x * s, a.y * s}; }
+
+__device__ __forceinline__ int bitrev(int j, int log2n) {
+  return (int)(__brev((unsigned)j) >> (32 - log2n));
+}
+
+// ---- Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11) ----------------------------------------
+// Round: multiply words 0 and 2 by the Philox multipliers into 64-bit products, new counter
+// (hi(c2 M1) ^ c1 ^ k0, lo(c2 M1), hi(c0 M0) ^ c3 ^ k1, lo(c0 M0)); the key advances by the
+// Weyl increments between rounds.
+__device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2,
+                                              uint32_t& c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * (uint64_t)c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * (uint64_t)c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+  }
+}
+
+// ---- ordered 64-bit keys for float64 min / max via integer atomics ------------------------
+__device__ __forceinline__ unsigned long long order_key(double d) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(d);
+  return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+// ---- launchers (defined in fft.hip, particles.hip, diag.hip) ------------------------------
+template <typename T> int elems_per_block();
+template <typename T> void block_counts(const SimDev<T>& d, int counts[K_COUNT]);
+
+template <typename T> void launch_zfwd(const Batch<T>& b, int nblk, hipStream_t s);
+template <typename T> void launch_yfwd(const Batch<T>& b, int nblk, hipStream_t s);
+template <typename T> void launch_xpass(const Batch<T>& b, int nblk, hipStream_t s);
+template <typename T> void launch_yinv(const Batch<T>& b, int nblk, hipStream_t s);
+template <typename T> void launch_zinv(const Batch<T>& b, int nblk, hipStream_t s);
+template <typename T> void launch_particles(const Batch<T>& b, int nblk, hipStream_t s);
+template <typename T> void launch_deposit(const Batch<T>& b, int nblk, hipStream_t s);
+template <typename T> void launch_diag(const Batch<T>& b, int nblk, int nsims, hipStream_t s);
+template <typename T> void launch_diag_step(const Batch<T>& b, int nblk, int nsims, hipStream_t s);
+
+// LDS bytes the FFT kernels need (host side, for launch configuration).
+template <typename T> size_t fft_lds_bytes(int kind);
+
+}  // namespace sipf

@@ -1,0 +1,146 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on identical seeded
+inputs.  Tolerances: float64 form 1e-10 relative (fields: relative L2 and max norms; particle
+positions: max minimum-image distance / L; masses: max relative error); float32 form 1e-4 on
+the same measures (the FP32 bound is checked over the lengths below, where rounding of
+float32 positions and fields accumulates)."""
+import numpy as np
+import pytest
+
+from oracle import pic, spectral
+from oracle import step as S
+from paper_2605_20140_amd import workloads as W
+
+from _parity import compare_state, flags_of, gpu_sim, oracle_params, oracle_state, rel_errors
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+TOL32 = 1e-4
+
+
+def _run_both(ic, nsteps, precision=0, sim_id=0, **kw):
+    sim = gpu_sim(ic, precision=precision, flags=flags_of(**kw), sim_id=sim_id)
+    sim.step(nsteps)
+    out = sim.fields()
+    sim.close()
+    prm = oracle_params(dict(ic["params"], sim_id=sim_id), **kw)
+    ref = S.run(oracle_state(ic), prm, nsteps)
+    return out, ref, prm
+
+
+def test_init_deposit_matches_oracle():
+    ic = W.make_initial_state("blob16")
+    sim = gpu_sim(ic)
+    u, _ = sim.aux()
+    out = sim.fields()
+    ref = pic.deposit(ic["X0"], ic["a0"], 16, 1.0)
+    assert max(rel_errors(u, ref)) < 1e-12
+    d = out["diag"]
+    assert d["mass_grid"] == pytest.approx(1.0, rel=1e-12)
+    assert d["mass_particles"] == pytest.approx(1.0, rel=1e-13)
+    assert d["step"] == 0
+
+
+def test_one_step_gradient_and_deposit():
+    ic = W.make_initial_state("modes64", N=32, P=50000)
+    sim = gpu_sim(ic)
+    sim.step(1)
+    u, g = sim.aux()
+    out = sim.fields()
+    prm = oracle_params(ic["params"])
+    ref, aux = S.step(oracle_state(ic), prm, return_aux=True)
+    for j in range(3):
+        assert max(rel_errors(g[j], aux["grad"][j])) < 1e-11, j
+    u_ref = pic.deposit(ref.X, ref.a, 32, 1.0)
+    assert max(rel_errors(u, u_ref)) < 1e-10
+    compare_state(out, ref, TOL64)
+
+
+def test_blob16_full_length_fp64():
+    """16^3 grid, 4096 particles, 100 steps of dt = 1e-3."""
+    ic = W.make_initial_state("blob16")
+    out, ref, prm = _run_both(ic, 100)
+    errs = compare_state(out, ref, TOL64)
+    d = out["diag"]
+    assert d["step"] == 100 and d["n_nan"] == 0
+    assert d["mass_grid"] == pytest.approx(d["mass_particles"], rel=1e-12)
+    print("blob16 fp64 errors", errs)
+
+
+@pytest.mark.parametrize("N,P,steps", [(4, 300, 5), (8, 257, 7), (32, 4096 + 77, 5),
+                                       (64, 20000, 3)])
+def test_sizes_and_ragged_tails_fp64(N, P, steps):
+    ic = W.make_initial_state("blob16", N=N, P=P)
+    out, ref, _ = _run_both(ic, steps)
+    compare_state(out, ref, TOL64)
+
+
+def test_empty_particle_set_fp64():
+    ic = W.make_initial_state("blob16", P=0)
+    out, ref, _ = _run_both(ic, 10)
+    compare_state(out, ref, TOL64)
+    assert out["diag"]["mass_particles"] == 0.0
+
+
+@pytest.mark.parametrize("kw", [dict(freeze_w=True), dict(freeze_v=True, freeze_m=True),
+                                dict(no_noise=True), dict(linear_mass=True),
+                                dict(implicit_v=True), dict(diffusion="exp")])
+def test_variants_fp64(kw):
+    ic = W.make_initial_state("blob16", P=3000)
+    out, ref, _ = _run_both(ic, 20, **kw)
+    compare_state(out, ref, TOL64)
+
+
+@pytest.mark.parametrize("diffusion", ["exp", "aliased"])
+def test_resolved_heat_kernel_variants_fp64(diffusion):
+    """Exponential and aliased multipliers where the grid resolves the heat kernel
+    (dt D (pi N / L)^2 > 10, the regime of Lemma kernel)."""
+    ic = W.make_initial_state("blob16", P=3000, D_m=5.0, D_w=8.0)
+    out, ref, _ = _run_both(ic, 10, diffusion=diffusion)
+    compare_state(out, ref, TOL64)
+
+
+def test_sim_id_and_seed_select_streams():
+    ic = W.make_initial_state("blob16", P=2000)
+    out, ref, _ = _run_both(ic, 3, sim_id=(7 << 32) + 5)
+    compare_state(out, ref, TOL64)
+
+
+def test_restart_from_checkpoint_matches_uninterrupted():
+    ic = W.make_initial_state("blob16", P=2000)
+    sim = gpu_sim(ic)
+    sim.step(6)
+    mid = sim.fields()
+    sim.step(4)
+    full = sim.fields()
+    sim.close()
+    ic2 = dict(ic, X0=mid["X"], a0=mid["a"], v0=mid["v"], m0=mid["m"], w0=mid["w"])
+    sim2 = gpu_sim(ic2, step0=6)
+    sim2.step(4)
+    res = sim2.fields()
+    sim2.close()
+    for f in ("v", "m", "w"):
+        assert max(rel_errors(res[f], full[f])) < 1e-12
+    assert np.abs(res["X"] - full["X"]).max() < 1e-13
+    assert res["diag"]["step"] == 10
+
+
+def test_blob16_full_length_fp32():
+    ic = W.make_initial_state("blob16")
+    out, ref, _ = _run_both(ic, 100, precision=1)
+    errs = compare_state(out, ref, TOL32)
+    print("blob16 fp32 errors", errs)
+
+
+def test_modes64_fp64_and_fp32_prefix():
+    """64^3 grid, 2^20 particles: the first 5 steps in both forms."""
+    ic = W.make_initial_state("modes64")
+    prm = oracle_params(ic["params"])
+    ref = S.run(oracle_state(ic), prm, 5)
+    for precision, tol in ((0, TOL64), (1, TOL32)):
+        sim = gpu_sim(ic, precision=precision)
+        sim.step(5)
+        out = sim.fields()
+        sim.close()
+        errs = compare_state(out, ref, tol)
+        print("modes64 precision", precision, errs)
