@@ -110,8 +110,9 @@ int sipf_state_bytes(const sipf_params* prm, size_t* bytes);
  * at the nodes).  d_workspace: device pointer, 256-byte aligned, at least
  * sipf_state_bytes() long, owned by the caller and not used by anything else while the
  * simulation exists.  hip_stream: hipStream_t on which all later work of this simulation is
- * ordered (NULL = the default stream).  X0: 3P float64 (SoA), a0: P float64 > 0, v0/m0/w0:
- * N^3 float64 each, finite, >= 0.  Positions are wrapped into [0, L).  In SIPF_FP32
+ * ordered (NULL = the default stream).  X0: 3P float64 (SoA), finite; a0: P float64, finite
+ * and > 0; v0: N^3 float64, finite, >= 0; m0, w0: N^3 float64, finite (a checkpoint may hold
+ * the small negative values the implicit solve allows).  Positions are wrapped into [0, L).  In SIPF_FP32
  * precision, positions and fields are rounded to float32; a0 stays float64.
  * The call is synchronous.  On success *out receives the handle.
  * Errors: SIPF_EINVAL (parameters or inputs), SIPF_ENOMEM (workspace), SIPF_EHIP. */
@@ -150,7 +151,7 @@ int sipf_aux(sipf_sim* sim, double* u_bar, double* grad_v);
  * events between the stages, and add each stage's elapsed milliseconds to stage_ms[k]
  * (caller-owned, SIPF_NUM_STAGES floats; stage order: SIPF_STAGE_*).  Synchronous.
  * Results are identical to sipf_step.  Errors: SIPF_EINVAL, SIPF_EHIP. */
-#define SIPF_NUM_STAGES 7
+#define SIPF_NUM_STAGES 8
 #define SIPF_STAGE_ZFWD 0      /* reaction + forward z transforms            */
 #define SIPF_STAGE_YFWD 1      /* forward y transforms                       */
 #define SIPF_STAGE_XPASS 2     /* x transforms + spectral solves + d1 v      */
@@ -158,6 +159,7 @@ int sipf_aux(sipf_sim* sim, double* u_bar, double* grad_v);
 #define SIPF_STAGE_ZINV 4      /* inverse z transforms + d3 v, field writes  */
 #define SIPF_STAGE_PARTICLES 5 /* gather + push + mass update + deposit      */
 #define SIPF_STAGE_DIAG 6      /* reductions                                 */
+#define SIPF_STAGE_BINNING 7   /* tile binning of the particles (when due)   */
 int sipf_step_timed(sipf_sim* sim, int32_t nsteps, float* stage_ms);
 
 /* Free the host handle and the library's HIP objects (graphs, events); the workspace

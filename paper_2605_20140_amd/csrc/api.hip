@@ -35,7 +35,8 @@ size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 struct Layout {
   size_t total = 0;
   size_t desc, blk, step, diag;
-  size_t x, y, z, a, id;
+  size_t x[2], y[2], z[2], a[2], id[2];
+  size_t tcount, toff, coff, key;
   size_t ubar, v, m, w, g4;
   size_t SM, SW, SV, SGx, SGy;
   size_t tw, mtab;
@@ -94,11 +95,19 @@ Layout make_layout(const sipf_params& p) {
   L.blk = take(sizeof(int) * K_COUNT * 2);
   L.step = take(sizeof(uint64_t));
   L.diag = take(sizeof(unsigned long long) * D_COUNT);
-  L.x = take(P * s);
-  L.y = take(P * s);
-  L.z = take(P * s);
-  L.a = take(P * 8);
-  L.id = take(P * 4);
+  for (int k = 0; k < 2; ++k) {
+    L.x[k] = take(P * s);
+    L.y[k] = take(P * s);
+    L.z[k] = take(P * s);
+    L.a[k] = take(P * 8);
+    L.id[k] = take(P * 4);
+  }
+  const size_t nt1 = N / kTile > 0 ? N / kTile : 1;
+  const size_t ntiles = nt1 * nt1 * nt1;
+  L.tcount = take(ntiles * 4);
+  L.toff = take((ntiles + 1) * 4);
+  L.coff = take((ntiles + 1) * 4);
+  L.key = take(P * 8);
   L.ubar = take(G * s);
   L.v = take(G * s);
   L.m = take(G * s);
@@ -127,8 +136,12 @@ struct sipf_sim {
   hipStream_t cap = nullptr;
   int device = 0;
   int counts[K_COUNT];
-  hipGraph_t graph = nullptr;
+  hipGraph_t graph = nullptr;       // one step
   hipGraphExec_t exec = nullptr;
+  hipGraph_t graph_bin = nullptr;   // binning + one step
+  hipGraphExec_t exec_bin = nullptr;
+  int resort_every = 8;             // steps between binnings
+  int since_bin = 0;                // steps since the last binning
   unsigned char host_desc[std::max(sizeof(SimDev<double>), sizeof(SimDev<float>))];
 };
 
@@ -143,14 +156,17 @@ Batch<T> single_batch(const sipf_sim* s) {
   return b;
 }
 
+// One step; with bin != 0 the particles are first binned into set 1 and the particle pass
+// reads set 1 (and writes set 0).
 template <typename T>
-void enqueue_step(const Batch<T>& b, const int* tot, int nsims, hipStream_t st) {
+void enqueue_step(const Batch<T>& b, const int* tot, int nsims, int bin, hipStream_t st) {
+  if (bin) launch_binning<T>(b, tot, nsims, st);
   launch_zfwd<T>(b, tot[K_ZFWD], st);
   launch_yfwd<T>(b, tot[K_YFWD], st);
   launch_xpass<T>(b, tot[K_XPASS], st);
   launch_yinv<T>(b, tot[K_YINV], st);
   launch_zinv<T>(b, tot[K_ZINV], st);
-  launch_particles<T>(b, tot[K_PART], st);
+  launch_particles<T>(b, tot[K_PART], bin ? 1 : 0, st);
   launch_diag_step<T>(b, tot[K_DIAG], nsims, st);
 }
 
@@ -225,11 +241,20 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   d.sim_hi = (uint32_t)(p.sim_id >> 32);
   d.mult_kind = (p.flags & (SIPF_FLAG_EXP_DIFFUSION | SIPF_FLAG_ALIASED_DIFFUSION)) ? 1 : 0;
   d.use_lowpass = p.H0 > 0 ? 1 : 0;
-  d.x = reinterpret_cast<T*>(ws + L.x);
-  d.y = reinterpret_cast<T*>(ws + L.y);
-  d.z = reinterpret_cast<T*>(ws + L.z);
-  d.a = reinterpret_cast<double*>(ws + L.a);
-  d.id = reinterpret_cast<uint32_t*>(ws + L.id);
+  d.ntile1 = N / kTile > 0 ? N / kTile : 1;
+  d.ntiles = d.ntile1 * d.ntile1 * d.ntile1;
+  d.use_region = N >= 2 * kTile ? 1 : 0;
+  for (int k = 0; k < 2; ++k) {
+    d.xs[k] = reinterpret_cast<T*>(ws + L.x[k]);
+    d.ys[k] = reinterpret_cast<T*>(ws + L.y[k]);
+    d.zs[k] = reinterpret_cast<T*>(ws + L.z[k]);
+    d.as[k] = reinterpret_cast<double*>(ws + L.a[k]);
+    d.ids[k] = reinterpret_cast<uint32_t*>(ws + L.id[k]);
+  }
+  d.tcount = reinterpret_cast<uint32_t*>(ws + L.tcount);
+  d.toff = reinterpret_cast<uint32_t*>(ws + L.toff);
+  d.coff = reinterpret_cast<uint32_t*>(ws + L.coff);
+  d.key = reinterpret_cast<uint32_t*>(ws + L.key);
   d.ubar = reinterpret_cast<T*>(ws + L.ubar);
   d.v = reinterpret_cast<T*>(ws + L.v);
   d.m = reinterpret_cast<T*>(ws + L.m);
@@ -299,11 +324,12 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   HIPCHK(hipMemcpyAsync(ws + L.blk, blk, sizeof(blk), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(ws + L.step, &step0, sizeof(step0), hipMemcpyHostToDevice, st));
   if (P > 0) {
-    HIPCHK(hipMemcpyAsync(d.x, hx.data(), P * sizeof(T), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(d.y, hy.data(), P * sizeof(T), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(d.z, hz.data(), P * sizeof(T), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(d.a, a0, P * sizeof(double), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(d.id, hid.data(), P * sizeof(uint32_t), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d.xs[0], hx.data(), P * sizeof(T), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d.ys[0], hy.data(), P * sizeof(T), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d.zs[0], hz.data(), P * sizeof(T), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d.as[0], a0, P * sizeof(double), hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d.ids[0], hid.data(), P * sizeof(uint32_t), hipMemcpyHostToDevice,
+                          st));
   }
   HIPCHK(hipMemcpyAsync(d.v, hv.data(), G * sizeof(T), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(d.m, hm.data(), G * sizeof(T), hipMemcpyHostToDevice, st));
@@ -312,7 +338,20 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   HIPCHK(hipMemcpyAsync(d.mtab, hmt.data(), 3 * N * sizeof(T), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemsetAsync(d.ubar, 0, G * sizeof(T), st));
   HIPCHK(hipMemsetAsync(d.g4, 0, G * sizeof(vec4<T>), st));
+  HIPCHK(hipMemsetAsync(d.tcount, 0, (size_t)d.ntiles * sizeof(uint32_t), st));
   const Batch<T> b = single_batch<T>(sim);
+  // initial binning: set 0 -> set 1 by tile, then back into set 0
+  launch_binning<T>(b, sim->counts, 1, st);
+  if (P > 0) {
+    HIPCHK(hipMemcpyAsync(d.xs[0], d.xs[1], P * sizeof(T), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(d.ys[0], d.ys[1], P * sizeof(T), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(d.zs[0], d.zs[1], P * sizeof(T), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(d.as[0], d.as[1], P * sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIPCHK(hipMemcpyAsync(d.ids[0], d.ids[1], P * sizeof(uint32_t), hipMemcpyDeviceToDevice,
+                          st));
+  }
+  sim->resort_every = p.resort_every > 0 ? p.resort_every : 8;
+  sim->since_bin = 0;
   launch_deposit<T>(b, sim->counts[K_DEPOSIT], st);
   launch_diag<T>(b, sim->counts[K_DIAG], 1, st);
   HIPCHK(hipGetLastError());
@@ -321,10 +360,15 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   // capture one step as a graph on a private stream; replays go to the caller's stream
   HIPCHK(hipStreamCreateWithFlags(&sim->cap, hipStreamNonBlocking));
   HIPCHK(hipStreamBeginCapture(sim->cap, hipStreamCaptureModeThreadLocal));
-  enqueue_step<T>(b, sim->counts, 1, sim->cap);
+  enqueue_step<T>(b, sim->counts, 1, 0, sim->cap);
   HIPCHK(hipStreamEndCapture(sim->cap, &sim->graph));
   HIPCHK(hipGetLastError());
   HIPCHK(hipGraphInstantiate(&sim->exec, sim->graph, nullptr, nullptr, 0));
+  HIPCHK(hipStreamBeginCapture(sim->cap, hipStreamCaptureModeThreadLocal));
+  enqueue_step<T>(b, sim->counts, 1, 1, sim->cap);
+  HIPCHK(hipStreamEndCapture(sim->cap, &sim->graph_bin));
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipGraphInstantiate(&sim->exec_bin, sim->graph_bin, nullptr, nullptr, 0));
   return SIPF_OK;
 }
 
@@ -376,9 +420,9 @@ int fields_t(sipf_sim* sim, double* v, double* m, double* w, double* X, double* 
   if ((rc = grid(d.w, w))) return rc;
   if ((X || a) && P > 0) {
     std::vector<uint32_t> id(P);
-    HIPCHK(hipMemcpy(id.data(), d.id, P * sizeof(uint32_t), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(id.data(), d.ids[0], P * sizeof(uint32_t), hipMemcpyDeviceToHost));
     if (X) {
-      const T* comp[3] = {d.x, d.y, d.z};
+      const T* comp[3] = {d.xs[0], d.ys[0], d.zs[0]};
       for (int j = 0; j < 3; ++j) {
         HIPCHK(hipMemcpy(buf.data(), comp[j], P * sizeof(T), hipMemcpyDeviceToHost));
         for (int64_t i = 0; i < P; ++i) X[(int64_t)j * P + id[i]] = (double)buf[i];
@@ -386,7 +430,7 @@ int fields_t(sipf_sim* sim, double* v, double* m, double* w, double* X, double* 
     }
     if (a) {
       std::vector<double> ha(P);
-      HIPCHK(hipMemcpy(ha.data(), d.a, P * sizeof(double), hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(ha.data(), d.as[0], P * sizeof(double), hipMemcpyDeviceToHost));
       for (int64_t i = 0; i < P; ++i) a[id[i]] = ha[i];
     }
   }
@@ -499,7 +543,12 @@ int step_batch_t(sipf_sim* const* sims, int nsims, int nsteps) {
   b.sims = reinterpret_cast<const SimDev<T>*>(sl.dev);
   b.blk = reinterpret_cast<const int*>(static_cast<unsigned char*>(sl.dev) + blk_off);
   b.nsims = nsims;
-  for (int s = 0; s < nsteps; ++s) enqueue_step<T>(b, tot.data(), nsims, st);
+  for (int s = 0; s < nsteps; ++s) {
+    int bin = 0;
+    for (int i = 0; i < nsims; ++i) bin |= sims[i]->since_bin >= sims[i]->resort_every;
+    enqueue_step<T>(b, tot.data(), nsims, bin, st);
+    for (int i = 0; i < nsims; ++i) sims[i]->since_bin = bin ? 1 : sims[i]->since_bin + 1;
+  }
   HIPCHK(hipGetLastError());
   HIPCHK(hipEventRecord(sl.done, st));
   return SIPF_OK;
@@ -514,6 +563,9 @@ int step_timed_t(sipf_sim* sim, int nsteps, float* stage_ms) {
   for (auto& e : ev) HIPCHK(hipEventCreate(&e));
   int rc = SIPF_OK;
   for (int s = 0; s < nsteps && rc == SIPF_OK; ++s) {
+    const int bin = sim->since_bin >= sim->resort_every;
+    (void)hipEventRecord(ev[SIPF_NUM_STAGES], st);
+    if (bin) launch_binning<T>(b, c, 1, st);
     (void)hipEventRecord(ev[0], st);
     launch_zfwd<T>(b, c[K_ZFWD], st);
     (void)hipEventRecord(ev[1], st);
@@ -525,21 +577,25 @@ int step_timed_t(sipf_sim* sim, int nsteps, float* stage_ms) {
     (void)hipEventRecord(ev[4], st);
     launch_zinv<T>(b, c[K_ZINV], st);
     (void)hipEventRecord(ev[5], st);
-    launch_particles<T>(b, c[K_PART], st);
+    launch_particles<T>(b, c[K_PART], bin, st);
     (void)hipEventRecord(ev[6], st);
     launch_diag_step<T>(b, c[K_DIAG], 1, st);
     (void)hipEventRecord(ev[7], st);
+    sim->since_bin = bin ? 1 : sim->since_bin + 1;
     hipError_t e = hipEventSynchronize(ev[7]);
     if (e == hipSuccess) e = hipGetLastError();
     if (e != hipSuccess) {
       rc = fail(SIPF_EHIP, std::string("timed step: ") + hipGetErrorString(e));
       break;
     }
-    for (int k = 0; k < SIPF_NUM_STAGES; ++k) {
+    for (int k = 0; k < SIPF_STAGE_DIAG + 1; ++k) {
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
       stage_ms[k] += ms;
     }
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, ev[SIPF_NUM_STAGES], ev[0]);
+    stage_ms[SIPF_STAGE_BINNING] += ms;
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
   return rc;
@@ -614,7 +670,15 @@ int sipf_init(const sipf_params* prm, void* d_workspace, size_t bytes, void* hip
 int sipf_step(sipf_sim* sim, int32_t nsteps) {
   if (!sim) return fail(SIPF_EINVAL, "sim is NULL");
   if (nsteps < 0) return fail(SIPF_EINVAL, "nsteps must be >= 0");
-  for (int32_t s = 0; s < nsteps; ++s) HIPCHK(hipGraphLaunch(sim->exec, sim->stream));
+  for (int32_t s = 0; s < nsteps; ++s) {
+    if (sim->since_bin >= sim->resort_every) {
+      HIPCHK(hipGraphLaunch(sim->exec_bin, sim->stream));
+      sim->since_bin = 1;
+    } else {
+      HIPCHK(hipGraphLaunch(sim->exec, sim->stream));
+      sim->since_bin += 1;
+    }
+  }
   return SIPF_OK;
 }
 
@@ -655,6 +719,8 @@ void sipf_destroy(sipf_sim* sim) {
   (void)hipStreamSynchronize(sim->stream);
   if (sim->exec) (void)hipGraphExecDestroy(sim->exec);
   if (sim->graph) (void)hipGraphDestroy(sim->graph);
+  if (sim->exec_bin) (void)hipGraphExecDestroy(sim->exec_bin);
+  if (sim->graph_bin) (void)hipGraphDestroy(sim->graph_bin);
   if (sim->cap) (void)hipStreamDestroy(sim->cap);
   delete sim;
 }

@@ -64,9 +64,9 @@ __global__ void __launch_bounds__(kThreads) k_diag(Batch<T> bt) {
   Acc a = {0, 0, 0, inf, inf, inf, -inf, -inf, inf, -inf, inf, 0ull, 0ull, 0ull};
   const int64_t stride = (int64_t)nb * kThreads;
   for (int64_t i = (int64_t)lb * kThreads + threadIdx.x; i < d.P; i += stride) {
-    const double am = d.a[i];
-    const bool bad = !isfinite(am) || !isfinite((double)d.x[i]) || !isfinite((double)d.y[i]) ||
-                     !isfinite((double)d.z[i]);
+    const double am = d.as[0][i];
+    const bool bad = !isfinite(am) || !isfinite((double)d.xs[0][i]) ||
+                     !isfinite((double)d.ys[0][i]) || !isfinite((double)d.zs[0][i]);
     if (bad) {
       a.nan += 1;
     } else {

@@ -46,8 +46,11 @@ void block_counts(const SimDev<T>& d, int c[K_COUNT]) {
   c[K_YINV] = (int)(3 * ny + ny2);
   c[K_ZINV] = c[K_ZFWD];
   const int64_t pb = (d.P + kThreads - 1) / kThreads;
-  c[K_PART] = (int)pb;
+  c[K_PART] = (int)((d.P + kChunk - 1) / kChunk + d.ntiles);  // bound on (tile, chunk) items
   c[K_DEPOSIT] = (int)pb;
+  c[K_SCOUNT] = (int)pb;
+  c[K_SSCAN] = 1;
+  c[K_SSCATTER] = (int)pb;
   int64_t work = d.P > N * N * N ? d.P : N * N * N;
   int64_t db = (work + kThreads * 8 - 1) / (kThreads * 8);
   if (db < 1) db = 1;

@@ -1,21 +1,30 @@
 // Particle half of the SIPF-W step on gfx950: grid-to-particle gather (Alg. g2p), Philox
 // Wiener increments, Euler-Maruyama push and mass update (eq. u_hat_update, eq. SDE), and the
-// particle-to-grid deposit (Alg. p2g) of the new state, fused in one pass over the particles.
+// particle-to-grid deposit (Alg. p2g) of the new state, fused in one pass over the particles;
+// plus the tile binning that makes that pass local.
 //
 // Particles are structure of arrays: x, y, z in the working precision T, masses a in
 // float64, and a 32-bit particle index id that keys the noise stream, so results do not
-// depend on the storage order.
+// depend on the storage order.  Set 0 holds the state; binning scatters set 0 into set 1 by
+// tile, and the particle pass that follows reads set 1 and writes its results back into
+// set 0, which stays tile-ordered until the next binning.
 //
 // Trilinear stencil: s = x / h, i = floor(s), f = s - i; node weights (1 - f, f) per axis
 // (K_h = h^3 R_h); R_h = K_h / h^3 for the deposit.  Node indices wrap modulo N.
+//
+// Particle pass: one block per (tile, chunk of <= kChunk particles).  The block stages the
+// gather array of its tile's nodes plus a kMargin-cell margin in LDS, gathers from LDS,
+// deposits the new state into an LDS accumulator, and flushes every non-zero accumulator
+// node to the global density with one atomic.  A particle whose stencil leaves the region
+// (it drifted more than kMargin cells since the last binning) uses global memory instead.
 #include "sipf_internal.h"
 
 namespace sipf {
 
 template <typename T>
 struct Stencil {
-  int i0[3], i1[3];
-  T f[3];
+  int c[3];  // cell index (lower node), in [0, N)
+  T f[3];    // fractional offsets
 };
 
 template <typename T>
@@ -26,32 +35,13 @@ __device__ __forceinline__ Stencil<T> make_stencil(T x, T y, T z, T inv_h, int N
   for (int j = 0; j < 3; ++j) {
     const T fl = floor(s[j]);
     st.f[j] = s[j] - fl;
-    const int i = (int)fl;
-    st.i0[j] = i & (N - 1);
-    st.i1[j] = (i + 1) & (N - 1);
+    st.c[j] = ((int)fl) & (N - 1);
   }
   return st;
 }
 
 __device__ __forceinline__ int64_t node(int a, int b, int c, int N) {
   return ((int64_t)a * N + b) * N + c;
-}
-
-template <typename T>
-__device__ __forceinline__ void deposit_stencil(T* ubar, const Stencil<T>& st, T q, int N) {
-  const T wx[2] = {(T)1 - st.f[0], st.f[0]};
-  const T wy[2] = {(T)1 - st.f[1], st.f[1]};
-  const T wz[2] = {(T)1 - st.f[2], st.f[2]};
-  const int ix[2] = {st.i0[0], st.i1[0]};
-  const int iy[2] = {st.i0[1], st.i1[1]};
-  const int iz[2] = {st.i0[2], st.i1[2]};
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int c = 0; c < 2; ++c)
-        unsafeAtomicAdd(&ubar[node(ix[a], iy[b], iz[c], N)], q * wx[a] * wy[b] * wz[c]);
 }
 
 // Box-Muller normals from one Philox block.  float64: exact uniforms (r + 1/2) 2^-32 and
@@ -93,72 +83,205 @@ __device__ __forceinline__ T wrap_periodic(T x, T L) {
   return x;
 }
 
-// One thread per particle.
+// Region of one tile: node (ox + r1, oy + r2, oz + r3), r in [0, kRegion)^3, wrapped.
+struct Region {
+  int o[3];
+};
+
+// Local lower-node coordinates of a stencil inside the region, or false if any of its 8
+// nodes falls outside.
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_particles(Batch<T> bt) {
+__device__ __forceinline__ bool in_region(const Stencil<T>& st, const Region& rg, int N,
+                                          int l[3]) {
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    l[j] = (st.c[j] - rg.o[j]) & (N - 1);
+    ok = ok && (l[j] <= kRegion - 2);
+  }
+  return ok;
+}
+
+__device__ __forceinline__ int rindex(int a, int b, int c) {
+  return (a * kRegion + b) * kRegion + c;
+}
+
+template <typename T>
+__device__ __forceinline__ void weights(const Stencil<T>& st, T wx[2], T wy[2], T wz[2]) {
+  wx[0] = (T)1 - st.f[0];
+  wx[1] = st.f[0];
+  wy[0] = (T)1 - st.f[1];
+  wy[1] = st.f[1];
+  wz[0] = (T)1 - st.f[2];
+  wz[1] = st.f[2];
+}
+
+template <typename T>
+__device__ __forceinline__ void deposit_global(T* ubar, const Stencil<T>& st, T q, int N) {
+  T wx[2], wy[2], wz[2];
+  weights(st, wx, wy, wz);
+  const int ix[2] = {st.c[0], (st.c[0] + 1) & (N - 1)};
+  const int iy[2] = {st.c[1], (st.c[1] + 1) & (N - 1)};
+  const int iz[2] = {st.c[2], (st.c[2] + 1) & (N - 1)};
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+        unsafeAtomicAdd(&ubar[node(ix[a], iy[b], iz[c], N)], q * wx[a] * wy[b] * wz[c]);
+}
+
+// ---- particle pass ----------------------------------------------------------------------
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_particles(Batch<T> bt, int src_set) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
   const int s = find_sim(bt, K_PART, lb);
   const SimDev<T>& d = bt.sims[s];
-  const int64_t i = (int64_t)lb * kThreads + threadIdx.x;
-  if (i >= d.P) return;
+  const int nchunks = (int)d.coff[d.ntiles];
+  if (lb >= nchunks) return;
+  // tile of this chunk: the last tile whose first chunk is <= lb
+  int lo = 0, hi = d.ntiles;
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if ((int)d.coff[mid] <= lb) lo = mid; else hi = mid;
+  }
+  const int tile = lo;
+  const uint32_t start = d.toff[tile] + (uint32_t)(lb - (int)d.coff[tile]) * kChunk;
+  const uint32_t tend = d.toff[tile + 1];
+  const uint32_t end = start + kChunk < tend ? start + kChunk : tend;
   const int N = d.N;
-  const uint32_t n = (uint32_t)(*d.step);
-  const T x = d.x[i], y = d.y[i], z = d.z[i];
-  const double a = d.a[i];
-  const uint32_t id = d.id[i];
+  const int nt = d.ntile1;
+  Region rg;
+  rg.o[0] = (tile / (nt * nt)) * kTile - kMargin;
+  rg.o[1] = ((tile / nt) % nt) * kTile - kMargin;
+  rg.o[2] = (tile % nt) * kTile - kMargin;
+  const bool use_region = d.use_region;
 
-  // gather (d1 v, d2 v, d3 v, w) at the old position
-  const Stencil<T> st = make_stencil(x, y, z, d.inv_h, N);
-  const T wx[2] = {(T)1 - st.f[0], st.f[0]};
-  const T wy[2] = {(T)1 - st.f[1], st.f[1]};
-  const T wz[2] = {(T)1 - st.f[2], st.f[2]};
-  const int ix[2] = {st.i0[0], st.i1[0]};
-  const int iy[2] = {st.i0[1], st.i1[1]};
-  const int iz[2] = {st.i0[2], st.i1[2]};
-  T g0 = 0, g1 = 0, g2 = 0, gw = 0;
-#pragma unroll
-  for (int aa = 0; aa < 2; ++aa)
-#pragma unroll
-    for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-      for (int cc = 0; cc < 2; ++cc) {
-        const vec4<T> q = d.g4[node(ix[aa], iy[bb], iz[cc], N)];
-        const T wgt = wx[aa] * wy[bb] * wz[cc];
-        g0 += wgt * q.x;
-        g1 += wgt * q.y;
-        g2 += wgt * q.z;
-        gw += wgt * q.w;
-      }
-
-  // Wiener increment
-  T zn[3] = {0, 0, 0};
-  if (!(d.flags & SIPF_FLAG_NO_NOISE)) {
-    uint32_t c0 = id, c1 = n, c2 = d.sim_lo, c3 = d.sim_hi;
-    philox4x32_10(c0, c1, c2, c3, d.seed_lo, d.seed_hi);
-    box_muller(c0, c1, c2, c3, zn);
+  vec4<T>* gl = reinterpret_cast<vec4<T>*>(smem_raw);  // gather array of the region
+  T* acc = reinterpret_cast<T*>(gl + kRegion3);        // deposit accumulator
+  if (use_region) {
+    for (int e = threadIdx.x; e < kRegion3; e += kThreads) {
+      const int rz = e % kRegion, ry = (e / kRegion) % kRegion, rx = e / (kRegion * kRegion);
+      gl[e] = d.g4[node((rg.o[0] + rx) & (N - 1), (rg.o[1] + ry) & (N - 1),
+                        (rg.o[2] + rz) & (N - 1), N)];
+      acc[e] = (T)0;
+    }
+    __syncthreads();
   }
 
-  // push and mass update
-  const T xn = wrap_periodic(x + d.drift * g0 + d.noise_amp * zn[0], d.L);
-  const T yn = wrap_periodic(y + d.drift * g1 + d.noise_amp * zn[1], d.L);
-  const T zz = wrap_periodic(z + d.drift * g2 + d.noise_amp * zn[2], d.L);
-  const T rho = (T)2 * gw / ((T)1 + gw);
-  double an;
-  if (d.flags & SIPF_FLAG_LINEAR_MASS)
-    an = a * (1.0 + d.dt * (double)rho - d.dt);
-  else
-    an = a * exp(d.dt * ((double)rho - 1.0));
-  d.x[i] = xn;
-  d.y[i] = yn;
-  d.z[i] = zz;
-  d.a[i] = an;
+  const uint32_t n = (uint32_t)(*d.step);
+  const T* xi = d.xs[src_set];
+  const T* yi = d.ys[src_set];
+  const T* zi = d.zs[src_set];
+  const double* ai = d.as[src_set];
+  const uint32_t* idi = d.ids[src_set];
+  T* xo = d.xs[0];
+  T* yo = d.ys[0];
+  T* zo = d.zs[0];
+  double* ao = d.as[0];
+  const bool linear_mass = d.flags & SIPF_FLAG_LINEAR_MASS;
+  const bool noise = !(d.flags & SIPF_FLAG_NO_NOISE);
 
-  // deposit of the new state: ubar^{n+1}
-  const Stencil<T> sn = make_stencil(xn, yn, zz, d.inv_h, N);
-  deposit_stencil(d.ubar, sn, (T)an * d.inv_h3, N);
+  for (uint32_t i = start + threadIdx.x; i < end; i += kThreads) {
+    const T x = xi[i], y = yi[i], z = zi[i];
+    const double a = ai[i];
+    const uint32_t id = idi[i];
+
+    // gather (d1 v, d2 v, d3 v, w) at the old position
+    const Stencil<T> st = make_stencil(x, y, z, d.inv_h, N);
+    T wx[2], wy[2], wz[2];
+    weights(st, wx, wy, wz);
+    T g0 = 0, g1 = 0, g2 = 0, gw = 0;
+    int l[3];
+    if (use_region && in_region(st, rg, N, l)) {
+#pragma unroll
+      for (int aa = 0; aa < 2; ++aa)
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+          for (int cc = 0; cc < 2; ++cc) {
+            const vec4<T> q = gl[rindex(l[0] + aa, l[1] + bb, l[2] + cc)];
+            const T wgt = wx[aa] * wy[bb] * wz[cc];
+            g0 += wgt * q.x;
+            g1 += wgt * q.y;
+            g2 += wgt * q.z;
+            gw += wgt * q.w;
+          }
+    } else {
+      const int ix[2] = {st.c[0], (st.c[0] + 1) & (N - 1)};
+      const int iy[2] = {st.c[1], (st.c[1] + 1) & (N - 1)};
+      const int iz[2] = {st.c[2], (st.c[2] + 1) & (N - 1)};
+#pragma unroll
+      for (int aa = 0; aa < 2; ++aa)
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+          for (int cc = 0; cc < 2; ++cc) {
+            const vec4<T> q = d.g4[node(ix[aa], iy[bb], iz[cc], N)];
+            const T wgt = wx[aa] * wy[bb] * wz[cc];
+            g0 += wgt * q.x;
+            g1 += wgt * q.y;
+            g2 += wgt * q.z;
+            gw += wgt * q.w;
+          }
+    }
+
+    // Wiener increment: Philox counter (particle index, step, simulation)
+    T zn[3] = {0, 0, 0};
+    if (noise) {
+      uint32_t c0 = id, c1 = n, c2 = d.sim_lo, c3 = d.sim_hi;
+      philox4x32_10(c0, c1, c2, c3, d.seed_lo, d.seed_hi);
+      box_muller(c0, c1, c2, c3, zn);
+    }
+
+    // push and mass update
+    const T xn = wrap_periodic(x + d.drift * g0 + d.noise_amp * zn[0], d.L);
+    const T yn = wrap_periodic(y + d.drift * g1 + d.noise_amp * zn[1], d.L);
+    const T zz = wrap_periodic(z + d.drift * g2 + d.noise_amp * zn[2], d.L);
+    const T rho = (T)2 * gw / ((T)1 + gw);
+    const double an = linear_mass ? a * (1.0 + d.dt * (double)rho - d.dt)
+                                  : a * exp(d.dt * ((double)rho - 1.0));
+    xo[i] = xn;
+    yo[i] = yn;
+    zo[i] = zz;
+    ao[i] = an;
+    if (src_set) d.ids[0][i] = id;
+
+    // deposit of the new state: ubar^{n+1}
+    const Stencil<T> sn = make_stencil(xn, yn, zz, d.inv_h, N);
+    const T q = (T)an * d.inv_h3;
+    if (use_region && in_region(sn, rg, N, l)) {
+      weights(sn, wx, wy, wz);
+#pragma unroll
+      for (int aa = 0; aa < 2; ++aa)
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+          for (int cc = 0; cc < 2; ++cc)
+            atomicAdd(&acc[rindex(l[0] + aa, l[1] + bb, l[2] + cc)],
+                      q * wx[aa] * wy[bb] * wz[cc]);
+    } else {
+      deposit_global(d.ubar, sn, q, N);
+    }
+  }
+
+  if (use_region) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < kRegion3; e += kThreads) {
+      const T v = acc[e];
+      if (v != (T)0) {
+        const int rz = e % kRegion, ry = (e / kRegion) % kRegion, rx = e / (kRegion * kRegion);
+        unsafeAtomicAdd(&d.ubar[node((rg.o[0] + rx) & (N - 1), (rg.o[1] + ry) & (N - 1),
+                                     (rg.o[2] + rz) & (N - 1), N)],
+                        v);
+      }
+    }
+  }
 }
 
-// Standalone deposit of the current particles (initialisation).
+// ---- standalone deposit of set 0 (initialisation) -----------------------------------------
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_deposit(Batch<T> bt) {
   int lb;
@@ -166,23 +289,140 @@ __global__ void __launch_bounds__(kThreads) k_deposit(Batch<T> bt) {
   const SimDev<T>& d = bt.sims[s];
   const int64_t i = (int64_t)lb * kThreads + threadIdx.x;
   if (i >= d.P) return;
-  const Stencil<T> st = make_stencil(d.x[i], d.y[i], d.z[i], d.inv_h, d.N);
-  deposit_stencil(d.ubar, st, (T)d.a[i] * d.inv_h3, d.N);
+  const Stencil<T> st = make_stencil(d.xs[0][i], d.ys[0][i], d.zs[0][i], d.inv_h, d.N);
+  deposit_global(d.ubar, st, (T)d.as[0][i] * d.inv_h3, d.N);
+}
+
+// ---- binning ----------------------------------------------------------------------------
+// Tile of every particle of set 0 and its rank among the particles of that tile; ranks come
+// from one atomic per distinct tile per wavefront.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_bin_count(Batch<T> bt) {
+  int lb;
+  const int s = find_sim(bt, K_SCOUNT, lb);
+  const SimDev<T>& d = bt.sims[s];
+  const int64_t i = (int64_t)lb * kThreads + threadIdx.x;
+  const bool valid = i < d.P;
+  uint32_t tile = 0;
+  if (valid) {
+    const int N = d.N, nt = d.ntile1;
+    const Stencil<T> st = make_stencil(d.xs[0][i], d.ys[0][i], d.zs[0][i], d.inv_h, N);
+    const int tx = st.c[0] / kTile, ty = st.c[1] / kTile, tz = st.c[2] / kTile;
+    tile = (uint32_t)(((tx < nt ? tx : nt - 1) * nt + (ty < nt ? ty : nt - 1)) * nt +
+                      (tz < nt ? tz : nt - 1));
+  }
+  const int lane = threadIdx.x & 63;
+  unsigned long long pending = __ballot(valid);
+  uint32_t rank = 0;
+  while (pending) {
+    const int leader = __ffsll((long long)pending) - 1;
+    const uint32_t lt = __shfl(tile, leader, 64);
+    const unsigned long long same = __ballot(valid && tile == lt) & pending;
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(&d.tcount[lt], (uint32_t)__popcll(same));
+    base = __shfl(base, leader, 64);
+    if ((same >> lane) & 1ull) rank = base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+    pending &= ~same;
+  }
+  if (valid) {
+    d.key[2 * i] = tile;
+    d.key[2 * i + 1] = rank;
+  }
+}
+
+// Exclusive scans of the tile counts (tile offsets) and of ceil(count / kChunk) (chunk
+// offsets); clears the counts for the next binning.  One block of kThreads per simulation.
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_bin_scan(Batch<T> bt) {
+  int lb;
+  const int s = find_sim(bt, K_SSCAN, lb);
+  const SimDev<T>& d = bt.sims[s];
+  const int nt = d.ntiles;
+  const int per = (nt + kThreads - 1) / kThreads;
+  const int b0 = threadIdx.x * per;
+  const int b1 = b0 + per < nt ? b0 + per : nt;
+  uint32_t sp = 0, sc = 0;
+  for (int t = b0; t < b1; ++t) {
+    const uint32_t c = d.tcount[t];
+    sp += c;
+    sc += (c + kChunk - 1) / kChunk;
+  }
+  __shared__ uint32_t pp[kThreads], pc[kThreads];
+  pp[threadIdx.x] = sp;
+  pc[threadIdx.x] = sc;
+  __syncthreads();
+  // inclusive Hillis-Steele scan of the per-thread sums
+  for (int off = 1; off < kThreads; off <<= 1) {
+    uint32_t ap = 0, ac = 0;
+    if ((int)threadIdx.x >= off) {
+      ap = pp[threadIdx.x - off];
+      ac = pc[threadIdx.x - off];
+    }
+    __syncthreads();
+    pp[threadIdx.x] += ap;
+    pc[threadIdx.x] += ac;
+    __syncthreads();
+  }
+  uint32_t rp = threadIdx.x ? pp[threadIdx.x - 1] : 0;
+  uint32_t rc = threadIdx.x ? pc[threadIdx.x - 1] : 0;
+  for (int t = b0; t < b1; ++t) {
+    const uint32_t c = d.tcount[t];
+    d.toff[t] = rp;
+    d.coff[t] = rc;
+    rp += c;
+    rc += (c + kChunk - 1) / kChunk;
+    d.tcount[t] = 0;
+  }
+  if (threadIdx.x == kThreads - 1) {
+    d.toff[nt] = pp[kThreads - 1];
+    d.coff[nt] = pc[kThreads - 1];
+  }
 }
 
 template <typename T>
-void launch_particles(const Batch<T>& b, int nblk, hipStream_t st) {
+__global__ void __launch_bounds__(kThreads) k_bin_scatter(Batch<T> bt) {
+  int lb;
+  const int s = find_sim(bt, K_SSCATTER, lb);
+  const SimDev<T>& d = bt.sims[s];
+  const int64_t i = (int64_t)lb * kThreads + threadIdx.x;
+  if (i >= d.P) return;
+  const uint32_t dst = d.toff[d.key[2 * i]] + d.key[2 * i + 1];
+  d.xs[1][dst] = d.xs[0][i];
+  d.ys[1][dst] = d.ys[0][i];
+  d.zs[1][dst] = d.zs[0][i];
+  d.as[1][dst] = d.as[0][i];
+  d.ids[1][dst] = d.ids[0][i];
+}
+
+template <typename T>
+size_t particle_lds_bytes() {
+  return kRegion3 * (sizeof(vec4<T>) + sizeof(T));
+}
+
+template <typename T>
+void launch_particles(const Batch<T>& b, int nblk, int src_set, hipStream_t st) {
   if (nblk <= 0) return;
-  hipLaunchKernelGGL(k_particles<T>, dim3(nblk), dim3(kThreads), 0, st, b);
+  hipLaunchKernelGGL(k_particles<T>, dim3(nblk), dim3(kThreads), particle_lds_bytes<T>(), st, b,
+                     src_set);
 }
 template <typename T>
 void launch_deposit(const Batch<T>& b, int nblk, hipStream_t st) {
   if (nblk <= 0) return;
   hipLaunchKernelGGL(k_deposit<T>, dim3(nblk), dim3(kThreads), 0, st, b);
 }
-template void launch_particles<double>(const Batch<double>&, int, hipStream_t);
-template void launch_particles<float>(const Batch<float>&, int, hipStream_t);
+template <typename T>
+void launch_binning(const Batch<T>& b, const int* tot, int nsims, hipStream_t st) {
+  if (tot[K_SCOUNT] > 0)
+    hipLaunchKernelGGL(k_bin_count<T>, dim3(tot[K_SCOUNT]), dim3(kThreads), 0, st, b);
+  hipLaunchKernelGGL(k_bin_scan<T>, dim3(tot[K_SSCAN]), dim3(kThreads), 0, st, b);
+  if (tot[K_SSCATTER] > 0)
+    hipLaunchKernelGGL(k_bin_scatter<T>, dim3(tot[K_SSCATTER]), dim3(kThreads), 0, st, b);
+}
+template void launch_particles<double>(const Batch<double>&, int, int, hipStream_t);
+template void launch_particles<float>(const Batch<float>&, int, int, hipStream_t);
 template void launch_deposit<double>(const Batch<double>&, int, hipStream_t);
 template void launch_deposit<float>(const Batch<float>&, int, hipStream_t);
+template void launch_binning<double>(const Batch<double>&, const int*, int, hipStream_t);
+template void launch_binning<float>(const Batch<float>&, const int*, int, hipStream_t);
 
 }  // namespace sipf

@@ -16,6 +16,15 @@ namespace sipf {
 
 constexpr int kThreads = 256;  // threads per block of every kernel (4 wavefronts of 64)
 
+// Particle binning: cubic tiles of kTile^3 cells; a particle kernel block handles up to
+// kChunk particles of one tile and keeps the tile's nodes plus a kMargin-cell drift margin
+// (kRegion nodes per axis) in LDS.
+constexpr int kTile = 8;
+constexpr int kMargin = 1;
+constexpr int kRegion = kTile + 2 * kMargin + 1;
+constexpr int kRegion3 = kRegion * kRegion * kRegion;
+constexpr int kChunk = 2048;
+
 template <typename T>
 struct alignas(2 * sizeof(T)) cplx {
   T x, y;
@@ -36,6 +45,9 @@ enum KernelKind {
   K_PART,       // gather + Euler-Maruyama push + mass update + deposit
   K_DIAG,       // reductions for the diagnostics
   K_DEPOSIT,    // standalone deposit (initialisation)
+  K_SCOUNT,     // binning: tile of every particle and its rank within the tile
+  K_SSCAN,      // binning: tile and chunk offsets (one block per simulation)
+  K_SSCATTER,   // binning: scatter particles into the sorted set
   K_COUNT
 };
 
@@ -68,10 +80,18 @@ struct SimDev {
   uint32_t seed_lo, seed_hi, sim_lo, sim_hi;
   int mult_kind;      // 0 implicit, 1 separable tables (exp / aliased)
   int use_lowpass;
-  // particles, structure of arrays
-  T *x, *y, *z;
-  double* a;
-  uint32_t* id;
+  int ntile1;         // tiles per axis, max(1, N / kTile)
+  int ntiles;         // ntile1^3
+  int use_region;     // LDS tile regions (N >= 2 kTile, so a region never aliases itself)
+  // particles, structure of arrays; set 0 is the state, set 1 receives the binned copy
+  T *xs[2], *ys[2], *zs[2];
+  double* as[2];
+  uint32_t* ids[2];   // particle index: keys the noise stream, restores the input order
+  // binning
+  uint32_t* tcount;   // ntiles: particles per tile (zero between binnings)
+  uint32_t* toff;     // ntiles + 1: first sorted index of each tile
+  uint32_t* coff;     // ntiles + 1: first chunk of each tile
+  uint32_t* key;      // 2P: (tile, rank within tile) per particle
   // grid (real, N^3 row-major)
   T *ubar, *v, *m, *w;
   vec4<T>* g4;        // gather field per node: (d1 v, d2 v, d3 v, w^n)
@@ -159,7 +179,8 @@ template <typename T> void launch_yfwd(const Batch<T>& b, int nblk, hipStream_t 
 template <typename T> void launch_xpass(const Batch<T>& b, int nblk, hipStream_t s);
 template <typename T> void launch_yinv(const Batch<T>& b, int nblk, hipStream_t s);
 template <typename T> void launch_zinv(const Batch<T>& b, int nblk, hipStream_t s);
-template <typename T> void launch_particles(const Batch<T>& b, int nblk, hipStream_t s);
+template <typename T> void launch_particles(const Batch<T>& b, int nblk, int src_set, hipStream_t s);
+template <typename T> void launch_binning(const Batch<T>& b, const int* tot, int nsims, hipStream_t s);
 template <typename T> void launch_deposit(const Batch<T>& b, int nblk, hipStream_t s);
 template <typename T> void launch_diag(const Batch<T>& b, int nblk, int nsims, hipStream_t s);
 template <typename T> void launch_diag_step(const Batch<T>& b, int nblk, int nsims, hipStream_t s);
