@@ -121,7 +121,8 @@ int sipf_init(const sipf_params* prm, void* d_workspace, size_t bytes, void* hip
               const double* w0, sipf_sim** out);
 
 /* Enqueue nsteps >= 0 steps (Alg. sipf-pic loop body) on the simulation's stream; returns
- * without waiting.  Each step also recomputes the diagnostics.  Errors: SIPF_EINVAL,
+ * without waiting.  Each step also recomputes the diagnostics (the kernels that write a
+ * value reduce it as they go).  Errors: SIPF_EINVAL,
  * SIPF_EHIP. */
 int sipf_step(sipf_sim* sim, int32_t nsteps);
 
@@ -158,7 +159,7 @@ int sipf_aux(sipf_sim* sim, double* u_bar, double* grad_v);
 #define SIPF_STAGE_YINV 3      /* inverse y transforms + d2 v                */
 #define SIPF_STAGE_ZINV 4      /* inverse z transforms + d3 v, field writes  */
 #define SIPF_STAGE_PARTICLES 5 /* gather + push + mass update + deposit      */
-#define SIPF_STAGE_DIAG 6      /* reductions                                 */
+#define SIPF_STAGE_FINALIZE 6  /* diagnostics buffer swap, step index        */
 #define SIPF_STAGE_BINNING 7   /* tile binning of the particles (when due)   */
 int sipf_step_timed(sipf_sim* sim, int32_t nsteps, float* stage_ms);
 

@@ -36,7 +36,7 @@ struct Layout {
   size_t total = 0;
   size_t desc, blk, step, diag;
   size_t x[2], y[2], z[2], a[2], id[2];
-  size_t tcount, toff, coff, key;
+  size_t tcount, toff, coff, ctile, key;
   size_t ubar, v, m, w, g4;
   size_t SM, SW, SV, SGx, SGy;
   size_t tw, mtab;
@@ -94,7 +94,7 @@ Layout make_layout(const sipf_params& p) {
   L.desc = take(std::max(sizeof(SimDev<double>), sizeof(SimDev<float>)));
   L.blk = take(sizeof(int) * K_COUNT * 2);
   L.step = take(sizeof(uint64_t));
-  L.diag = take(sizeof(unsigned long long) * D_COUNT);
+  L.diag = take(sizeof(unsigned long long) * kDiagWords);
   for (int k = 0; k < 2; ++k) {
     L.x[k] = take(P * s);
     L.y[k] = take(P * s);
@@ -107,6 +107,7 @@ Layout make_layout(const sipf_params& p) {
   L.tcount = take(ntiles * 4);
   L.toff = take((ntiles + 1) * 4);
   L.coff = take((ntiles + 1) * 4);
+  L.ctile = take(((P + kChunk - 1) / kChunk + ntiles) * 4);
   L.key = take(P * 8);
   L.ubar = take(G * s);
   L.v = take(G * s);
@@ -166,8 +167,8 @@ void enqueue_step(const Batch<T>& b, const int* tot, int nsims, int bin, hipStre
   launch_xpass<T>(b, tot[K_XPASS], st);
   launch_yinv<T>(b, tot[K_YINV], st);
   launch_zinv<T>(b, tot[K_ZINV], st);
-  launch_particles<T>(b, tot[K_PART], bin ? 1 : 0, st);
-  launch_diag_step<T>(b, tot[K_DIAG], nsims, st);
+  launch_particles<T>(b, tot[K_PART], bin ? 1 : 0, 0, st);
+  launch_finalize<T>(b, nsims, st);
 }
 
 // float64 multiplier tables of the separable diffusion forms and of the low-pass filter,
@@ -254,6 +255,8 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   d.tcount = reinterpret_cast<uint32_t*>(ws + L.tcount);
   d.toff = reinterpret_cast<uint32_t*>(ws + L.toff);
   d.coff = reinterpret_cast<uint32_t*>(ws + L.coff);
+  d.ctile = reinterpret_cast<uint32_t*>(ws + L.ctile);
+  d.max_chunks = (int)((P + kChunk - 1) / kChunk + d.ntiles);
   d.key = reinterpret_cast<uint32_t*>(ws + L.key);
   d.ubar = reinterpret_cast<T*>(ws + L.ubar);
   d.v = reinterpret_cast<T*>(ws + L.v);
@@ -352,8 +355,9 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   }
   sim->resort_every = p.resort_every > 0 ? p.resort_every : 8;
   sim->since_bin = 0;
-  launch_deposit<T>(b, sim->counts[K_DEPOSIT], st);
-  launch_diag<T>(b, sim->counts[K_DIAG], 1, st);
+  launch_particles<T>(b, sim->counts[K_PART], 0, 1, st);  // ubar^0
+  launch_diag_clear<T>(b, 1, st);
+  launch_diag_init<T>(b, sim->counts[K_DIAG], 1, st);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));  // host staging buffers are freed on return
 
@@ -434,10 +438,23 @@ int fields_t(sipf_sim* sim, double* v, double* m, double* w, double* X, double* 
       for (int64_t i = 0; i < P; ++i) a[id[i]] = ha[i];
     }
   }
-  unsigned long long acc[D_COUNT];
+  // read-time reduction of the deposited density into buffer 2
+  {
+    const Batch<T> b = single_batch<T>(sim);
+    launch_diag_u<T>(b, sim->counts[K_DIAG], 1, sim->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(sim->stream));
+  }
+  unsigned long long all[2 * kStripeWords];
   uint64_t step = 0;
-  HIPCHK(hipMemcpy(acc, d.diag, sizeof(acc), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(all, d.diag + kDiagResult, sizeof(all), hipMemcpyDeviceToHost));
   HIPCHK(hipMemcpy(&step, d.step, sizeof(step), hipMemcpyDeviceToHost));
+  unsigned long long acc[D_COUNT];
+  memcpy(acc, all, sizeof(acc));
+  const unsigned long long* ub = all + kStripeWords;
+  acc[D_SUM_U] = ub[D_SUM_U];
+  acc[D_MIN_U] = ub[D_MIN_U];
+  acc[D_NAN] += ub[D_NAN];
   sipf_diag dg;
   dg.mass_particles = as_double(acc[D_SUM_A]);
   dg.mass_grid = as_double(acc[D_SUM_U]) * d.h3;
@@ -577,9 +594,9 @@ int step_timed_t(sipf_sim* sim, int nsteps, float* stage_ms) {
     (void)hipEventRecord(ev[4], st);
     launch_zinv<T>(b, c[K_ZINV], st);
     (void)hipEventRecord(ev[5], st);
-    launch_particles<T>(b, c[K_PART], bin, st);
+    launch_particles<T>(b, c[K_PART], bin, 0, st);
     (void)hipEventRecord(ev[6], st);
-    launch_diag_step<T>(b, c[K_DIAG], 1, st);
+    launch_finalize<T>(b, 1, st);
     (void)hipEventRecord(ev[7], st);
     sim->since_bin = bin ? 1 : sim->since_bin + 1;
     hipError_t e = hipEventSynchronize(ev[7]);
@@ -588,7 +605,7 @@ int step_timed_t(sipf_sim* sim, int nsteps, float* stage_ms) {
       rc = fail(SIPF_EHIP, std::string("timed step: ") + hipGetErrorString(e));
       break;
     }
-    for (int k = 0; k < SIPF_STAGE_DIAG + 1; ++k) {
+    for (int k = 0; k < SIPF_STAGE_FINALIZE + 1; ++k) {
       float ms = 0.f;
       (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
       stage_ms[k] += ms;

@@ -25,7 +25,7 @@
 // inverse transforms are decimation in frequency (natural input, bit-reversed output), so
 // no transform needs an explicit reordering step.  Inverse transforms are unnormalised; the
 // 1/N^3 factor is folded into the multipliers.
-#include "sipf_internal.h"
+#include "diag_acc.h"
 
 namespace sipf {
 
@@ -46,12 +46,11 @@ void block_counts(const SimDev<T>& d, int c[K_COUNT]) {
   c[K_YINV] = (int)(3 * ny + ny2);
   c[K_ZINV] = c[K_ZFWD];
   const int64_t pb = (d.P + kThreads - 1) / kThreads;
-  c[K_PART] = (int)((d.P + kChunk - 1) / kChunk + d.ntiles);  // bound on (tile, chunk) items
-  c[K_DEPOSIT] = (int)pb;
-  c[K_SCOUNT] = (int)pb;
+  c[K_PART] = d.max_chunks;  // bound on the number of (tile, chunk) items
+  c[K_SCOUNT] = (int)((d.P + kBinBlock - 1) / kBinBlock);
   c[K_SSCAN] = 1;
   c[K_SSCATTER] = (int)pb;
-  int64_t work = d.P > N * N * N ? d.P : N * N * N;
+  const int64_t work = d.P > N * N * N ? d.P : N * N * N;
   int64_t db = (work + kThreads * 8 - 1) / (kThreads * 8);
   if (db < 1) db = 1;
   if (db > 1024) db = 1024;
@@ -144,6 +143,8 @@ __global__ void __launch_bounds__(kThreads) k_zfwd(Batch<T> bt) {
   const T dt = (T)d.dt, gam = (T)d.gamma, adt = (T)(d.alpha * d.dt);
   const bool freeze_v = d.flags & SIPF_FLAG_FREEZE_V;
   const bool impl_v = d.flags & SIPF_FLAG_IMPLICIT_V;
+  Acc acc;
+  acc_init(acc);
   for (int e = threadIdx.x; e < B * N; e += kThreads) {
     const int rr = e >> lg, iz = e & (N - 1);
     const int64_t g = (r0 + rr) * N + iz;
@@ -151,7 +152,12 @@ __global__ void __launch_bounds__(kThreads) k_zfwd(Batch<T> bt) {
     const T ms = mm + dt * u;
     const T eta = (T)2 * u / ((T)1 + u);
     const T wsr = ww + dt * (gam * vv - eta * ww);
-    if (!freeze_v) d.v[g] = impl_v ? vv / ((T)1 + adt * mm) : vv * exp(-adt * mm);
+    T vn = vv;
+    if (!freeze_v) {
+      vn = impl_v ? vv / ((T)1 + adt * mm) : vv * exp(-adt * mm);
+      d.v[g] = vn;
+    }
+    if (isfinite((double)vn)) acc_min(acc, D_MIN_V, (double)vn); else acc.cnt[0] += 1;
     d.ubar[g] = (T)0;
     const int br = bitrev(iz, lg);
     A[rr * N + br] = cplx<T>{ms, wsr};
@@ -179,6 +185,7 @@ __global__ void __launch_bounds__(kThreads) k_zfwd(Batch<T> bt) {
     }
     d.SV[o] = Vv;
   }
+  acc_flush(acc, diag_stripe(d));
 }
 
 // ---- y passes -------------------------------------------------------------------------------
@@ -368,6 +375,8 @@ __global__ void __launch_bounds__(kThreads) k_zinv(Batch<T> bt) {
   fft_dif(MW, 2 * B + Bh, N, lg, tw, (T)-1);
   const bool freeze_m = d.flags & SIPF_FLAG_FREEZE_M;
   const bool freeze_w = d.flags & SIPF_FLAG_FREEZE_W;
+  Acc acc;
+  acc_init(acc);
   for (int e = threadIdx.x; e < B * N; e += kThreads) {
     const int rr = e >> lg, iz = e & (N - 1);
     const int br = bitrev(iz, lg);
@@ -377,9 +386,23 @@ __global__ void __launch_bounds__(kThreads) k_zinv(Batch<T> bt) {
     const cplx<T> gzp = GZ[(rr >> 1) * N + br];
     const T wold = d.w[g];
     d.g4[g] = vec4<T>{gg.x, gg.y, (rr & 1) ? gzp.y : gzp.x, wold};
-    if (!freeze_m) d.m[g] = mw.x;
-    if (!freeze_w) d.w[g] = mw.y;
+    T mn = mw.x, wn = mw.y;
+    if (!freeze_m) d.m[g] = mn; else mn = d.m[g];
+    if (!freeze_w) d.w[g] = wn; else wn = wold;
+    const double md = mn, wd = wn;
+    if (isfinite(md) && isfinite(wd)) {
+      acc.sum[2] += md;
+      acc_min(acc, D_MIN_M, md);
+      acc_min(acc, D_MAX_M, md);
+      acc_min(acc, D_MIN_W, wd);
+      acc_min(acc, D_MAX_W, wd);
+      acc.cnt[1] += md < 0.0;
+      acc.cnt[2] += wd < 0.0;
+    } else {
+      acc.cnt[0] += 1;
+    }
   }
+  acc_flush(acc, diag_stripe(d));
 }
 
 // ---- LDS sizes and launchers ----------------------------------------------------------------

@@ -17,7 +17,7 @@
 // deposits the new state into an LDS accumulator, and flushes every non-zero accumulator
 // node to the global density with one atomic.  A particle whose stencil leaves the region
 // (it drifted more than kMargin cells since the last binning) uses global memory instead.
-#include "sipf_internal.h"
+#include "diag_acc.h"
 
 namespace sipf {
 
@@ -133,21 +133,42 @@ __device__ __forceinline__ void deposit_global(T* ubar, const Stencil<T>& st, T 
 }
 
 // ---- particle pass ----------------------------------------------------------------------
+// deposit_only != 0: deposit the current state of set 0 and change nothing else (used once
+// at initialisation for ubar^0).
+//
+// The deposit accumulator in LDS is float64 in both precisions: float64 LDS atomics are
+// far cheaper than float32 ones under the same-address contention of dense cells, and the
+// wider sum loses nothing when the block's total is rounded into the global density.
+constexpr int kPer = kChunk / kThreads;  // particles per thread
+// particles whose loads are issued together (float64 ones need twice the registers)
+template <typename T> struct LoadBatch { static constexpr int n = 8; };
+template <> struct LoadBatch<double> { static constexpr int n = 4; };
+
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_particles(Batch<T> bt, int src_set) {
+__device__ __forceinline__ void deposit_lds(double* acc, const Stencil<T>& st, const int l[3],
+                                            T q) {
+  T wx[2], wy[2], wz[2];
+  weights(st, wx, wy, wz);
+#pragma unroll
+  for (int aa = 0; aa < 2; ++aa)
+#pragma unroll
+    for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+      for (int cc = 0; cc < 2; ++cc)
+        atomicAdd(&acc[rindex(l[0] + aa, l[1] + bb, l[2] + cc)],
+                  (double)(q * wx[aa] * wy[bb] * wz[cc]));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_particles(Batch<T> bt, int src_set,
+                                                        int deposit_only) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
   const int s = find_sim(bt, K_PART, lb);
   const SimDev<T>& d = bt.sims[s];
   const int nchunks = (int)d.coff[d.ntiles];
   if (lb >= nchunks) return;
-  // tile of this chunk: the last tile whose first chunk is <= lb
-  int lo = 0, hi = d.ntiles;
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if ((int)d.coff[mid] <= lb) lo = mid; else hi = mid;
-  }
-  const int tile = lo;
+  const int tile = (int)d.ctile[lb];
   const uint32_t start = d.toff[tile] + (uint32_t)(lb - (int)d.coff[tile]) * kChunk;
   const uint32_t tend = d.toff[tile + 1];
   const uint32_t end = start + kChunk < tend ? start + kChunk : tend;
@@ -159,174 +180,251 @@ __global__ void __launch_bounds__(kThreads) k_particles(Batch<T> bt, int src_set
   rg.o[2] = (tile % nt) * kTile - kMargin;
   const bool use_region = d.use_region;
 
-  vec4<T>* gl = reinterpret_cast<vec4<T>*>(smem_raw);  // gather array of the region
-  T* acc = reinterpret_cast<T*>(gl + kRegion3);        // deposit accumulator
-  if (use_region) {
-    for (int e = threadIdx.x; e < kRegion3; e += kThreads) {
-      const int rz = e % kRegion, ry = (e / kRegion) % kRegion, rx = e / (kRegion * kRegion);
-      gl[e] = d.g4[node((rg.o[0] + rx) & (N - 1), (rg.o[1] + ry) & (N - 1),
-                        (rg.o[2] + rz) & (N - 1), N)];
-      acc[e] = (T)0;
-    }
-    __syncthreads();
-  }
-
-  const uint32_t n = (uint32_t)(*d.step);
   const T* xi = d.xs[src_set];
   const T* yi = d.ys[src_set];
   const T* zi = d.zs[src_set];
   const double* ai = d.as[src_set];
   const uint32_t* idi = d.ids[src_set];
+  constexpr int kB = LoadBatch<T>::n;
+  T px[kB], py[kB], pz[kB];
+  double pa[kB];
+  uint32_t pid[kB];
+  // issue the loads of kB particles before any arithmetic on them
+  auto load_batch = [&](int j0) {
+#pragma unroll
+    for (int j = 0; j < kB; ++j) {
+      const uint32_t i = start + threadIdx.x + (j0 + j) * kThreads;
+      if (i < end) {
+        px[j] = xi[i];
+        py[j] = yi[i];
+        pz[j] = zi[i];
+        pa[j] = ai[i];
+        pid[j] = deposit_only ? 0u : idi[i];
+      }
+    }
+  };
+  load_batch(0);  // in flight while the region is staged
+
+  vec4<T>* gl = reinterpret_cast<vec4<T>*>(smem_raw);  // gather array of the region
+  double* acc = reinterpret_cast<double*>(gl + kRegion3);  // deposit accumulator
+  if (use_region) {
+    for (int e = threadIdx.x; e < kRegion3; e += kThreads) {
+      const int rz = e % kRegion, ry = (e / kRegion) % kRegion, rx = e / (kRegion * kRegion);
+      if (!deposit_only)
+        gl[e] = d.g4[node((rg.o[0] + rx) & (N - 1), (rg.o[1] + ry) & (N - 1),
+                          (rg.o[2] + rz) & (N - 1), N)];
+      acc[e] = 0.0;
+    }
+    __syncthreads();
+  }
+
+  const uint32_t n = (uint32_t)(*d.step);
   T* xo = d.xs[0];
   T* yo = d.ys[0];
   T* zo = d.zs[0];
   double* ao = d.as[0];
   const bool linear_mass = d.flags & SIPF_FLAG_LINEAR_MASS;
   const bool noise = !(d.flags & SIPF_FLAG_NO_NOISE);
+  Acc dg;
+  acc_init(dg);
 
-  for (uint32_t i = start + threadIdx.x; i < end; i += kThreads) {
-    const T x = xi[i], y = yi[i], z = zi[i];
-    const double a = ai[i];
-    const uint32_t id = idi[i];
+  for (int j0 = 0; j0 < kPer; j0 += kB) {
+    if (j0 > 0) load_batch(j0);
+#pragma unroll
+    for (int j = 0; j < kB; ++j) {
+      const uint32_t i = start + threadIdx.x + (j0 + j) * kThreads;
+      if (i >= end) continue;
+      const T x = px[j], y = py[j], z = pz[j];
+      const double a = pa[j];
+      int l[3];
+      if (deposit_only) {
+        const Stencil<T> s0 = make_stencil(x, y, z, d.inv_h, N);
+        const T q0 = (T)a * d.inv_h3;
+        if (use_region && in_region(s0, rg, N, l))
+          deposit_lds(acc, s0, l, q0);
+        else
+          deposit_global(d.ubar, s0, q0, N);
+        continue;
+      }
+      // gather (d1 v, d2 v, d3 v, w) at the old position
+      const Stencil<T> st = make_stencil(x, y, z, d.inv_h, N);
+      T wx[2], wy[2], wz[2];
+      weights(st, wx, wy, wz);
+      T g0 = 0, g1 = 0, g2 = 0, gw = 0;
+      if (use_region && in_region(st, rg, N, l)) {
+#pragma unroll
+        for (int aa = 0; aa < 2; ++aa)
+#pragma unroll
+          for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+            for (int cc = 0; cc < 2; ++cc) {
+              const vec4<T> q = gl[rindex(l[0] + aa, l[1] + bb, l[2] + cc)];
+              const T wgt = wx[aa] * wy[bb] * wz[cc];
+              g0 += wgt * q.x;
+              g1 += wgt * q.y;
+              g2 += wgt * q.z;
+              gw += wgt * q.w;
+            }
+      } else {
+        const int ix[2] = {st.c[0], (st.c[0] + 1) & (N - 1)};
+        const int iy[2] = {st.c[1], (st.c[1] + 1) & (N - 1)};
+        const int iz[2] = {st.c[2], (st.c[2] + 1) & (N - 1)};
+#pragma unroll
+        for (int aa = 0; aa < 2; ++aa)
+#pragma unroll
+          for (int bb = 0; bb < 2; ++bb)
+#pragma unroll
+            for (int cc = 0; cc < 2; ++cc) {
+              const vec4<T> q = d.g4[node(ix[aa], iy[bb], iz[cc], N)];
+              const T wgt = wx[aa] * wy[bb] * wz[cc];
+              g0 += wgt * q.x;
+              g1 += wgt * q.y;
+              g2 += wgt * q.z;
+              gw += wgt * q.w;
+            }
+      }
 
-    // gather (d1 v, d2 v, d3 v, w) at the old position
-    const Stencil<T> st = make_stencil(x, y, z, d.inv_h, N);
-    T wx[2], wy[2], wz[2];
-    weights(st, wx, wy, wz);
-    T g0 = 0, g1 = 0, g2 = 0, gw = 0;
-    int l[3];
-    if (use_region && in_region(st, rg, N, l)) {
-#pragma unroll
-      for (int aa = 0; aa < 2; ++aa)
-#pragma unroll
-        for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-          for (int cc = 0; cc < 2; ++cc) {
-            const vec4<T> q = gl[rindex(l[0] + aa, l[1] + bb, l[2] + cc)];
-            const T wgt = wx[aa] * wy[bb] * wz[cc];
-            g0 += wgt * q.x;
-            g1 += wgt * q.y;
-            g2 += wgt * q.z;
-            gw += wgt * q.w;
-          }
-    } else {
-      const int ix[2] = {st.c[0], (st.c[0] + 1) & (N - 1)};
-      const int iy[2] = {st.c[1], (st.c[1] + 1) & (N - 1)};
-      const int iz[2] = {st.c[2], (st.c[2] + 1) & (N - 1)};
-#pragma unroll
-      for (int aa = 0; aa < 2; ++aa)
-#pragma unroll
-        for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-          for (int cc = 0; cc < 2; ++cc) {
-            const vec4<T> q = d.g4[node(ix[aa], iy[bb], iz[cc], N)];
-            const T wgt = wx[aa] * wy[bb] * wz[cc];
-            g0 += wgt * q.x;
-            g1 += wgt * q.y;
-            g2 += wgt * q.z;
-            gw += wgt * q.w;
-          }
-    }
+      // Wiener increment: Philox counter (particle index, step, simulation)
+      T zn[3] = {0, 0, 0};
+      if (noise) {
+        uint32_t c0 = pid[j], c1 = n, c2 = d.sim_lo, c3 = d.sim_hi;
+        philox4x32_10(c0, c1, c2, c3, d.seed_lo, d.seed_hi);
+        box_muller(c0, c1, c2, c3, zn);
+      }
 
-    // Wiener increment: Philox counter (particle index, step, simulation)
-    T zn[3] = {0, 0, 0};
-    if (noise) {
-      uint32_t c0 = id, c1 = n, c2 = d.sim_lo, c3 = d.sim_hi;
-      philox4x32_10(c0, c1, c2, c3, d.seed_lo, d.seed_hi);
-      box_muller(c0, c1, c2, c3, zn);
-    }
+      // push and mass update
+      const T xn = wrap_periodic(x + d.drift * g0 + d.noise_amp * zn[0], d.L);
+      const T yn = wrap_periodic(y + d.drift * g1 + d.noise_amp * zn[1], d.L);
+      const T zz = wrap_periodic(z + d.drift * g2 + d.noise_amp * zn[2], d.L);
+      const T rho = (T)2 * gw / ((T)1 + gw);
+      const double an = linear_mass ? a * (1.0 + d.dt * (double)rho - d.dt)
+                                    : a * exp(d.dt * ((double)rho - 1.0));
+      xo[i] = xn;
+      yo[i] = yn;
+      zo[i] = zz;
+      ao[i] = an;
+      if (src_set) d.ids[0][i] = pid[j];
+      if (isfinite(an) && isfinite((double)xn) && isfinite((double)yn) && isfinite((double)zz)) {
+        dg.sum[0] += an;
+        acc_min(dg, D_MIN_A, an);
+        acc_min(dg, D_MAX_A, an);
+      } else {
+        dg.cnt[0] += 1;
+      }
 
-    // push and mass update
-    const T xn = wrap_periodic(x + d.drift * g0 + d.noise_amp * zn[0], d.L);
-    const T yn = wrap_periodic(y + d.drift * g1 + d.noise_amp * zn[1], d.L);
-    const T zz = wrap_periodic(z + d.drift * g2 + d.noise_amp * zn[2], d.L);
-    const T rho = (T)2 * gw / ((T)1 + gw);
-    const double an = linear_mass ? a * (1.0 + d.dt * (double)rho - d.dt)
-                                  : a * exp(d.dt * ((double)rho - 1.0));
-    xo[i] = xn;
-    yo[i] = yn;
-    zo[i] = zz;
-    ao[i] = an;
-    if (src_set) d.ids[0][i] = id;
-
-    // deposit of the new state: ubar^{n+1}
-    const Stencil<T> sn = make_stencil(xn, yn, zz, d.inv_h, N);
-    const T q = (T)an * d.inv_h3;
-    if (use_region && in_region(sn, rg, N, l)) {
-      weights(sn, wx, wy, wz);
-#pragma unroll
-      for (int aa = 0; aa < 2; ++aa)
-#pragma unroll
-        for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-          for (int cc = 0; cc < 2; ++cc)
-            atomicAdd(&acc[rindex(l[0] + aa, l[1] + bb, l[2] + cc)],
-                      q * wx[aa] * wy[bb] * wz[cc]);
-    } else {
-      deposit_global(d.ubar, sn, q, N);
+      // deposit of the new state: ubar^{n+1}
+      const Stencil<T> sn = make_stencil(xn, yn, zz, d.inv_h, N);
+      const T q = (T)an * d.inv_h3;
+      if (use_region && in_region(sn, rg, N, l))
+        deposit_lds(acc, sn, l, q);
+      else
+        deposit_global(d.ubar, sn, q, N);
     }
   }
 
   if (use_region) {
     __syncthreads();
     for (int e = threadIdx.x; e < kRegion3; e += kThreads) {
-      const T v = acc[e];
-      if (v != (T)0) {
+      const double v = acc[e];
+      if (v != 0.0) {
         const int rz = e % kRegion, ry = (e / kRegion) % kRegion, rx = e / (kRegion * kRegion);
         unsafeAtomicAdd(&d.ubar[node((rg.o[0] + rx) & (N - 1), (rg.o[1] + ry) & (N - 1),
                                      (rg.o[2] + rz) & (N - 1), N)],
-                        v);
+                        (T)v);
       }
     }
   }
-}
-
-// ---- standalone deposit of set 0 (initialisation) -----------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(kThreads) k_deposit(Batch<T> bt) {
-  int lb;
-  const int s = find_sim(bt, K_DEPOSIT, lb);
-  const SimDev<T>& d = bt.sims[s];
-  const int64_t i = (int64_t)lb * kThreads + threadIdx.x;
-  if (i >= d.P) return;
-  const Stencil<T> st = make_stencil(d.xs[0][i], d.ys[0][i], d.zs[0][i], d.inv_h, d.N);
-  deposit_global(d.ubar, st, (T)d.as[0][i] * d.inv_h3, d.N);
+  if (!deposit_only) acc_flush(dg, diag_stripe(d));
 }
 
 // ---- binning ----------------------------------------------------------------------------
-// Tile of every particle of set 0 and its rank among the particles of that tile; ranks come
-// from one atomic per distinct tile per wavefront.
+// Tile of every particle of set 0 and its rank among the particles of that tile.  A block
+// takes kBinChunk consecutive particles: wavefronts aggregate equal tiles (one LDS atomic per
+// distinct tile per wavefront) into a block-local hash table, then the block adds each
+// distinct tile's count to the global counter with one atomic and derives global ranks.
+// Set 0 is tile-ordered after the first binning, so a block sees one or two tiles and the
+// global counters see few atomics.  Tiles that do not fit the table take one global atomic
+// per wavefront instead.
+constexpr int kBinChunk = kBinBlock;
+constexpr int kBinPer = kBinChunk / kThreads;
+constexpr int kHash = 512;
+constexpr uint32_t kEmpty = 0xFFFFFFFFu;
+constexpr uint32_t kGlobalFlag = 0x80000000u;
+
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_bin_count(Batch<T> bt) {
   int lb;
   const int s = find_sim(bt, K_SCOUNT, lb);
   const SimDev<T>& d = bt.sims[s];
-  const int64_t i = (int64_t)lb * kThreads + threadIdx.x;
-  const bool valid = i < d.P;
-  uint32_t tile = 0;
-  if (valid) {
-    const int N = d.N, nt = d.ntile1;
-    const Stencil<T> st = make_stencil(d.xs[0][i], d.ys[0][i], d.zs[0][i], d.inv_h, N);
-    const int tx = st.c[0] / kTile, ty = st.c[1] / kTile, tz = st.c[2] / kTile;
-    tile = (uint32_t)(((tx < nt ? tx : nt - 1) * nt + (ty < nt ? ty : nt - 1)) * nt +
-                      (tz < nt ? tz : nt - 1));
+  __shared__ uint32_t hkey[kHash], hcnt[kHash], hbase[kHash];
+  for (int e = threadIdx.x; e < kHash; e += kThreads) {
+    hkey[e] = kEmpty;
+    hcnt[e] = 0;
   }
+  __syncthreads();
+  const int N = d.N, nt = d.ntile1;
   const int lane = threadIdx.x & 63;
-  unsigned long long pending = __ballot(valid);
-  uint32_t rank = 0;
-  while (pending) {
-    const int leader = __ffsll((long long)pending) - 1;
-    const uint32_t lt = __shfl(tile, leader, 64);
-    const unsigned long long same = __ballot(valid && tile == lt) & pending;
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(&d.tcount[lt], (uint32_t)__popcll(same));
-    base = __shfl(base, leader, 64);
-    if ((same >> lane) & 1ull) rank = base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
-    pending &= ~same;
+  const int64_t i0 = (int64_t)lb * kBinChunk + threadIdx.x;
+  uint32_t tiles[kBinPer], slot[kBinPer], lrank[kBinPer];
+#pragma unroll
+  for (int j = 0; j < kBinPer; ++j) {
+    const int64_t i = i0 + (int64_t)j * kThreads;
+    const bool valid = i < d.P;
+    uint32_t tile = 0;
+    if (valid) {
+      const Stencil<T> st = make_stencil(d.xs[0][i], d.ys[0][i], d.zs[0][i], d.inv_h, N);
+      const int tx = st.c[0] / kTile, ty = st.c[1] / kTile, tz = st.c[2] / kTile;
+      tile = (uint32_t)(((tx < nt ? tx : nt - 1) * nt + (ty < nt ? ty : nt - 1)) * nt +
+                        (tz < nt ? tz : nt - 1));
+    }
+    tiles[j] = tile;
+    slot[j] = kEmpty;
+    lrank[j] = 0;
+    unsigned long long pending = __ballot(valid);
+    while (pending) {
+      const int leader = __ffsll((long long)pending) - 1;
+      const uint32_t lt = __shfl(tile, leader, 64);
+      const unsigned long long same = __ballot(valid && tile == lt) & pending;
+      uint32_t sl = kEmpty, base = 0;
+      if (lane == leader) {
+        uint32_t h = (lt * 2654435761u) >> 23;  // 9-bit multiplicative hash
+        for (int probe = 0; probe < 16; ++probe, h = (h + 1) & (kHash - 1)) {
+          const uint32_t k = atomicCAS(&hkey[h], kEmpty, lt);
+          if (k == kEmpty || k == lt) {
+            sl = h;
+            break;
+          }
+        }
+        if (sl != kEmpty) {
+          base = atomicAdd(&hcnt[sl], (uint32_t)__popcll(same));
+        } else {
+          base = atomicAdd(&d.tcount[lt], (uint32_t)__popcll(same));
+          sl = kGlobalFlag;
+        }
+      }
+      sl = __shfl(sl, leader, 64);
+      base = __shfl(base, leader, 64);
+      if ((same >> lane) & 1ull) {
+        slot[j] = sl;
+        lrank[j] = base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+      }
+      pending &= ~same;
+    }
   }
-  if (valid) {
-    d.key[2 * i] = tile;
-    d.key[2 * i + 1] = rank;
+  __syncthreads();
+  for (int e = threadIdx.x; e < kHash; e += kThreads) {
+    const uint32_t k = hkey[e];
+    if (k != kEmpty) hbase[e] = atomicAdd(&d.tcount[k], hcnt[e]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < kBinPer; ++j) {
+    const int64_t i = i0 + (int64_t)j * kThreads;
+    if (i < d.P) {
+      const uint32_t r = slot[j] == kGlobalFlag ? lrank[j] : hbase[slot[j]] + lrank[j];
+      d.key[2 * i] = tiles[j];
+      d.key[2 * i + 1] = r;
+    }
   }
 }
 
@@ -367,10 +465,12 @@ __global__ void __launch_bounds__(kThreads) k_bin_scan(Batch<T> bt) {
   uint32_t rc = threadIdx.x ? pc[threadIdx.x - 1] : 0;
   for (int t = b0; t < b1; ++t) {
     const uint32_t c = d.tcount[t];
+    const uint32_t nch = (c + kChunk - 1) / kChunk;
     d.toff[t] = rp;
     d.coff[t] = rc;
+    for (uint32_t k = 0; k < nch; ++k) d.ctile[rc + k] = (uint32_t)t;
     rp += c;
-    rc += (c + kChunk - 1) / kChunk;
+    rc += nch;
     d.tcount[t] = 0;
   }
   if (threadIdx.x == kThreads - 1) {
@@ -396,19 +496,15 @@ __global__ void __launch_bounds__(kThreads) k_bin_scatter(Batch<T> bt) {
 
 template <typename T>
 size_t particle_lds_bytes() {
-  return kRegion3 * (sizeof(vec4<T>) + sizeof(T));
+  return kRegion3 * (sizeof(vec4<T>) + sizeof(double));
 }
 
 template <typename T>
-void launch_particles(const Batch<T>& b, int nblk, int src_set, hipStream_t st) {
+void launch_particles(const Batch<T>& b, int nblk, int src_set, int deposit_only,
+                      hipStream_t st) {
   if (nblk <= 0) return;
   hipLaunchKernelGGL(k_particles<T>, dim3(nblk), dim3(kThreads), particle_lds_bytes<T>(), st, b,
-                     src_set);
-}
-template <typename T>
-void launch_deposit(const Batch<T>& b, int nblk, hipStream_t st) {
-  if (nblk <= 0) return;
-  hipLaunchKernelGGL(k_deposit<T>, dim3(nblk), dim3(kThreads), 0, st, b);
+                     src_set, deposit_only);
 }
 template <typename T>
 void launch_binning(const Batch<T>& b, const int* tot, int nsims, hipStream_t st) {
@@ -418,10 +514,8 @@ void launch_binning(const Batch<T>& b, const int* tot, int nsims, hipStream_t st
   if (tot[K_SSCATTER] > 0)
     hipLaunchKernelGGL(k_bin_scatter<T>, dim3(tot[K_SSCATTER]), dim3(kThreads), 0, st, b);
 }
-template void launch_particles<double>(const Batch<double>&, int, int, hipStream_t);
-template void launch_particles<float>(const Batch<float>&, int, int, hipStream_t);
-template void launch_deposit<double>(const Batch<double>&, int, hipStream_t);
-template void launch_deposit<float>(const Batch<float>&, int, hipStream_t);
+template void launch_particles<double>(const Batch<double>&, int, int, int, hipStream_t);
+template void launch_particles<float>(const Batch<float>&, int, int, int, hipStream_t);
 template void launch_binning<double>(const Batch<double>&, const int*, int, hipStream_t);
 template void launch_binning<float>(const Batch<float>&, const int*, int, hipStream_t);
 

@@ -23,7 +23,8 @@ constexpr int kTile = 8;
 constexpr int kMargin = 1;
 constexpr int kRegion = kTile + 2 * kMargin + 1;
 constexpr int kRegion3 = kRegion * kRegion * kRegion;
-constexpr int kChunk = 2048;
+constexpr int kChunk = 4096;
+constexpr int kBinBlock = 2048;  // particles per block of the binning count kernel
 
 template <typename T>
 struct alignas(2 * sizeof(T)) cplx {
@@ -43,8 +44,7 @@ enum KernelKind {
   K_YINV,       // inverse y transforms (forms the y-derivative spectrum)
   K_ZINV,       // inverse z transform (half spectrum -> real), forms d3 v, writes fields
   K_PART,       // gather + Euler-Maruyama push + mass update + deposit
-  K_DIAG,       // reductions for the diagnostics
-  K_DEPOSIT,    // standalone deposit (initialisation)
+  K_DIAG,       // full reductions for the diagnostics (initialisation, read time)
   K_SCOUNT,     // binning: tile of every particle and its rank within the tile
   K_SSCAN,      // binning: tile and chunk offsets (one block per simulation)
   K_SSCATTER,   // binning: scatter particles into the sorted set
@@ -52,12 +52,19 @@ enum KernelKind {
 };
 
 // Diagnostic accumulator slots (uint64 words; sums stored as float64 bit patterns).
+// Layout of SimDev::diag: kStripes accumulator copies of kStripeWords words, then the reduced
+// diagnostics of the latest state (D_COUNT words), then the read-time reduction of ubar.
 enum DiagSlot {
   D_SUM_A = 0, D_SUM_U, D_SUM_M,
   D_MIN_V, D_MIN_M, D_MIN_W, D_MAX_M, D_MAX_W, D_MIN_A, D_MAX_A, D_MIN_U,
   D_NAN, D_NEG_M, D_NEG_W,
   D_COUNT
 };
+constexpr int kStripes = 64;
+constexpr int kStripeWords = 16;  // >= D_COUNT, 128 bytes
+constexpr int kDiagResult = kStripes * kStripeWords;   // offset of the reduced state diag
+constexpr int kDiagResultU = kDiagResult + kStripeWords;  // offset of the ubar reduction
+constexpr int kDiagWords = kDiagResultU + kStripeWords;
 
 // Device-visible description of one simulation.  All pointers point into its workspace.
 template <typename T>
@@ -91,6 +98,8 @@ struct SimDev {
   uint32_t* tcount;   // ntiles: particles per tile (zero between binnings)
   uint32_t* toff;     // ntiles + 1: first sorted index of each tile
   uint32_t* coff;     // ntiles + 1: first chunk of each tile
+  uint32_t* ctile;    // max_chunks: tile of each chunk
+  int max_chunks;     // bound on the number of chunks: ceil(P / kChunk) + ntiles
   uint32_t* key;      // 2P: (tile, rank within tile) per particle
   // grid (real, N^3 row-major)
   T *ubar, *v, *m, *w;
@@ -100,7 +109,7 @@ struct SimDev {
   cplx<T>* tw;        // exp(-2 pi i k / N), k < N/2
   T* mtab;            // separable multiplier tables: [field m | field w | lowpass] x N each
   uint64_t* step;     // absolute step index n (device-resident, advanced once per step)
-  unsigned long long* diag;  // D_COUNT accumulator words
+  unsigned long long* diag;  // kDiagWords words, see DiagSlot
 };
 
 template <typename T>
@@ -179,11 +188,13 @@ template <typename T> void launch_yfwd(const Batch<T>& b, int nblk, hipStream_t 
 template <typename T> void launch_xpass(const Batch<T>& b, int nblk, hipStream_t s);
 template <typename T> void launch_yinv(const Batch<T>& b, int nblk, hipStream_t s);
 template <typename T> void launch_zinv(const Batch<T>& b, int nblk, hipStream_t s);
-template <typename T> void launch_particles(const Batch<T>& b, int nblk, int src_set, hipStream_t s);
+template <typename T>
+void launch_particles(const Batch<T>& b, int nblk, int src_set, int deposit_only, hipStream_t s);
 template <typename T> void launch_binning(const Batch<T>& b, const int* tot, int nsims, hipStream_t s);
-template <typename T> void launch_deposit(const Batch<T>& b, int nblk, hipStream_t s);
-template <typename T> void launch_diag(const Batch<T>& b, int nblk, int nsims, hipStream_t s);
-template <typename T> void launch_diag_step(const Batch<T>& b, int nblk, int nsims, hipStream_t s);
+template <typename T> void launch_diag_init(const Batch<T>& b, int nblk, int nsims, hipStream_t s);
+template <typename T> void launch_diag_u(const Batch<T>& b, int nblk, int nsims, hipStream_t s);
+template <typename T> void launch_finalize(const Batch<T>& b, int nsims, hipStream_t s);
+template <typename T> void launch_diag_clear(const Batch<T>& b, int nsims, hipStream_t s);
 
 // LDS bytes the FFT kernels need (host side, for launch configuration).
 template <typename T> size_t fft_lds_bytes(int kind);

@@ -30,7 +30,7 @@ ERRORS = {-1: "SIPF_EINVAL", -2: "SIPF_ENOMEM", -3: "SIPF_EHIP", -4: "SIPF_EPOS"
 # exported symbols, as declared in include/sipf.h
 EXPORTS = ("sipf_state_bytes", "sipf_init", "sipf_step", "sipf_step_batch", "sipf_fields",
            "sipf_aux", "sipf_step_timed", "sipf_destroy", "sipf_last_error")
-STAGES = ("zfwd", "yfwd", "xpass", "yinv", "zinv", "particles", "diag", "binning")
+STAGES = ("zfwd", "yfwd", "xpass", "yinv", "zinv", "particles", "finalize", "binning")
 
 
 class Params(ctypes.Structure):

@@ -53,9 +53,10 @@ def test_state_bytes_scales():
     b64 = sipf.state_bytes(_p(N=64, P=1 << 20))
     b32 = sipf.state_bytes(_p(N=64, P=1 << 20, precision=1))
     assert b32 < b64
-    # particles: 3 s + 8 + 4 bytes; grid: (4 + 4) s N^3 real + 5 half spectra
+    # particles: two sets of (3 s + 8 + 4) bytes + an 8-byte binning key; grid: (4 + 4) s N^3
+    # real + 5 half spectra
     N, P = 64, 1 << 20
-    expect64 = P * (24 + 12) + N ** 3 * 8 * 8 + 5 * (N // 2 + 1) * N * N * 16
+    expect64 = P * (2 * (24 + 12) + 8) + N ** 3 * 8 * 8 + 5 * (N // 2 + 1) * N * N * 16
     assert expect64 <= b64 < expect64 + 64 * 1024
     assert sipf.state_bytes(_p(P=0)) > 0
 

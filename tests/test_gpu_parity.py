@@ -64,6 +64,12 @@ def test_blob16_full_length_fp64():
     d = out["diag"]
     assert d["step"] == 100 and d["n_nan"] == 0
     assert d["mass_grid"] == pytest.approx(d["mass_particles"], rel=1e-12)
+    od = S.diagnostics(ref, prm)
+    for k in ("mass_particles", "mass_grid", "mass_m", "min_v", "min_m", "min_w", "max_m",
+              "max_w", "min_a", "max_a", "min_u"):
+        assert d[k] == pytest.approx(od[k], rel=1e-9, abs=1e-12), k
+    for k in ("n_nan", "n_neg_m", "n_neg_w"):
+        assert d[k] == od[k], k
     print("blob16 fp64 errors", errs)
 
 
