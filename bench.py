@@ -108,6 +108,33 @@ def cpu_baseline(ic):
                        "float64 numpy oracle, single thread", seconds=round(dt, 2))
 
 
+def served(nreq, budget_gib, seed=4):
+    """Served mix: Poisson arrivals at 0.7 x the solo capacity (requests/s measured by
+    running a few requests alone first), continuous batching, p50/p99 latency."""
+    import numpy as np
+    from paper_2605_20140_amd import serve, workloads as W
+    q = W.served_mix(nreq=nreq, rate=None, steps=200, seed=seed)
+    reqs = serve.make_requests(q)
+    be = serve.GpuBackend(precision=1)
+    # solo capacity: the first few requests, one at a time
+    probe = reqs[:4]
+    t = time.perf_counter()
+    srv = serve.Server(be, budget_gib << 30, max_slots=1, tick_steps=50)
+    srv.run([serve.Request(r.rid, 0.0, r.N, r.P, r.steps, r.params, r.ic) for r in probe])
+    solo_s = (time.perf_counter() - t) / len(probe)
+    rate = 0.7 / solo_s
+    rng = np.random.Generator(np.random.Philox(seed))
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(reqs)))
+    for r, ta in zip(reqs, arrivals):
+        r.t_arrive = float(ta)
+    srv = serve.Server(be, budget_gib << 30, max_slots=64, tick_steps=10)
+    _, summ = srv.run(reqs)
+    summ.update(rate_per_s=rate, solo_service_s=solo_s, hbm_budget_gib=budget_gib,
+                max_slots=64, tick_steps=10, form="fp32",
+                mix="N in {32,64,128}, P = 2^U(16,22), chi = 10^U(-3,-2), 200 steps, dt 1e-3")
+    return summ
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -117,6 +144,10 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=24)
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--served-requests", type=int, default=48,
+                    help="requests in the served-mix run (0: skip it)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run one device copy of 512 MiB (reference for byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has no "
@@ -130,6 +161,14 @@ def main():
     prm = ic["params"]
     r32 = run_form(ic, 1, args.steps, args.warmup, args.profile_steps)
     r64 = None if args.no_fp64 else run_form(ic, 0, args.steps, args.warmup, args.profile_steps)
+    if args.copy_calibration:
+        src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda:0").fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    srv = served(args.served_requests, 32) if args.served_requests > 0 else None
     cpu = None if args.no_cpu_baseline else cpu_baseline(ic)
     line = {
         "metric": METRIC,
@@ -151,6 +190,7 @@ def main():
         "cpu_baseline": cpu,
         "stages": r32["stages"],
         "check": r32["check"],
+        "served": srv,
         "fp64": None if r64 is None else {
             "value": r64["value"], "ms_per_step": r64["ms_per_step"], "dtype": "f64",
             "roofline": r64["roofline"], "stages": r64["stages"], "check": r64["check"]},

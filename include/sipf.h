@@ -126,6 +126,12 @@ int sipf_init(const sipf_params* prm, void* d_workspace, size_t bytes, void* hip
  * SIPF_EHIP. */
 int sipf_step(sipf_sim* sim, int32_t nsteps);
 
+/* Move a simulation to another stream (for example from the stream it was initialised on
+ * to the stream its batch runs on).  Work already queued on the old stream is ordered
+ * before later work on the new one; nothing waits on the host.  Errors: SIPF_EINVAL,
+ * SIPF_EHIP. */
+int sipf_set_stream(sipf_sim* sim, void* hip_stream);
+
 /* Served form: enqueue nsteps steps of nsims resident simulations as one set of batched
  * launches (each kernel launch covers the work of all listed simulations).  All must share
  * the precision, deposit order and device; they run on the stream of sims[0].  Results are

@@ -135,6 +135,8 @@ struct sipf_sim {
   Layout lay;
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;
+  hipStream_t last_stream = nullptr;  // stream of the last batched step, if any
+  hipEvent_t ev = nullptr;            // orders this simulation's streams for batches
   int device = 0;
   int counts[K_COUNT];
   hipGraph_t graph = nullptr;       // one step
@@ -410,6 +412,7 @@ int fields_t(sipf_sim* sim, double* v, double* m, double* w, double* X, double* 
   const SimDev<T>& d = *reinterpret_cast<const SimDev<T>*>(sim->host_desc);
   const size_t G = (size_t)p.N * p.N * p.N;
   const int64_t P = p.P;
+  if (sim->last_stream) HIPCHK(hipStreamSynchronize(sim->last_stream));
   HIPCHK(hipStreamSynchronize(sim->stream));
   std::vector<T> buf(std::max<size_t>(G, (size_t)P));
   auto grid = [&](const T* src, double* dst) -> int {
@@ -486,6 +489,7 @@ int aux_t(sipf_sim* sim, double* u_bar, double* grad_v) {
   const sipf_params& p = sim->prm;
   const SimDev<T>& d = *reinterpret_cast<const SimDev<T>*>(sim->host_desc);
   const size_t G = (size_t)p.N * p.N * p.N;
+  if (sim->last_stream) HIPCHK(hipStreamSynchronize(sim->last_stream));
   HIPCHK(hipStreamSynchronize(sim->stream));
   if (u_bar) {
     std::vector<T> buf(G);
@@ -505,45 +509,62 @@ int aux_t(sipf_sim* sim, double* u_bar, double* grad_v) {
 }
 
 // ---- batched launches (served form) --------------------------------------------------------
-struct BatchSlot {
-  void* dev = nullptr;
-  void* host = nullptr;  // pinned staging
-  size_t cap = 0;
-  hipEvent_t done = nullptr;
+// A batch is a list of resident simulations stepped by one launch per kernel.  Its launch
+// table (descriptors and per-kernel block offsets) lives in a small library-owned device
+// buffer, and its step is captured as two HIP graphs (with and without binning).  Entries
+// are cached per simulation list (least recently used first out) and dropped when one of
+// their simulations is destroyed.
+struct BatchGraph {
+  std::vector<sipf_sim*> sims;
   int device = -1;
+  void* table = nullptr;
+  hipGraph_t graph[2] = {nullptr, nullptr};
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  hipEvent_t done = nullptr;
+  uint64_t last_use = 0;
 };
+constexpr size_t kMaxBatchGraphs = 8;
 std::mutex g_batch_mu;
-BatchSlot g_slots[4];
-int g_next_slot = 0;
+std::vector<BatchGraph*> g_graphs;
+uint64_t g_use_clock = 0;
+hipStream_t g_cap_stream[64] = {};
+
+void free_batch_graph(BatchGraph* e) {
+  if (e->done) (void)hipEventSynchronize(e->done);
+  for (int k = 0; k < 2; ++k) {
+    if (e->exec[k]) (void)hipGraphExecDestroy(e->exec[k]);
+    if (e->graph[k]) (void)hipGraphDestroy(e->graph[k]);
+  }
+  if (e->table) (void)hipFree(e->table);
+  if (e->done) (void)hipEventDestroy(e->done);
+  delete e;
+}
+
+// drop every cached batch that contains sim (called from sipf_destroy)
+void forget_sim(sipf_sim* sim) {
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  for (size_t i = 0; i < g_graphs.size();) {
+    BatchGraph* e = g_graphs[i];
+    if (std::find(e->sims.begin(), e->sims.end(), sim) != e->sims.end()) {
+      free_batch_graph(e);
+      g_graphs.erase(g_graphs.begin() + i);
+    } else {
+      ++i;
+    }
+  }
+}
 
 template <typename T>
-int step_batch_t(sipf_sim* const* sims, int nsims, int nsteps) {
-  hipStream_t st = sims[0]->stream;
+int build_batch_graph(sipf_sim* const* sims, int nsims, int dev, BatchGraph** out) {
+  BatchGraph* e = new BatchGraph();
+  e->sims.assign(sims, sims + nsims);
+  e->device = dev;
   const size_t desc_bytes = sizeof(SimDev<T>) * nsims;
   const size_t blk_off = align_up(desc_bytes);
   const size_t bytes = blk_off + sizeof(int) * K_COUNT * (nsims + 1);
+  std::vector<unsigned char> h(bytes);
+  int* blk = reinterpret_cast<int*>(h.data() + blk_off);
   std::vector<int> tot(K_COUNT, 0);
-  std::lock_guard<std::mutex> lk(g_batch_mu);
-  BatchSlot& sl = g_slots[g_next_slot];
-  g_next_slot = (g_next_slot + 1) % 4;
-  int dev = 0;
-  HIPCHK(hipGetDevice(&dev));
-  if (sl.done) HIPCHK(hipEventSynchronize(sl.done));  // previous use of this slot finished
-  if (sl.cap < bytes || sl.device != dev) {
-    if (sl.dev) HIPCHK(hipFree(sl.dev));
-    if (sl.host) HIPCHK(hipHostFree(sl.host));
-    if (sl.done) HIPCHK(hipEventDestroy(sl.done));
-    sl.dev = sl.host = nullptr;
-    sl.done = nullptr;
-    const size_t cap = std::max<size_t>(bytes * 2, 1 << 16);
-    HIPCHK(hipMalloc(&sl.dev, cap));
-    HIPCHK(hipHostMalloc(&sl.host, cap, hipHostMallocDefault));
-    HIPCHK(hipEventCreateWithFlags(&sl.done, hipEventDisableTiming));
-    sl.cap = cap;
-    sl.device = dev;
-  }
-  unsigned char* h = static_cast<unsigned char*>(sl.host);
-  int* blk = reinterpret_cast<int*>(h + blk_off);
   for (int k = 0; k < K_COUNT; ++k) {
     int acc = 0;
     for (int i = 0; i < nsims; ++i) {
@@ -554,20 +575,84 @@ int step_batch_t(sipf_sim* const* sims, int nsims, int nsteps) {
     tot[k] = acc;
   }
   for (int i = 0; i < nsims; ++i)
-    memcpy(h + sizeof(SimDev<T>) * i, sims[i]->host_desc, sizeof(SimDev<T>));
-  HIPCHK(hipMemcpyAsync(sl.dev, sl.host, bytes, hipMemcpyHostToDevice, st));
+    memcpy(h.data() + sizeof(SimDev<T>) * i, sims[i]->host_desc, sizeof(SimDev<T>));
+  int rc = SIPF_OK;
+  auto chk = [&](hipError_t err, const char* what) {
+    if (err != hipSuccess && rc == SIPF_OK)
+      rc = fail(SIPF_EHIP, std::string(what) + ": " + hipGetErrorString(err));
+  };
+  chk(hipMalloc(&e->table, bytes), "hipMalloc(batch table)");
+  if (rc == SIPF_OK) chk(hipMemcpy(e->table, h.data(), bytes, hipMemcpyHostToDevice), "hipMemcpy");
+  if (rc == SIPF_OK) chk(hipEventCreateWithFlags(&e->done, hipEventDisableTiming), "hipEventCreate");
+  if (rc == SIPF_OK && !g_cap_stream[dev])
+    chk(hipStreamCreateWithFlags(&g_cap_stream[dev], hipStreamNonBlocking), "hipStreamCreate");
   Batch<T> b;
-  b.sims = reinterpret_cast<const SimDev<T>*>(sl.dev);
-  b.blk = reinterpret_cast<const int*>(static_cast<unsigned char*>(sl.dev) + blk_off);
+  b.sims = reinterpret_cast<const SimDev<T>*>(e->table);
+  b.blk = reinterpret_cast<const int*>(static_cast<unsigned char*>(e->table) + blk_off);
   b.nsims = nsims;
+  for (int bin = 0; bin < 2 && rc == SIPF_OK; ++bin) {
+    chk(hipStreamBeginCapture(g_cap_stream[dev], hipStreamCaptureModeThreadLocal), "capture");
+    if (rc != SIPF_OK) break;
+    enqueue_step<T>(b, tot.data(), nsims, bin, g_cap_stream[dev]);
+    chk(hipStreamEndCapture(g_cap_stream[dev], &e->graph[bin]), "hipStreamEndCapture");
+    if (rc == SIPF_OK) chk(hipGetLastError(), "batched launch");
+    if (rc == SIPF_OK)
+      chk(hipGraphInstantiate(&e->exec[bin], e->graph[bin], nullptr, nullptr, 0),
+          "hipGraphInstantiate");
+  }
+  if (rc != SIPF_OK) {
+    free_batch_graph(e);
+    return rc;
+  }
+  *out = e;
+  return SIPF_OK;
+}
+
+template <typename T>
+int step_batch_t(sipf_sim* const* sims, int nsims, int nsteps) {
+  hipStream_t st = sims[0]->stream;
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return fail(SIPF_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  BatchGraph* e = nullptr;
+  for (BatchGraph* c : g_graphs)
+    if (c->device == dev && (int)c->sims.size() == nsims &&
+        std::equal(c->sims.begin(), c->sims.end(), sims)) {
+      e = c;
+      break;
+    }
+  if (!e) {
+    if (g_graphs.size() >= kMaxBatchGraphs) {
+      auto lru = std::min_element(g_graphs.begin(), g_graphs.end(),
+                                  [](BatchGraph* x, BatchGraph* y) {
+                                    return x->last_use < y->last_use;
+                                  });
+      free_batch_graph(*lru);
+      g_graphs.erase(lru);
+    }
+    const int rc = build_batch_graph<T>(sims, nsims, dev, &e);
+    if (rc) return rc;
+    g_graphs.push_back(e);
+  }
+  e->last_use = ++g_use_clock;
+  // work a simulation queued on other streams is ordered before the batch
+  for (int i = 0; i < nsims; ++i) {
+    for (hipStream_t o : {sims[i]->stream, sims[i]->last_stream}) {
+      if (o != st && o != nullptr) {
+        HIPCHK(hipEventRecord(sims[i]->ev, o));
+        HIPCHK(hipStreamWaitEvent(st, sims[i]->ev, 0));
+      }
+    }
+  }
   for (int s = 0; s < nsteps; ++s) {
     int bin = 0;
     for (int i = 0; i < nsims; ++i) bin |= sims[i]->since_bin >= sims[i]->resort_every;
-    enqueue_step<T>(b, tot.data(), nsims, bin, st);
+    HIPCHK(hipGraphLaunch(e->exec[bin], st));
     for (int i = 0; i < nsims; ++i) sims[i]->since_bin = bin ? 1 : sims[i]->since_bin + 1;
   }
-  HIPCHK(hipGetLastError());
-  HIPCHK(hipEventRecord(sl.done, st));
+  HIPCHK(hipEventRecord(e->done, st));
+  for (int i = 0; i < nsims; ++i) sims[i]->last_stream = st;
   return SIPF_OK;
 }
 
@@ -618,6 +703,16 @@ int step_timed_t(sipf_sim* sim, int nsteps, float* stage_ms) {
   return rc;
 }
 
+// Work on the simulation's own stream after batched steps on another stream waits for them.
+int order_after_batch(sipf_sim* sim) {
+  if (sim->last_stream && sim->last_stream != sim->stream) {
+    HIPCHK(hipEventRecord(sim->ev, sim->last_stream));
+    HIPCHK(hipStreamWaitEvent(sim->stream, sim->ev, 0));
+  }
+  sim->last_stream = nullptr;
+  return SIPF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -625,6 +720,8 @@ extern "C" {
 int sipf_step_timed(sipf_sim* sim, int32_t nsteps, float* stage_ms) {
   if (!sim || !stage_ms) return fail(SIPF_EINVAL, "sim / stage_ms is NULL");
   if (nsteps < 0) return fail(SIPF_EINVAL, "nsteps must be >= 0");
+  int rc = order_after_batch(sim);
+  if (rc) return rc;
   return sim->prm.precision == SIPF_FP64 ? step_timed_t<double>(sim, nsteps, stage_ms)
                                          : step_timed_t<float>(sim, nsteps, stage_ms);
 }
@@ -672,6 +769,10 @@ int sipf_init(const sipf_params* prm, void* d_workspace, size_t bytes, void* hip
   sim->lay = L;
   sim->stream = static_cast<hipStream_t>(hip_stream);
   (void)hipGetDevice(&sim->device);
+  if (hipEventCreateWithFlags(&sim->ev, hipEventDisableTiming) != hipSuccess) {
+    delete sim;
+    return fail(SIPF_EHIP, "hipEventCreate failed");
+  }
   rc = p.precision == SIPF_FP64 ? init_t<double>(sim, X0, a0, v0, m0, w0)
                                 : init_t<float>(sim, X0, a0, v0, m0, w0);
   if (rc) {
@@ -687,6 +788,8 @@ int sipf_init(const sipf_params* prm, void* d_workspace, size_t bytes, void* hip
 int sipf_step(sipf_sim* sim, int32_t nsteps) {
   if (!sim) return fail(SIPF_EINVAL, "sim is NULL");
   if (nsteps < 0) return fail(SIPF_EINVAL, "nsteps must be >= 0");
+  int rc = order_after_batch(sim);
+  if (rc) return rc;
   for (int32_t s = 0; s < nsteps; ++s) {
     if (sim->since_bin >= sim->resort_every) {
       HIPCHK(hipGraphLaunch(sim->exec_bin, sim->stream));
@@ -696,6 +799,25 @@ int sipf_step(sipf_sim* sim, int32_t nsteps) {
       sim->since_bin += 1;
     }
   }
+  return SIPF_OK;
+}
+
+int sipf_set_stream(sipf_sim* sim, void* hip_stream) {
+  if (!sim) return fail(SIPF_EINVAL, "sim is NULL");
+  hipStream_t ns = static_cast<hipStream_t>(hip_stream);
+  for (hipStream_t o : {sim->stream, sim->last_stream}) {
+    if (o && o != ns) {
+      HIPCHK(hipEventRecord(sim->ev, o));
+      HIPCHK(hipStreamWaitEvent(ns, sim->ev, 0));
+    }
+  }
+  if (!ns && (sim->stream || sim->last_stream)) {
+    // the null stream: wait on the host instead
+    if (sim->stream) HIPCHK(hipStreamSynchronize(sim->stream));
+    if (sim->last_stream) HIPCHK(hipStreamSynchronize(sim->last_stream));
+  }
+  sim->stream = ns;
+  sim->last_stream = nullptr;
   return SIPF_OK;
 }
 
@@ -733,7 +855,10 @@ int sipf_aux(sipf_sim* sim, double* u_bar, double* grad_v) {
 
 void sipf_destroy(sipf_sim* sim) {
   if (!sim) return;
+  forget_sim(sim);
+  if (sim->last_stream) (void)hipStreamSynchronize(sim->last_stream);
   (void)hipStreamSynchronize(sim->stream);
+  if (sim->ev) (void)hipEventDestroy(sim->ev);
   if (sim->exec) (void)hipGraphExecDestroy(sim->exec);
   if (sim->graph) (void)hipGraphDestroy(sim->graph);
   if (sim->exec_bin) (void)hipGraphExecDestroy(sim->exec_bin);

@@ -28,8 +28,8 @@ FLAG_ALIASED_DIFFUSION = 0x100
 ERRORS = {-1: "SIPF_EINVAL", -2: "SIPF_ENOMEM", -3: "SIPF_EHIP", -4: "SIPF_EPOS"}
 
 # exported symbols, as declared in include/sipf.h
-EXPORTS = ("sipf_state_bytes", "sipf_init", "sipf_step", "sipf_step_batch", "sipf_fields",
-           "sipf_aux", "sipf_step_timed", "sipf_destroy", "sipf_last_error")
+EXPORTS = ("sipf_state_bytes", "sipf_init", "sipf_step", "sipf_set_stream", "sipf_step_batch",
+           "sipf_fields", "sipf_aux", "sipf_step_timed", "sipf_destroy", "sipf_last_error")
 STAGES = ("zfwd", "yfwd", "xpass", "yinv", "zinv", "particles", "finalize", "binning")
 
 
@@ -84,6 +84,7 @@ def lib():
                                 dp, dp, dp, dp, dp, ctypes.POINTER(vp)]
         L.sipf_step.argtypes = [vp, ctypes.c_int32]
         L.sipf_step_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_int32]
+        L.sipf_set_stream.argtypes = [vp, vp]
         L.sipf_fields.argtypes = [vp, dp, dp, dp, dp, dp, ctypes.POINTER(Diag)]
         L.sipf_aux.argtypes = [vp, dp, dp]
         L.sipf_step_timed.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_float)]
@@ -91,7 +92,7 @@ def lib():
         L.sipf_destroy.restype = None
         L.sipf_last_error.restype = ctypes.c_char_p
         for name in ("sipf_state_bytes", "sipf_init", "sipf_step", "sipf_step_batch",
-                     "sipf_fields", "sipf_aux", "sipf_step_timed"):
+                     "sipf_fields", "sipf_aux", "sipf_step_timed", "sipf_set_stream"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -178,6 +179,11 @@ class Simulation:
         _check(lib().sipf_aux(self.handle, _dptr(u), _dptr(g)))
         return u.reshape(N, N, N), [g[j * N ** 3:(j + 1) * N ** 3].reshape(N, N, N)
                                     for j in range(3)]
+
+    def set_stream(self, stream):
+        """Move the simulation's work to a torch stream (queued work is ordered before)."""
+        _check(lib().sipf_set_stream(self.handle, ctypes.c_void_p(stream.cuda_stream)))
+        self.stream = stream
 
     def step_timed(self, nsteps=1):
         """Run nsteps steps eagerly with HIP events between stages; per-stage total ms."""
