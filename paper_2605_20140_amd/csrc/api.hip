@@ -159,18 +159,42 @@ Batch<T> single_batch(const sipf_sim* s) {
   return b;
 }
 
+// Simulations of one grid size, for the FFT launches (their kernels are compiled per N).
+template <typename T>
+struct FftGroup {
+  Batch<T> b;
+  int tot[K_COUNT];
+  int lg;
+};
+
+template <typename T>
+void enqueue_fft(const std::vector<FftGroup<T>>& groups, hipStream_t st) {
+  for (const auto& g : groups) launch_zfwd<T>(g.b, g.tot[K_ZFWD], g.lg, st);
+  for (const auto& g : groups) launch_yfwd<T>(g.b, g.tot[K_YFWD], g.lg, st);
+  for (const auto& g : groups) launch_xpass<T>(g.b, g.tot[K_XPASS], g.lg, st);
+  for (const auto& g : groups) launch_plane<T>(g.b, g.tot[K_PLANE], g.lg, st, 0);
+  for (const auto& g : groups) launch_yinv<T>(g.b, g.tot[K_YINV], g.lg, st);
+  for (const auto& g : groups) launch_zinv<T>(g.b, g.tot[K_ZINV], g.lg, st);
+}
+
 // One step; with bin != 0 the particles are first binned into set 1 and the particle pass
 // reads set 1 (and writes set 0).
 template <typename T>
-void enqueue_step(const Batch<T>& b, const int* tot, int nsims, int bin, hipStream_t st) {
+void enqueue_step(const Batch<T>& b, const int* tot, int nsims,
+                  const std::vector<FftGroup<T>>& groups, int bin, hipStream_t st) {
   if (bin) launch_binning<T>(b, tot, nsims, st);
-  launch_zfwd<T>(b, tot[K_ZFWD], st);
-  launch_yfwd<T>(b, tot[K_YFWD], st);
-  launch_xpass<T>(b, tot[K_XPASS], st);
-  launch_yinv<T>(b, tot[K_YINV], st);
-  launch_zinv<T>(b, tot[K_ZINV], st);
+  enqueue_fft<T>(groups, st);
   launch_particles<T>(b, tot[K_PART], bin ? 1 : 0, 0, st);
   launch_finalize<T>(b, nsims, st);
+}
+
+template <typename T>
+std::vector<FftGroup<T>> single_groups(const sipf_sim* s, const Batch<T>& b) {
+  FftGroup<T> g;
+  g.b = b;
+  memcpy(g.tot, s->counts, sizeof(g.tot));
+  g.lg = reinterpret_cast<const SimDev<T>*>(s->host_desc)->log2N;
+  return {g};
 }
 
 // float64 multiplier tables of the separable diffusion forms and of the low-pass filter,
@@ -227,6 +251,9 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   d.two_pi_over_L = (T)(2.0 * M_PI / p.L);
   d.inv_n3 = (T)(1.0 / ((double)N * N * N));
   d.inv_n2 = (T)(1.0 / ((double)N * N));
+  d.use_plane = plane_fits<T>(lg) ? 1 : 0;
+  d.gz_scale = (T)(2.0 * M_PI / p.L / (d.use_plane ? (double)N : (double)N * N));
+  if (d.use_plane) launch_plane<T>(Batch<T>{}, 0, lg, nullptr, 1);  // raise its LDS limit
   d.dt = p.dt;
   d.D_u = p.D_u;
   d.chi = p.chi;
@@ -365,13 +392,14 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
 
   // capture one step as a graph on a private stream; replays go to the caller's stream
   HIPCHK(hipStreamCreateWithFlags(&sim->cap, hipStreamNonBlocking));
+  const auto groups = single_groups<T>(sim, b);
   HIPCHK(hipStreamBeginCapture(sim->cap, hipStreamCaptureModeThreadLocal));
-  enqueue_step<T>(b, sim->counts, 1, 0, sim->cap);
+  enqueue_step<T>(b, sim->counts, 1, groups, 0, sim->cap);
   HIPCHK(hipStreamEndCapture(sim->cap, &sim->graph));
   HIPCHK(hipGetLastError());
   HIPCHK(hipGraphInstantiate(&sim->exec, sim->graph, nullptr, nullptr, 0));
   HIPCHK(hipStreamBeginCapture(sim->cap, hipStreamCaptureModeThreadLocal));
-  enqueue_step<T>(b, sim->counts, 1, 1, sim->cap);
+  enqueue_step<T>(b, sim->counts, 1, groups, 1, sim->cap);
   HIPCHK(hipStreamEndCapture(sim->cap, &sim->graph_bin));
   HIPCHK(hipGetLastError());
   HIPCHK(hipGraphInstantiate(&sim->exec_bin, sim->graph_bin, nullptr, nullptr, 0));
@@ -554,28 +582,68 @@ void forget_sim(sipf_sim* sim) {
   }
 }
 
+// Launch table of a list of simulations: descriptors, then per-kernel block offsets.
+template <typename T>
+size_t table_bytes(int n) {
+  return align_up(sizeof(SimDev<T>) * n) + align_up(sizeof(int) * K_COUNT * (n + 1));
+}
+
+template <typename T>
+void fill_table(sipf_sim* const* sims, int n, unsigned char* h, int* tot) {
+  const size_t blk_off = align_up(sizeof(SimDev<T>) * n);
+  int* blk = reinterpret_cast<int*>(h + blk_off);
+  for (int k = 0; k < K_COUNT; ++k) {
+    int acc = 0;
+    for (int i = 0; i < n; ++i) {
+      blk[k * (n + 1) + i] = acc;
+      acc += sims[i]->counts[k];
+    }
+    blk[k * (n + 1) + n] = acc;
+    tot[k] = acc;
+  }
+  for (int i = 0; i < n; ++i)
+    memcpy(h + sizeof(SimDev<T>) * i, sims[i]->host_desc, sizeof(SimDev<T>));
+}
+
+template <typename T>
+Batch<T> table_batch(unsigned char* dev, int n) {
+  Batch<T> b;
+  b.sims = reinterpret_cast<const SimDev<T>*>(dev);
+  b.blk = reinterpret_cast<const int*>(dev + align_up(sizeof(SimDev<T>) * n));
+  b.nsims = n;
+  return b;
+}
+
 template <typename T>
 int build_batch_graph(sipf_sim* const* sims, int nsims, int dev, BatchGraph** out) {
   BatchGraph* e = new BatchGraph();
   e->sims.assign(sims, sims + nsims);
   e->device = dev;
-  const size_t desc_bytes = sizeof(SimDev<T>) * nsims;
-  const size_t blk_off = align_up(desc_bytes);
-  const size_t bytes = blk_off + sizeof(int) * K_COUNT * (nsims + 1);
-  std::vector<unsigned char> h(bytes);
-  int* blk = reinterpret_cast<int*>(h.data() + blk_off);
-  std::vector<int> tot(K_COUNT, 0);
-  for (int k = 0; k < K_COUNT; ++k) {
-    int acc = 0;
-    for (int i = 0; i < nsims; ++i) {
-      blk[k * (nsims + 1) + i] = acc;
-      acc += sims[i]->counts[k];
-    }
-    blk[k * (nsims + 1) + nsims] = acc;
-    tot[k] = acc;
+  // the whole list, then one sub-list per grid size (FFT kernels are compiled per N)
+  std::vector<int> lgs;
+  for (int i = 0; i < nsims; ++i) {
+    const int lg = reinterpret_cast<const SimDev<T>*>(sims[i]->host_desc)->log2N;
+    if (std::find(lgs.begin(), lgs.end(), lg) == lgs.end()) lgs.push_back(lg);
   }
-  for (int i = 0; i < nsims; ++i)
-    memcpy(h.data() + sizeof(SimDev<T>) * i, sims[i]->host_desc, sizeof(SimDev<T>));
+  std::vector<std::vector<sipf_sim*>> sub(lgs.size());
+  for (int i = 0; i < nsims; ++i) {
+    const int lg = reinterpret_cast<const SimDev<T>*>(sims[i]->host_desc)->log2N;
+    sub[std::find(lgs.begin(), lgs.end(), lg) - lgs.begin()].push_back(sims[i]);
+  }
+  size_t bytes = table_bytes<T>(nsims);
+  std::vector<size_t> offs;
+  for (const auto& l : sub) {
+    offs.push_back(bytes);
+    bytes += table_bytes<T>((int)l.size());
+  }
+  std::vector<unsigned char> h(bytes, 0);
+  std::vector<int> tot(K_COUNT, 0);
+  fill_table<T>(sims, nsims, h.data(), tot.data());
+  std::vector<FftGroup<T>> groups(sub.size());
+  for (size_t g = 0; g < sub.size(); ++g) {
+    fill_table<T>(sub[g].data(), (int)sub[g].size(), h.data() + offs[g], groups[g].tot);
+    groups[g].lg = lgs[g];
+  }
   int rc = SIPF_OK;
   auto chk = [&](hipError_t err, const char* what) {
     if (err != hipSuccess && rc == SIPF_OK)
@@ -586,14 +654,14 @@ int build_batch_graph(sipf_sim* const* sims, int nsims, int dev, BatchGraph** ou
   if (rc == SIPF_OK) chk(hipEventCreateWithFlags(&e->done, hipEventDisableTiming), "hipEventCreate");
   if (rc == SIPF_OK && !g_cap_stream[dev])
     chk(hipStreamCreateWithFlags(&g_cap_stream[dev], hipStreamNonBlocking), "hipStreamCreate");
-  Batch<T> b;
-  b.sims = reinterpret_cast<const SimDev<T>*>(e->table);
-  b.blk = reinterpret_cast<const int*>(static_cast<unsigned char*>(e->table) + blk_off);
-  b.nsims = nsims;
+  unsigned char* base = static_cast<unsigned char*>(e->table);
+  const Batch<T> b = table_batch<T>(base, nsims);
+  for (size_t g = 0; g < sub.size(); ++g)
+    groups[g].b = table_batch<T>(base + offs[g], (int)sub[g].size());
   for (int bin = 0; bin < 2 && rc == SIPF_OK; ++bin) {
     chk(hipStreamBeginCapture(g_cap_stream[dev], hipStreamCaptureModeThreadLocal), "capture");
     if (rc != SIPF_OK) break;
-    enqueue_step<T>(b, tot.data(), nsims, bin, g_cap_stream[dev]);
+    enqueue_step<T>(b, tot.data(), nsims, groups, bin, g_cap_stream[dev]);
     chk(hipStreamEndCapture(g_cap_stream[dev], &e->graph[bin]), "hipStreamEndCapture");
     if (rc == SIPF_OK) chk(hipGetLastError(), "batched launch");
     if (rc == SIPF_OK)
@@ -661,6 +729,7 @@ int step_timed_t(sipf_sim* sim, int nsteps, float* stage_ms) {
   const Batch<T> b = single_batch<T>(sim);
   hipStream_t st = sim->stream;
   const int* c = sim->counts;
+  const int lg = reinterpret_cast<const SimDev<T>*>(sim->host_desc)->log2N;
   hipEvent_t ev[SIPF_NUM_STAGES + 1];
   for (auto& e : ev) HIPCHK(hipEventCreate(&e));
   int rc = SIPF_OK;
@@ -669,15 +738,16 @@ int step_timed_t(sipf_sim* sim, int nsteps, float* stage_ms) {
     (void)hipEventRecord(ev[SIPF_NUM_STAGES], st);
     if (bin) launch_binning<T>(b, c, 1, st);
     (void)hipEventRecord(ev[0], st);
-    launch_zfwd<T>(b, c[K_ZFWD], st);
+    launch_zfwd<T>(b, c[K_ZFWD], lg, st);
     (void)hipEventRecord(ev[1], st);
-    launch_yfwd<T>(b, c[K_YFWD], st);
+    launch_yfwd<T>(b, c[K_YFWD], lg, st);
     (void)hipEventRecord(ev[2], st);
-    launch_xpass<T>(b, c[K_XPASS], st);
+    launch_xpass<T>(b, c[K_XPASS], lg, st);
+    launch_plane<T>(b, c[K_PLANE], lg, st, 0);
     (void)hipEventRecord(ev[3], st);
-    launch_yinv<T>(b, c[K_YINV], st);
+    launch_yinv<T>(b, c[K_YINV], lg, st);
     (void)hipEventRecord(ev[4], st);
-    launch_zinv<T>(b, c[K_ZINV], st);
+    launch_zinv<T>(b, c[K_ZINV], lg, st);
     (void)hipEventRecord(ev[5], st);
     launch_particles<T>(b, c[K_PART], bin, 0, st);
     (void)hipEventRecord(ev[6], st);

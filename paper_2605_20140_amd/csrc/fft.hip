@@ -5,9 +5,10 @@
 // the transposed layout S[k3][i1][i2] with k3 in [0, N/2]: the z (i3) transform is done
 // first on contiguous rows and writes k3-major, so that every later pass reads and writes
 // contiguous runs (y lines are contiguous, x lines are strided by N with runs of
-// consecutive i2 per block).
+// consecutive i2 per block).  Along y the spectra are kept in the order the forward line
+// transform leaves them in (see below); the multipliers map positions to frequencies.
 //
-// Passes per step (each one kernel; transforms in LDS, radix 2):
+// Passes per step (each one kernel):
 //   zfwd : reaction (eq. g_hat_phy with S of eq. g_t) on (ubar, m, v, w) at time n, writes
 //          v^{n+1} and clears ubar; real z transforms of m*, w* (packed as m* + i w*) and of
 //          v^n (two rows packed) -> SM, SW, SV.
@@ -21,10 +22,14 @@
 //   zinv : forms the z-derivative spectrum i (2 pi/L) q_3 SV, inverse real z transforms of
 //          (SM, SW), (SGx, SGy) and of row pairs of the z derivative; writes m^{n+1},
 //          w^{n+1} and the gather array g4 = (d1 v^n, d2 v^n, d3 v^n, w^n).
-// Forward transforms are decimation in time (bit-reversed input order, natural output);
-// inverse transforms are decimation in frequency (natural input, bit-reversed output), so
-// no transform needs an explicit reordering step.  Inverse transforms are unnormalised; the
-// 1/N^3 factor is folded into the multipliers.
+//
+// Line transforms (length N = N1 N2, held in LDS): four-step.  Forward: N1 transforms of
+// length N2 over stride-N1 subsequences, twiddles W_N^{n1 k2}, then N2 transforms of length N1
+// over contiguous runs; each sub-transform runs in registers (unrolled radix 2).  The result
+// X[k2 + N2 k1] stays at position k1 + N1 k2 (fpos).  The inverse takes exactly that order and
+// returns natural order, so transform -> multiply -> inverse needs no reordering.  Two LDS
+// barriers per transform.  Inverse transforms are unnormalised; the 1/N^3 (or 1/N^2) factor
+// is folded into the multipliers.
 #include "diag_acc.h"
 
 namespace sipf {
@@ -41,9 +46,10 @@ void block_counts(const SimDev<T>& d, int c[K_COUNT]) {
   const int64_t ny = (lines + Bl - 1) / Bl;
   const int64_t ny2 = (lines + Bl / 2 - 1) / (Bl / 2);
   c[K_ZFWD] = (int)(N * N / d.rows_per_blk);
-  c[K_YFWD] = (int)(3 * ny);
-  c[K_XPASS] = (int)(3 * H * (N / d.cols_per_blk));
-  c[K_YINV] = (int)(3 * ny + ny2);
+  c[K_YFWD] = d.use_plane ? 0 : (int)(3 * ny);
+  c[K_XPASS] = d.use_plane ? 0 : (int)(3 * H * (N / d.cols_per_blk));
+  c[K_YINV] = d.use_plane ? 0 : (int)(3 * ny + ny2);
+  c[K_PLANE] = d.use_plane ? (int)(4 * H) : 0;
   c[K_ZINV] = c[K_ZFWD];
   const int64_t pb = (d.P + kThreads - 1) / kThreads;
   c[K_PART] = d.max_chunks;  // bound on the number of (tile, chunk) items
@@ -59,57 +65,173 @@ void block_counts(const SimDev<T>& d, int c[K_COUNT]) {
 template void block_counts<double>(const SimDev<double>&, int*);
 template void block_counts<float>(const SimDev<float>&, int*);
 
-// ---- radix-2 transforms of many lines held in LDS -----------------------------------------
-// Lines of length N = 2^lg are stored back to back.  tw[k] = exp(-2 pi i k / N), k < N/2.
-// Decimation in time: input in bit-reversed order, output natural.  sgn = +1 forward
-// (exp(-i)), -1 inverse (exp(+i)).
-template <typename T>
-__device__ void fft_dit(cplx<T>* buf, int nlines, int N, int lg, const cplx<T>* tw, T sgn) {
-  const int half = N >> 1;
-  const int nbf = nlines * half;
-  for (int s = 0; s < lg; ++s) {
-    __syncthreads();
+// ---- register transforms ----------------------------------------------------------------
+// exp(2 pi i k / 32) for k < 16, correctly rounded
+struct W32 {
+  double c, s;
+};
+__device__ constexpr W32 kW32[16] = {
+    {1.0, 0.0},
+    {0.9807852804032304, 0.19509032201612828},
+    {0.9238795325112867, 0.3826834323650898},
+    {0.8314696123025452, 0.5555702330196022},
+    {0.7071067811865476, 0.7071067811865476},
+    {0.5555702330196022, 0.8314696123025452},
+    {0.3826834323650898, 0.9238795325112867},
+    {0.19509032201612828, 0.9807852804032304},
+    {0.0, 1.0},
+    {-0.19509032201612828, 0.9807852804032304},
+    {-0.3826834323650898, 0.9238795325112867},
+    {-0.5555702330196022, 0.8314696123025452},
+    {-0.7071067811865476, 0.7071067811865476},
+    {-0.8314696123025452, 0.5555702330196022},
+    {-0.9238795325112867, 0.3826834323650898},
+    {-0.9807852804032304, 0.19509032201612828},
+};
+
+constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n >> 1); }
+constexpr int brevc(int x, int bits) {
+  int r = 0;
+  for (int i = 0; i < bits; ++i) r |= ((x >> i) & 1) << (bits - 1 - i);
+  return r;
+}
+
+// In-register DFT of length R <= 32, natural order in and out.  DIR = +1: exp(-2 pi i jk/R);
+// DIR = -1: exp(+2 pi i jk/R).
+template <typename T, int R, int DIR>
+__device__ __forceinline__ void reg_dft(cplx<T> (&a)[R]) {
+  constexpr int LR = ilog2c(R);
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int j = brevc(i, LR);
+    if (j > i) {
+      const cplx<T> t = a[i];
+      a[i] = a[j];
+      a[j] = t;
+    }
+  }
+#pragma unroll
+  for (int s = 0; s < LR; ++s) {
     const int hs = 1 << s;
-    const int tstep = half >> s;
-    for (int b = threadIdx.x; b < nbf; b += kThreads) {
-      const int line = b >> (lg - 1);
-      const int j = b & (half - 1);
+#pragma unroll
+    for (int j = 0; j < R / 2; ++j) {
       const int k = j & (hs - 1);
       const int i0 = ((j >> s) << (s + 1)) + k;
-      cplx<T> w = tw[k * tstep];
-      w.y *= sgn;
-      cplx<T>* Lp = buf + line * N;
-      const cplx<T> a = Lp[i0];
-      const cplx<T> t = cmul(Lp[i0 + hs], w);
-      Lp[i0] = cadd(a, t);
-      Lp[i0 + hs] = csub(a, t);
+      const int ti = k * (32 >> (s + 1));
+      const cplx<T> u = a[i0];
+      cplx<T> v = a[i0 + hs];
+      if (k != 0) v = cmul(v, cplx<T>{(T)kW32[ti].c, (T)(-DIR * kW32[ti].s)});
+      a[i0] = cadd(u, v);
+      a[i0 + hs] = csub(u, v);
     }
+  }
+}
+
+template <int LG>
+struct Split {
+  static constexpr int L1 = LG / 2, L2 = LG - LG / 2;
+  static constexpr int N1 = 1 << L1, N2 = 1 << L2, N = 1 << LG;
+};
+
+// position of frequency k after a forward line transform, and its inverse map
+template <int LG>
+__device__ __forceinline__ int fpos(int k) {
+  using S = Split<LG>;
+  return (k >> S::L2) + ((k & (S::N2 - 1)) << S::L1);
+}
+template <int LG>
+__device__ __forceinline__ int ufpos(int p) {
+  using S = Split<LG>;
+  return (p >> S::L1) + ((p & (S::N1 - 1)) << S::L2);
+}
+
+// W_N^e (DIR +1) or W_N^{-e} (DIR -1) for 0 <= e < N from tw[k] = W_N^k, k < N/2
+template <typename T, int LG, int DIR>
+__device__ __forceinline__ cplx<T> twid(const cplx<T>* tw, int e) {
+  constexpr int H = (1 << LG) >> 1;
+  cplx<T> w = e < H ? tw[e] : cplx<T>{-tw[e - H].x, -tw[e - H].y};
+  if (DIR < 0) w.y = -w.y;
+  return w;
+}
+
+// Line transforms over nlines lines of buf: element n of line l at buf[l * ls + n * es].
+// NT threads cooperate.  LINE_FAST maps consecutive threads to consecutive lines (for
+// columns, es > 1, so that a wavefront touches consecutive LDS words); otherwise to
+// consecutive elements of one line.
+template <int LG, bool LINE_FAST>
+struct TaskMap {
+  // task t -> (line, sub-index < R) for sub-transforms of R = 2^LR
+  template <int LR>
+  __device__ static __forceinline__ void map(int t, int nlines, int& line, int& j) {
+    if (LINE_FAST) {
+      line = t % nlines;
+      j = t / nlines;
+    } else {
+      line = t >> LR;
+      j = t & ((1 << LR) - 1);
+    }
+  }
+};
+
+// forward transforms: natural order -> fpos order
+template <typename T, int LG, bool LINE_FAST = false, int NT = kThreads>
+__device__ void line_fwd(cplx<T>* buf, int nlines, int ls, int es, const cplx<T>* tw) {
+  using S = Split<LG>;
+  for (int t = threadIdx.x; t < nlines * S::N1; t += NT) {
+    int line, n1;
+    TaskMap<LG, LINE_FAST>::template map<S::L1>(t, nlines, line, n1);
+    cplx<T>* Lp = buf + line * ls + n1 * es;
+    cplx<T> a[S::N2];
+#pragma unroll
+    for (int n2 = 0; n2 < S::N2; ++n2) a[n2] = Lp[(n2 << S::L1) * es];
+    reg_dft<T, S::N2, 1>(a);
+    Lp[0] = a[0];
+#pragma unroll
+    for (int k2 = 1; k2 < S::N2; ++k2)
+      Lp[(k2 << S::L1) * es] = cmul(a[k2], twid<T, LG, 1>(tw, n1 * k2));
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nlines * S::N2; t += NT) {
+    int line, k2;
+    TaskMap<LG, LINE_FAST>::template map<S::L2>(t, nlines, line, k2);
+    cplx<T>* Lp = buf + line * ls + (k2 << S::L1) * es;
+    cplx<T> a[S::N1];
+#pragma unroll
+    for (int n1 = 0; n1 < S::N1; ++n1) a[n1] = Lp[n1 * es];
+    reg_dft<T, S::N1, 1>(a);
+#pragma unroll
+    for (int k1 = 0; k1 < S::N1; ++k1) Lp[k1 * es] = a[k1];
   }
   __syncthreads();
 }
 
-// Decimation in frequency: input natural, output in bit-reversed order.
-template <typename T>
-__device__ void fft_dif(cplx<T>* buf, int nlines, int N, int lg, const cplx<T>* tw, T sgn) {
-  const int half = N >> 1;
-  const int nbf = nlines * half;
-  for (int s = lg - 1; s >= 0; --s) {
-    __syncthreads();
-    const int hs = 1 << s;
-    const int tstep = half >> s;
-    for (int b = threadIdx.x; b < nbf; b += kThreads) {
-      const int line = b >> (lg - 1);
-      const int j = b & (half - 1);
-      const int k = j & (hs - 1);
-      const int i0 = ((j >> s) << (s + 1)) + k;
-      cplx<T> w = tw[k * tstep];
-      w.y *= sgn;
-      cplx<T>* Lp = buf + line * N;
-      const cplx<T> a = Lp[i0];
-      const cplx<T> b2 = Lp[i0 + hs];
-      Lp[i0] = cadd(a, b2);
-      Lp[i0 + hs] = cmul(csub(a, b2), w);
-    }
+// inverse (unnormalised) transforms: fpos order -> natural order
+template <typename T, int LG, bool LINE_FAST = false, int NT = kThreads>
+__device__ void line_inv(cplx<T>* buf, int nlines, int ls, int es, const cplx<T>* tw) {
+  using S = Split<LG>;
+  for (int t = threadIdx.x; t < nlines * S::N2; t += NT) {
+    int line, a2;
+    TaskMap<LG, LINE_FAST>::template map<S::L2>(t, nlines, line, a2);
+    cplx<T>* Lp = buf + line * ls + (a2 << S::L1) * es;
+    cplx<T> v[S::N1];
+#pragma unroll
+    for (int b = 0; b < S::N1; ++b) v[b] = Lp[b * es];
+    reg_dft<T, S::N1, -1>(v);
+    Lp[0] = v[0];
+#pragma unroll
+    for (int c = 1; c < S::N1; ++c) Lp[c * es] = cmul(v[c], twid<T, LG, -1>(tw, c * a2));
+  }
+  __syncthreads();
+  for (int t = threadIdx.x; t < nlines * S::N1; t += NT) {
+    int line, c;
+    TaskMap<LG, LINE_FAST>::template map<S::L1>(t, nlines, line, c);
+    cplx<T>* Lp = buf + line * ls + c * es;
+    cplx<T> v[S::N2];
+#pragma unroll
+    for (int a2 = 0; a2 < S::N2; ++a2) v[a2] = Lp[(a2 << S::L1) * es];
+    reg_dft<T, S::N2, -1>(v);
+#pragma unroll
+    for (int dd = 0; dd < S::N2; ++dd) Lp[(dd << S::L1) * es] = v[dd];
   }
   __syncthreads();
 }
@@ -127,17 +249,14 @@ __device__ __forceinline__ int deriv_freq(int k, int N) {
 __device__ __forceinline__ int lap_freq(int k, int N) { return k < (N >> 1) ? k : k - N; }
 
 // ---- zfwd ---------------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(kThreads) k_zfwd(Batch<T> bt) {
-  extern __shared__ __align__(16) unsigned char smem_raw[];
-  int lb;
-  const int s = find_sim(bt, K_ZFWD, lb);
-  const SimDev<T>& d = bt.sims[s];
-  const int N = d.N, lg = d.log2N, B = d.rows_per_blk;
+template <typename T, int LG>
+__device__ void zfwd_body(const SimDev<T>& d, int lb, unsigned char* smem) {
+  constexpr int N = 1 << LG;
+  const int B = d.rows_per_blk;
   const int64_t N2 = (int64_t)N * N;
   const int64_t r0 = (int64_t)lb * B;
-  cplx<T>* A = reinterpret_cast<cplx<T>*>(smem_raw);  // B lines: m* + i w*
-  cplx<T>* Vp = A + B * N;                             // B/2 lines: v(row 2q) + i v(row 2q+1)
+  cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);  // B lines: m* + i w*
+  cplx<T>* Vp = A + B * N;                        // B/2 lines: v(row 2q) + i v(row 2q+1)
   cplx<T>* tw = Vp + (B >> 1) * N;
   load_twiddles(tw, d);
   const T dt = (T)d.dt, gam = (T)d.gamma, adt = (T)(d.alpha * d.dt);
@@ -146,7 +265,7 @@ __global__ void __launch_bounds__(kThreads) k_zfwd(Batch<T> bt) {
   Acc acc;
   acc_init(acc);
   for (int e = threadIdx.x; e < B * N; e += kThreads) {
-    const int rr = e >> lg, iz = e & (N - 1);
+    const int rr = e >> LG, iz = e & (N - 1);
     const int64_t g = (r0 + rr) * N + iz;
     const T u = d.ubar[g], mm = d.m[g], vv = d.v[g], ww = d.w[g];
     const T ms = mm + dt * u;
@@ -159,23 +278,23 @@ __global__ void __launch_bounds__(kThreads) k_zfwd(Batch<T> bt) {
     }
     if (isfinite((double)vn)) acc_min(acc, D_MIN_V, (double)vn); else acc.cnt[0] += 1;
     d.ubar[g] = (T)0;
-    const int br = bitrev(iz, lg);
-    A[rr * N + br] = cplx<T>{ms, wsr};
-    T* vp = reinterpret_cast<T*>(&Vp[(rr >> 1) * N + br]);
+    A[rr * N + iz] = cplx<T>{ms, wsr};
+    T* vp = reinterpret_cast<T*>(&Vp[(rr >> 1) * N + iz]);
     vp[rr & 1] = vv;
   }
-  fft_dit(A, B + (B >> 1), N, lg, tw, (T)1);
-  const int H = (N >> 1) + 1;
+  __syncthreads();
+  line_fwd<T, LG>(A, B + (B >> 1), N, 1, tw);
+  constexpr int H = (N >> 1) + 1;
   for (int e = threadIdx.x; e < H * B; e += kThreads) {
     const int kz = e / B, rr = e - kz * B;
-    const int kc = (N - kz) & (N - 1);
+    const int pk = fpos<LG>(kz), pc = fpos<LG>((N - kz) & (N - 1));
     const int64_t o = (int64_t)kz * N2 + r0 + rr;
-    const cplx<T> Z = A[rr * N + kz], Zc = cconj(A[rr * N + kc]);
+    const cplx<T> Z = A[rr * N + pk], Zc = cconj(A[rr * N + pc]);
     const cplx<T> Ms = cscale(cadd(Z, Zc), (T)0.5);
     const cplx<T> Dm = cscale(csub(Z, Zc), (T)0.5);
     d.SM[o] = Ms;
     d.SW[o] = cplx<T>{Dm.y, -Dm.x};
-    const cplx<T> Y = Vp[(rr >> 1) * N + kz], Yc = cconj(Vp[(rr >> 1) * N + kc]);
+    const cplx<T> Y = Vp[(rr >> 1) * N + pk], Yc = cconj(Vp[(rr >> 1) * N + pc]);
     cplx<T> Vv;
     if (rr & 1) {
       const cplx<T> Dv = cscale(csub(Y, Yc), (T)0.5);
@@ -188,43 +307,50 @@ __global__ void __launch_bounds__(kThreads) k_zfwd(Batch<T> bt) {
   acc_flush(acc, diag_stripe(d));
 }
 
-// ---- y passes -------------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(kThreads) k_yfwd(Batch<T> bt) {
+template <typename T, int LG>
+__global__ void __launch_bounds__(kThreads) k_zfwd(Batch<T> bt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
-  const int s = find_sim(bt, K_YFWD, lb);
-  const SimDev<T>& d = bt.sims[s];
-  const int N = d.N, lg = d.log2N, Bl = d.lines_per_blk;
+  const int s = find_sim(bt, K_ZFWD, lb);
+  zfwd_body<T, LG>(bt.sims[s], lb, smem_raw);
+}
+
+// ---- y passes -------------------------------------------------------------------------------
+// Along y the spectra stay in fpos order between yfwd and yinv.
+template <typename T, int LG>
+__device__ void yfwd_body(const SimDev<T>& d, int lb, unsigned char* smem) {
+  constexpr int N = 1 << LG;
+  const int Bl = d.lines_per_blk;
   const int64_t lines = (int64_t)((N >> 1) + 1) * N;
   const int nbf = (int)((lines + Bl - 1) / Bl);
   const int f = lb / nbf;
   const int64_t l0 = (int64_t)(lb - f * nbf) * Bl;
   const int nl = (int)((lines - l0) < Bl ? (lines - l0) : Bl);
-  cplx<T>* S = f == 0 ? d.SM : (f == 1 ? d.SW : d.SV);
-  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* S = (f == 0 ? d.SM : (f == 1 ? d.SW : d.SV)) + l0 * N;
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* tw = buf + Bl * N;
   load_twiddles(tw, d);
-  const cplx<T>* src = S + l0 * N;
-  for (int e = threadIdx.x; e < nl * N; e += kThreads) {
-    const int line = e >> lg, j = e & (N - 1);
-    buf[line * N + bitrev(j, lg)] = src[e];
-  }
-  fft_dit(buf, nl, N, lg, tw, (T)1);
-  cplx<T>* dst = S + l0 * N;
-  for (int e = threadIdx.x; e < nl * N; e += kThreads) dst[e] = buf[e];
+  for (int e = threadIdx.x; e < nl * N; e += kThreads) buf[e] = S[e];
+  __syncthreads();
+  line_fwd<T, LG>(buf, nl, N, 1, tw);
+  for (int e = threadIdx.x; e < nl * N; e += kThreads) S[e] = buf[e];
 }
 
-template <typename T>
-__global__ void __launch_bounds__(kThreads) k_yinv(Batch<T> bt) {
+template <typename T, int LG>
+__global__ void __launch_bounds__(kThreads) k_yfwd(Batch<T> bt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
-  const int s = find_sim(bt, K_YINV, lb);
-  const SimDev<T>& d = bt.sims[s];
-  const int N = d.N, lg = d.log2N, Bl = d.lines_per_blk;
+  const int s = find_sim(bt, K_YFWD, lb);
+  yfwd_body<T, LG>(bt.sims[s], lb, smem_raw);
+}
+
+template <typename T, int LG>
+__device__ void yinv_body(const SimDev<T>& d, int lb, unsigned char* smem) {
+  constexpr int N = 1 << LG;
+  const int Bl = d.lines_per_blk;
   const int64_t lines = (int64_t)((N >> 1) + 1) * N;
   const int nb1 = (int)((lines + Bl - 1) / Bl);
-  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* tw = buf + Bl * N;
   load_twiddles(tw, d);
   if (lb < 3 * nb1) {
@@ -233,47 +359,50 @@ __global__ void __launch_bounds__(kThreads) k_yinv(Batch<T> bt) {
     const int nl = (int)((lines - l0) < Bl ? (lines - l0) : Bl);
     cplx<T>* S = (f == 0 ? d.SM : (f == 1 ? d.SW : d.SGx)) + l0 * N;
     for (int e = threadIdx.x; e < nl * N; e += kThreads) buf[e] = S[e];
-    fft_dif(buf, nl, N, lg, tw, (T)-1);
-    for (int e = threadIdx.x; e < nl * N; e += kThreads) {
-      const int line = e >> lg, j = e & (N - 1);
-      S[e] = buf[line * N + bitrev(j, lg)];
-    }
+    __syncthreads();
+    line_inv<T, LG>(buf, nl, N, 1, tw);
+    for (int e = threadIdx.x; e < nl * N; e += kThreads) S[e] = buf[e];
   } else {
-    // SV lines: transform SV and form + transform SGy = i (2 pi/L) q2 SV / N^3
+    // SV lines: transform SV and form + transform SGy = i (2 pi/L) q2 SV / N^2 (SV is never
+    // transformed along x, so its round trip scales by N^2 only)
     const int Bh = Bl >> 1;
     const int64_t l0 = (int64_t)(lb - 3 * nb1) * Bh;
     const int nl = (int)((lines - l0) < Bh ? (lines - l0) : Bh);
     const cplx<T>* SV = d.SV + l0 * N;
-    // SV is never transformed along x, so its round trip scales by N^2 only
     const T c = d.two_pi_over_L * d.inv_n2;
     for (int e = threadIdx.x; e < nl * N; e += kThreads) {
-      const int line = e >> lg, j = e & (N - 1);
+      const int line = e >> LG, p = e & (N - 1);
       const cplx<T> V = SV[e];
-      const T kk = c * (T)deriv_freq(j, N);
-      buf[(2 * line) * N + j] = V;
-      buf[(2 * line + 1) * N + j] = cplx<T>{-kk * V.y, kk * V.x};
+      const T kk = c * (T)deriv_freq(ufpos<LG>(p), N);
+      buf[(2 * line) * N + p] = V;
+      buf[(2 * line + 1) * N + p] = cplx<T>{-kk * V.y, kk * V.x};
     }
-    fft_dif(buf, 2 * nl, N, lg, tw, (T)-1);
+    __syncthreads();
+    line_inv<T, LG>(buf, 2 * nl, N, 1, tw);
     cplx<T>* dV = d.SV + l0 * N;
     cplx<T>* dG = d.SGy + l0 * N;
     for (int e = threadIdx.x; e < nl * N; e += kThreads) {
-      const int line = e >> lg, j = e & (N - 1);
-      const int br = bitrev(j, lg);
-      dV[e] = buf[(2 * line) * N + br];
-      dG[e] = buf[(2 * line + 1) * N + br];
+      const int line = e >> LG, j = e & (N - 1);
+      dV[e] = buf[(2 * line) * N + j];
+      dG[e] = buf[(2 * line + 1) * N + j];
     }
   }
 }
 
-// ---- x pass: forward x transform, multipliers, inverse x transform ------------------------
-template <typename T>
-__global__ void __launch_bounds__(kThreads) k_xpass(Batch<T> bt) {
+template <typename T, int LG>
+__global__ void __launch_bounds__(kThreads) k_yinv(Batch<T> bt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
-  const int s = find_sim(bt, K_XPASS, lb);
-  const SimDev<T>& d = bt.sims[s];
-  const int N = d.N, lg = d.log2N, Bx = d.cols_per_blk;
-  const int H = (N >> 1) + 1;
+  const int s = find_sim(bt, K_YINV, lb);
+  yinv_body<T, LG>(bt.sims[s], lb, smem_raw);
+}
+
+// ---- x pass: forward x transform, multipliers, inverse x transform ------------------------
+template <typename T, int LG>
+__device__ void xpass_body(const SimDev<T>& d, int lb, unsigned char* smem) {
+  constexpr int N = 1 << LG;
+  const int Bx = d.cols_per_blk;
+  constexpr int H = (N >> 1) + 1;
   const int ncb = N / Bx;
   const int per_field = H * ncb;
   const int f = lb / per_field;
@@ -283,24 +412,26 @@ __global__ void __launch_bounds__(kThreads) k_xpass(Batch<T> bt) {
   const int64_t N2 = (int64_t)N * N;
   const cplx<T>* src = (f == 0 ? d.SM : (f == 1 ? d.SW : d.SV)) + (int64_t)kz * N2;
   cplx<T>* dst = (f == 0 ? d.SM : (f == 1 ? d.SW : d.SGx)) + (int64_t)kz * N2;
-  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem_raw);  // Bx lines of N along i1
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);  // Bx lines of N along i1
   cplx<T>* tw = buf + Bx * N;
   load_twiddles(tw, d);
   for (int e = threadIdx.x; e < Bx * N; e += kThreads) {
     const int c = e % Bx, ix = e / Bx;
-    buf[c * N + bitrev(ix, lg)] = src[(int64_t)ix * N + y0 + c];
+    buf[c * N + ix] = src[(int64_t)ix * N + y0 + c];
   }
-  fft_dit(buf, Bx, N, lg, tw, (T)1);
+  __syncthreads();
+  line_fwd<T, LG>(buf, Bx, N, 1, tw);
   const int qz = lap_freq(kz, N);
   const T k0 = d.two_pi_over_L;
   for (int e = threadIdx.x; e < Bx * N; e += kThreads) {
-    const int c = e >> lg, kx = e & (N - 1);
-    const int ky = y0 + c;
-    T mult;
+    const int c = e >> LG, p = e & (N - 1);
+    const int kx = ufpos<LG>(p);
+    const int ky = ufpos<LG>(y0 + c);
     cplx<T> val = buf[e];
     if (f < 2) {
       const T D = (T)(f == 0 ? d.D_m : d.D_w);
       const T decay = (T)(f == 0 ? d.beta : 1.0);
+      T mult;
       if (d.mult_kind == 0) {
         const int qx = lap_freq(kx, N), qy = lap_freq(ky, N);
         const T k2 = k0 * k0 * (T)(qx * qx + qy * qy + qz * qz);
@@ -325,35 +456,105 @@ __global__ void __launch_bounds__(kThreads) k_xpass(Batch<T> bt) {
     }
     buf[e] = val;
   }
-  fft_dif(buf, Bx, N, lg, tw, (T)-1);
+  __syncthreads();
+  line_inv<T, LG>(buf, Bx, N, 1, tw);
   for (int e = threadIdx.x; e < Bx * N; e += kThreads) {
     const int c = e % Bx, ix = e / Bx;
-    dst[(int64_t)ix * N + y0 + c] = buf[c * N + bitrev(ix, lg)];
+    dst[(int64_t)ix * N + y0 + c] = buf[c * N + ix];
   }
 }
 
-// ---- zinv ---------------------------------------------------------------------------------
-template <typename T>
-__global__ void __launch_bounds__(kThreads) k_zinv(Batch<T> bt) {
+template <typename T, int LG>
+__global__ void __launch_bounds__(kThreads) k_xpass(Batch<T> bt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
-  const int s = find_sim(bt, K_ZINV, lb);
-  const SimDev<T>& d = bt.sims[s];
-  const int N = d.N, lg = d.log2N, B = d.rows_per_blk;
+  const int s = find_sim(bt, K_XPASS, lb);
+  xpass_body<T, LG>(bt.sims[s], lb, smem_raw);
+}
+
+// ---- plane pass: y, x, multipliers, x^-1, y^-1 on one k3 plane in LDS --------------------
+// Replaces yfwd + xpass + yinv when a k3 plane of a half spectrum (N^2 complex values,
+// contiguous in the S[k3][i1][i2] layout) fits in LDS.  Four jobs per plane: M, W (diffusion
+// multipliers), and from V the x- and y-derivative spectra.  V itself is not written: it
+// stays transformed along z only, and zinv forms the z derivative from it (scale 1/N).
+template <typename T, int LG>
+__device__ void plane_body(const SimDev<T>& d, int lb, unsigned char* smem) {
+  constexpr int N = 1 << LG;
+  constexpr int NN = N * N;
+  constexpr int NT = kPlaneThreads;
+  const int job = lb & 3, kz = lb >> 2;
+  const int64_t off = (int64_t)kz * NN;
+  const cplx<T>* src = (job == 0 ? d.SM : (job == 1 ? d.SW : d.SV)) + off;
+  cplx<T>* dst = (job == 0 ? d.SM : (job == 1 ? d.SW : (job == 2 ? d.SGx : d.SGy))) + off;
+  cplx<T>* P = reinterpret_cast<cplx<T>*>(smem);  // P[i1 * N + i2]
+  cplx<T>* tw = P + NN;
+  for (int k = threadIdx.x; k < (N >> 1); k += NT) tw[k] = d.tw[k];
+  for (int e = threadIdx.x; e < NN; e += NT) P[e] = src[e];
+  __syncthreads();
+  line_fwd<T, LG, false, NT>(P, N, N, 1, tw);  // along i2 (rows)
+  line_fwd<T, LG, true, NT>(P, N, 1, N, tw);   // along i1 (columns)
+  const int qz = lap_freq(kz, N);
+  const T k0 = d.two_pi_over_L;
+  const T D = (T)(job == 0 ? d.D_m : d.D_w);
+  const T decay = (T)(job == 0 ? d.beta : 1.0);
+  for (int e = threadIdx.x; e < NN; e += NT) {
+    const int kx = ufpos<LG>(e >> LG), ky = ufpos<LG>(e & (N - 1));
+    cplx<T> val = P[e];
+    T lp = (T)1;
+    if (d.use_lowpass) {
+      const T* t = d.mtab + 2 * N;
+      lp = t[kx] * t[ky] * t[kz];
+    }
+    if (job < 2) {
+      T mult;
+      if (d.mult_kind == 0) {
+        const int qx = lap_freq(kx, N), qy = lap_freq(ky, N);
+        const T k2 = k0 * k0 * (T)(qx * qx + qy * qy + qz * qz);
+        mult = (T)1 / ((T)1 + (T)d.dt * (decay + D * k2));
+      } else {
+        const T* tab = d.mtab + job * N;
+        mult = (T)exp(-(T)d.dt * decay) * tab[kx] * tab[ky] * tab[kz];
+      }
+      val = cscale(val, mult * d.inv_n3 * lp);
+    } else {
+      const T kk = k0 * (T)deriv_freq(job == 2 ? kx : ky, N) * d.inv_n3 * lp;
+      val = cplx<T>{-kk * val.y, kk * val.x};
+    }
+    P[e] = val;
+  }
+  __syncthreads();
+  line_inv<T, LG, true, NT>(P, N, 1, N, tw);
+  line_inv<T, LG, false, NT>(P, N, N, 1, tw);
+  for (int e = threadIdx.x; e < NN; e += NT) dst[e] = P[e];
+}
+
+template <typename T, int LG>
+__global__ void __launch_bounds__(kPlaneThreads) k_plane(Batch<T> bt) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  int lb;
+  const int s = find_sim(bt, K_PLANE, lb);
+  plane_body<T, LG>(bt.sims[s], lb, smem_raw);
+}
+
+// ---- zinv ---------------------------------------------------------------------------------
+template <typename T, int LG>
+__device__ void zinv_body(const SimDev<T>& d, int lb, unsigned char* smem) {
+  constexpr int N = 1 << LG;
+  const int B = d.rows_per_blk;
   const int64_t N2 = (int64_t)N * N;
   const int64_t r0 = (int64_t)lb * B;
   const int Bh = B >> 1;
-  cplx<T>* MW = reinterpret_cast<cplx<T>*>(smem_raw);  // B lines: m + i w
-  cplx<T>* GG = MW + B * N;                            // B lines: d1 v + i d2 v
-  cplx<T>* GZ = GG + B * N;                            // B/2 lines: d3 v rows 2q + i 2q+1
+  cplx<T>* MW = reinterpret_cast<cplx<T>*>(smem);  // B lines: m + i w
+  cplx<T>* GG = MW + B * N;                       // B lines: d1 v + i d2 v
+  cplx<T>* GZ = GG + B * N;                       // B/2 lines: d3 v rows 2q + i 2q+1
   cplx<T>* tw = GZ + Bh * N;
   load_twiddles(tw, d);
-  const int H = (N >> 1) + 1;
-  const T cz = d.two_pi_over_L * d.inv_n2;  // SV: y and z round trips only
+  constexpr int H = (N >> 1) + 1;
+  const T cz = d.gz_scale;  // 2 pi / L over the transforms SV went through (N or N^2)
   for (int e = threadIdx.x; e < H * Bh; e += kThreads) {
     const int kz = e / Bh, q = e - kz * Bh;
-    const int kc = N - kz;
     const bool mirror = kz > 0 && kz < (N >> 1);
+    const int pk = fpos<LG>(kz), pc = fpos<LG>((N - kz) & (N - 1));
     const T kk = cz * (T)deriv_freq(kz, N);
     cplx<T> gz[2];
 #pragma unroll
@@ -361,29 +562,29 @@ __global__ void __launch_bounds__(kThreads) k_zinv(Batch<T> bt) {
       const int rr = 2 * q + h;
       const int64_t o = (int64_t)kz * N2 + r0 + rr;
       const cplx<T> M = d.SM[o], W = d.SW[o], Gx = d.SGx[o], Gy = d.SGy[o], V = d.SV[o];
-      MW[rr * N + kz] = cplx<T>{M.x - W.y, M.y + W.x};
-      GG[rr * N + kz] = cplx<T>{Gx.x - Gy.y, Gx.y + Gy.x};
+      MW[rr * N + pk] = cplx<T>{M.x - W.y, M.y + W.x};
+      GG[rr * N + pk] = cplx<T>{Gx.x - Gy.y, Gx.y + Gy.x};
       if (mirror) {
-        MW[rr * N + kc] = cplx<T>{M.x + W.y, W.x - M.y};
-        GG[rr * N + kc] = cplx<T>{Gx.x + Gy.y, Gy.x - Gx.y};
+        MW[rr * N + pc] = cplx<T>{M.x + W.y, W.x - M.y};
+        GG[rr * N + pc] = cplx<T>{Gx.x + Gy.y, Gy.x - Gx.y};
       }
       gz[h] = cplx<T>{-kk * V.y, kk * V.x};
     }
-    GZ[q * N + kz] = cplx<T>{gz[0].x - gz[1].y, gz[0].y + gz[1].x};
-    if (mirror) GZ[q * N + kc] = cplx<T>{gz[0].x + gz[1].y, gz[1].x - gz[0].y};
+    GZ[q * N + pk] = cplx<T>{gz[0].x - gz[1].y, gz[0].y + gz[1].x};
+    if (mirror) GZ[q * N + pc] = cplx<T>{gz[0].x + gz[1].y, gz[1].x - gz[0].y};
   }
-  fft_dif(MW, 2 * B + Bh, N, lg, tw, (T)-1);
+  __syncthreads();
+  line_inv<T, LG>(MW, 2 * B + Bh, N, 1, tw);
   const bool freeze_m = d.flags & SIPF_FLAG_FREEZE_M;
   const bool freeze_w = d.flags & SIPF_FLAG_FREEZE_W;
   Acc acc;
   acc_init(acc);
   for (int e = threadIdx.x; e < B * N; e += kThreads) {
-    const int rr = e >> lg, iz = e & (N - 1);
-    const int br = bitrev(iz, lg);
+    const int rr = e >> LG, iz = e & (N - 1);
     const int64_t g = (r0 + rr) * N + iz;
-    const cplx<T> mw = MW[rr * N + br];
-    const cplx<T> gg = GG[rr * N + br];
-    const cplx<T> gzp = GZ[(rr >> 1) * N + br];
+    const cplx<T> mw = MW[rr * N + iz];
+    const cplx<T> gg = GG[rr * N + iz];
+    const cplx<T> gzp = GZ[(rr >> 1) * N + iz];
     const T wold = d.w[g];
     d.g4[g] = vec4<T>{gg.x, gg.y, (rr & 1) ? gzp.y : gzp.x, wold};
     T mn = mw.x, wn = mw.y;
@@ -405,6 +606,14 @@ __global__ void __launch_bounds__(kThreads) k_zinv(Batch<T> bt) {
   acc_flush(acc, diag_stripe(d));
 }
 
+template <typename T, int LG>
+__global__ void __launch_bounds__(kThreads) k_zinv(Batch<T> bt) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  int lb;
+  const int s = find_sim(bt, K_ZINV, lb);
+  zinv_body<T, LG>(bt.sims[s], lb, smem_raw);
+}
+
 // ---- LDS sizes and launchers ----------------------------------------------------------------
 template <typename T>
 size_t fft_lds_bytes(int kind) {
@@ -423,20 +632,79 @@ size_t fft_lds_bytes(int kind) {
 template size_t fft_lds_bytes<double>(int);
 template size_t fft_lds_bytes<float>(int);
 
-#define SIPF_LAUNCH(KER, KIND)                                                              \
-  template <typename T>                                                                     \
-  void launch_##KER(const Batch<T>& b, int nblk, hipStream_t st) {                          \
-    if (nblk <= 0) return;                                                                  \
-    hipLaunchKernelGGL(k_##KER<T>, dim3(nblk), dim3(kThreads), fft_lds_bytes<T>(KIND), st, \
-                       b);                                                                  \
-  }                                                                                         \
-  template void launch_##KER<double>(const Batch<double>&, int, hipStream_t);               \
-  template void launch_##KER<float>(const Batch<float>&, int, hipStream_t);
+// Host-side dispatch: one kernel instantiation per log2 N, so each carries only the
+// registers its own transform length needs.
+#define SIPF_LG_CASE(KER, KIND, L)                                                          \
+  case L:                                                                                   \
+    hipLaunchKernelGGL((k_##KER<T, L>), dim3(nblk), dim3(kThreads), fft_lds_bytes<T>(KIND), \
+                       st, b);                                                              \
+    break;
+#define SIPF_LAUNCH(KER, KIND)                                                     \
+  template <typename T>                                                            \
+  void launch_##KER(const Batch<T>& b, int nblk, int lg, hipStream_t st) {         \
+    if (nblk <= 0) return;                                                         \
+    switch (lg) {                                                                  \
+      SIPF_LG_CASE(KER, KIND, 2)                                                   \
+      SIPF_LG_CASE(KER, KIND, 3)                                                   \
+      SIPF_LG_CASE(KER, KIND, 4)                                                   \
+      SIPF_LG_CASE(KER, KIND, 5)                                                   \
+      SIPF_LG_CASE(KER, KIND, 6)                                                   \
+      SIPF_LG_CASE(KER, KIND, 7)                                                   \
+      SIPF_LG_CASE(KER, KIND, 8)                                                   \
+      SIPF_LG_CASE(KER, KIND, 9)                                                   \
+      default: break;                                                              \
+    }                                                                              \
+  }                                                                                \
+  template void launch_##KER<double>(const Batch<double>&, int, int, hipStream_t); \
+  template void launch_##KER<float>(const Batch<float>&, int, int, hipStream_t);
 
 SIPF_LAUNCH(zfwd, K_ZFWD)
 SIPF_LAUNCH(yfwd, K_YFWD)
 SIPF_LAUNCH(xpass, K_XPASS)
 SIPF_LAUNCH(yinv, K_YINV)
 SIPF_LAUNCH(zinv, K_ZINV)
+
+template <typename T>
+size_t plane_lds_bytes(int lg) {
+  const size_t N = (size_t)1 << lg;
+  return (N * N + N / 2) * sizeof(cplx<T>);
+}
+
+template <typename T>
+bool plane_fits(int lg) {
+  return plane_lds_bytes<T>(lg) <= kPlaneLdsMax;
+}
+template bool plane_fits<double>(int);
+template bool plane_fits<float>(int);
+
+#define SIPF_PLANE_CASE(L)                                                                \
+  case L:                                                                                 \
+    if (configure) {                                                                      \
+      (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_plane<T, L>),            \
+                                hipFuncAttributeMaxDynamicSharedMemorySize,               \
+                                (int)plane_lds_bytes<T>(L));                              \
+    } else {                                                                              \
+      hipLaunchKernelGGL((k_plane<T, L>), dim3(nblk), dim3(kPlaneThreads),                \
+                         plane_lds_bytes<T>(L), st, b);                                   \
+    }                                                                                     \
+    break;
+
+// configure != 0: only raise the kernel's dynamic LDS limit (call once, outside capture)
+template <typename T>
+void launch_plane(const Batch<T>& b, int nblk, int lg, hipStream_t st, int configure) {
+  if (!configure && nblk <= 0) return;
+  if (!plane_fits<T>(lg)) return;
+  switch (lg) {
+    SIPF_PLANE_CASE(2)
+    SIPF_PLANE_CASE(3)
+    SIPF_PLANE_CASE(4)
+    SIPF_PLANE_CASE(5)
+    SIPF_PLANE_CASE(6)
+    SIPF_PLANE_CASE(7)
+    default: break;
+  }
+}
+template void launch_plane<double>(const Batch<double>&, int, int, hipStream_t, int);
+template void launch_plane<float>(const Batch<float>&, int, int, hipStream_t, int);
 
 }  // namespace sipf

@@ -26,6 +26,10 @@ constexpr int kRegion3 = kRegion * kRegion * kRegion;
 constexpr int kChunk = 4096;
 constexpr int kBinBlock = 2048;  // particles per block of the binning count kernel
 
+// Plane pass: one block of kPlaneThreads per k3 plane and job when a plane fits in LDS.
+constexpr int kPlaneThreads = 512;
+constexpr size_t kPlaneLdsMax = 150 * 1024;
+
 template <typename T>
 struct alignas(2 * sizeof(T)) cplx {
   T x, y;
@@ -41,6 +45,7 @@ enum KernelKind {
   K_ZFWD = 0,   // reaction + forward z transform (real -> half spectrum, transposed)
   K_YFWD,       // forward y transforms of M*, W*, V
   K_XPASS,      // x transform, spectral solves / gradient multiplier, inverse x transform
+  K_PLANE,      // y + x transforms, multipliers, inverses on whole k3 planes (small N)
   K_YINV,       // inverse y transforms (forms the y-derivative spectrum)
   K_ZINV,       // inverse z transform (half spectrum -> real), forms d3 v, writes fields
   K_PART,       // gather + Euler-Maruyama push + mass update + deposit
@@ -80,6 +85,8 @@ struct SimDev {
   T two_pi_over_L;
   T inv_n3;           // 1/N^3 (normalisation of a 3D transform round trip)
   T inv_n2;           // 1/N^2 (round trip of the y and z transforms only)
+  T gz_scale;         // (2 pi / L) / N (plane path) or / N^2 (three-pass path): d3 v from SV
+  int use_plane;      // y/x passes fused into the plane pass
   double dt, D_u, chi, D_m, D_w, alpha, beta, gamma;
   T noise_amp;        // sqrt(2 D_u dt)
   T drift;            // chi dt
@@ -183,11 +190,14 @@ __device__ __forceinline__ unsigned long long order_key(double d) {
 template <typename T> int elems_per_block();
 template <typename T> void block_counts(const SimDev<T>& d, int counts[K_COUNT]);
 
-template <typename T> void launch_zfwd(const Batch<T>& b, int nblk, hipStream_t s);
-template <typename T> void launch_yfwd(const Batch<T>& b, int nblk, hipStream_t s);
-template <typename T> void launch_xpass(const Batch<T>& b, int nblk, hipStream_t s);
-template <typename T> void launch_yinv(const Batch<T>& b, int nblk, hipStream_t s);
-template <typename T> void launch_zinv(const Batch<T>& b, int nblk, hipStream_t s);
+template <typename T> void launch_zfwd(const Batch<T>& b, int nblk, int lg, hipStream_t s);
+template <typename T> void launch_yfwd(const Batch<T>& b, int nblk, int lg, hipStream_t s);
+template <typename T> void launch_xpass(const Batch<T>& b, int nblk, int lg, hipStream_t s);
+template <typename T> void launch_yinv(const Batch<T>& b, int nblk, int lg, hipStream_t s);
+template <typename T> void launch_zinv(const Batch<T>& b, int nblk, int lg, hipStream_t s);
+template <typename T>
+void launch_plane(const Batch<T>& b, int nblk, int lg, hipStream_t s, int configure);
+template <typename T> bool plane_fits(int lg);
 template <typename T>
 void launch_particles(const Batch<T>& b, int nblk, int src_set, int deposit_only, hipStream_t s);
 template <typename T> void launch_binning(const Batch<T>& b, const int* tot, int nsims, hipStream_t s);
