@@ -30,6 +30,8 @@
 // returns natural order, so transform -> multiply -> inverse needs no reordering.  Two LDS
 // barriers per transform.  Inverse transforms are unnormalised; the 1/N^3 (or 1/N^2) factor
 // is folded into the multipliers.
+#include <algorithm>
+
 #include "diag_acc.h"
 
 namespace sipf {
@@ -132,6 +134,14 @@ struct Split {
   static constexpr int L1 = LG / 2, L2 = LG - LG / 2;
   static constexpr int N1 = 1 << L1, N2 = 1 << L2, N = 1 << LG;
 };
+
+// LDS row stride of N-point lines: padded so that rows 1 KB apart do not fall on the same
+// LDS banks when one wavefront transforms several rows
+template <int LG>
+constexpr int row_stride() {
+  return (1 << LG) + (LG >= 4 ? 4 : 0);
+}
+inline int row_stride_rt(int lg) { return (1 << lg) + (lg >= 4 ? 4 : 0); }
 
 // position of frequency k after a forward line transform, and its inverse map
 template <int LG>
@@ -255,9 +265,10 @@ __device__ void zfwd_body(const SimDev<T>& d, int lb, unsigned char* smem) {
   const int B = d.rows_per_blk;
   const int64_t N2 = (int64_t)N * N;
   const int64_t r0 = (int64_t)lb * B;
+  constexpr int LS = row_stride<LG>();
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);  // B lines: m* + i w*
-  cplx<T>* Vp = A + B * N;                        // B/2 lines: v(row 2q) + i v(row 2q+1)
-  cplx<T>* tw = Vp + (B >> 1) * N;
+  cplx<T>* Vp = A + B * LS;                       // B/2 lines: v(row 2q) + i v(row 2q+1)
+  cplx<T>* tw = Vp + (B >> 1) * LS;
   load_twiddles(tw, d);
   const T dt = (T)d.dt, gam = (T)d.gamma, adt = (T)(d.alpha * d.dt);
   const bool freeze_v = d.flags & SIPF_FLAG_FREEZE_V;
@@ -278,23 +289,23 @@ __device__ void zfwd_body(const SimDev<T>& d, int lb, unsigned char* smem) {
     }
     if (isfinite((double)vn)) acc_min(acc, D_MIN_V, (double)vn); else acc.cnt[0] += 1;
     d.ubar[g] = (T)0;
-    A[rr * N + iz] = cplx<T>{ms, wsr};
-    T* vp = reinterpret_cast<T*>(&Vp[(rr >> 1) * N + iz]);
+    A[rr * LS + iz] = cplx<T>{ms, wsr};
+    T* vp = reinterpret_cast<T*>(&Vp[(rr >> 1) * LS + iz]);
     vp[rr & 1] = vv;
   }
   __syncthreads();
-  line_fwd<T, LG>(A, B + (B >> 1), N, 1, tw);
+  line_fwd<T, LG>(A, B + (B >> 1), LS, 1, tw);
   constexpr int H = (N >> 1) + 1;
   for (int e = threadIdx.x; e < H * B; e += kThreads) {
     const int kz = e / B, rr = e - kz * B;
     const int pk = fpos<LG>(kz), pc = fpos<LG>((N - kz) & (N - 1));
     const int64_t o = (int64_t)kz * N2 + r0 + rr;
-    const cplx<T> Z = A[rr * N + pk], Zc = cconj(A[rr * N + pc]);
+    const cplx<T> Z = A[rr * LS + pk], Zc = cconj(A[rr * LS + pc]);
     const cplx<T> Ms = cscale(cadd(Z, Zc), (T)0.5);
     const cplx<T> Dm = cscale(csub(Z, Zc), (T)0.5);
     d.SM[o] = Ms;
     d.SW[o] = cplx<T>{Dm.y, -Dm.x};
-    const cplx<T> Y = Vp[(rr >> 1) * N + pk], Yc = cconj(Vp[(rr >> 1) * N + pc]);
+    const cplx<T> Y = Vp[(rr >> 1) * LS + pk], Yc = cconj(Vp[(rr >> 1) * LS + pc]);
     cplx<T> Vv;
     if (rr & 1) {
       const cplx<T> Dv = cscale(csub(Y, Yc), (T)0.5);
@@ -327,13 +338,14 @@ __device__ void yfwd_body(const SimDev<T>& d, int lb, unsigned char* smem) {
   const int64_t l0 = (int64_t)(lb - f * nbf) * Bl;
   const int nl = (int)((lines - l0) < Bl ? (lines - l0) : Bl);
   cplx<T>* S = (f == 0 ? d.SM : (f == 1 ? d.SW : d.SV)) + l0 * N;
+  constexpr int LS = row_stride<LG>();
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
-  cplx<T>* tw = buf + Bl * N;
+  cplx<T>* tw = buf + Bl * LS;
   load_twiddles(tw, d);
-  for (int e = threadIdx.x; e < nl * N; e += kThreads) buf[e] = S[e];
+  for (int e = threadIdx.x; e < nl * N; e += kThreads) buf[(e >> LG) * LS + (e & (N - 1))] = S[e];
   __syncthreads();
-  line_fwd<T, LG>(buf, nl, N, 1, tw);
-  for (int e = threadIdx.x; e < nl * N; e += kThreads) S[e] = buf[e];
+  line_fwd<T, LG>(buf, nl, LS, 1, tw);
+  for (int e = threadIdx.x; e < nl * N; e += kThreads) S[e] = buf[(e >> LG) * LS + (e & (N - 1))];
 }
 
 template <typename T, int LG>
@@ -350,18 +362,21 @@ __device__ void yinv_body(const SimDev<T>& d, int lb, unsigned char* smem) {
   const int Bl = d.lines_per_blk;
   const int64_t lines = (int64_t)((N >> 1) + 1) * N;
   const int nb1 = (int)((lines + Bl - 1) / Bl);
+  constexpr int LS = row_stride<LG>();
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
-  cplx<T>* tw = buf + Bl * N;
+  cplx<T>* tw = buf + Bl * LS;
   load_twiddles(tw, d);
   if (lb < 3 * nb1) {
     const int f = lb / nb1;
     const int64_t l0 = (int64_t)(lb - f * nb1) * Bl;
     const int nl = (int)((lines - l0) < Bl ? (lines - l0) : Bl);
     cplx<T>* S = (f == 0 ? d.SM : (f == 1 ? d.SW : d.SGx)) + l0 * N;
-    for (int e = threadIdx.x; e < nl * N; e += kThreads) buf[e] = S[e];
+    for (int e = threadIdx.x; e < nl * N; e += kThreads)
+      buf[(e >> LG) * LS + (e & (N - 1))] = S[e];
     __syncthreads();
-    line_inv<T, LG>(buf, nl, N, 1, tw);
-    for (int e = threadIdx.x; e < nl * N; e += kThreads) S[e] = buf[e];
+    line_inv<T, LG>(buf, nl, LS, 1, tw);
+    for (int e = threadIdx.x; e < nl * N; e += kThreads)
+      S[e] = buf[(e >> LG) * LS + (e & (N - 1))];
   } else {
     // SV lines: transform SV and form + transform SGy = i (2 pi/L) q2 SV / N^2 (SV is never
     // transformed along x, so its round trip scales by N^2 only)
@@ -374,17 +389,17 @@ __device__ void yinv_body(const SimDev<T>& d, int lb, unsigned char* smem) {
       const int line = e >> LG, p = e & (N - 1);
       const cplx<T> V = SV[e];
       const T kk = c * (T)deriv_freq(ufpos<LG>(p), N);
-      buf[(2 * line) * N + p] = V;
-      buf[(2 * line + 1) * N + p] = cplx<T>{-kk * V.y, kk * V.x};
+      buf[(2 * line) * LS + p] = V;
+      buf[(2 * line + 1) * LS + p] = cplx<T>{-kk * V.y, kk * V.x};
     }
     __syncthreads();
-    line_inv<T, LG>(buf, 2 * nl, N, 1, tw);
+    line_inv<T, LG>(buf, 2 * nl, LS, 1, tw);
     cplx<T>* dV = d.SV + l0 * N;
     cplx<T>* dG = d.SGy + l0 * N;
     for (int e = threadIdx.x; e < nl * N; e += kThreads) {
       const int line = e >> LG, j = e & (N - 1);
-      dV[e] = buf[(2 * line) * N + j];
-      dG[e] = buf[(2 * line + 1) * N + j];
+      dV[e] = buf[(2 * line) * LS + j];
+      dG[e] = buf[(2 * line + 1) * LS + j];
     }
   }
 }
@@ -412,22 +427,23 @@ __device__ void xpass_body(const SimDev<T>& d, int lb, unsigned char* smem) {
   const int64_t N2 = (int64_t)N * N;
   const cplx<T>* src = (f == 0 ? d.SM : (f == 1 ? d.SW : d.SV)) + (int64_t)kz * N2;
   cplx<T>* dst = (f == 0 ? d.SM : (f == 1 ? d.SW : d.SGx)) + (int64_t)kz * N2;
+  constexpr int LS = row_stride<LG>();
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);  // Bx lines of N along i1
-  cplx<T>* tw = buf + Bx * N;
+  cplx<T>* tw = buf + Bx * LS;
   load_twiddles(tw, d);
   for (int e = threadIdx.x; e < Bx * N; e += kThreads) {
     const int c = e % Bx, ix = e / Bx;
-    buf[c * N + ix] = src[(int64_t)ix * N + y0 + c];
+    buf[c * LS + ix] = src[(int64_t)ix * N + y0 + c];
   }
   __syncthreads();
-  line_fwd<T, LG>(buf, Bx, N, 1, tw);
+  line_fwd<T, LG>(buf, Bx, LS, 1, tw);
   const int qz = lap_freq(kz, N);
   const T k0 = d.two_pi_over_L;
   for (int e = threadIdx.x; e < Bx * N; e += kThreads) {
     const int c = e >> LG, p = e & (N - 1);
     const int kx = ufpos<LG>(p);
     const int ky = ufpos<LG>(y0 + c);
-    cplx<T> val = buf[e];
+    cplx<T> val = buf[c * LS + p];
     if (f < 2) {
       const T D = (T)(f == 0 ? d.D_m : d.D_w);
       const T decay = (T)(f == 0 ? d.beta : 1.0);
@@ -454,13 +470,13 @@ __device__ void xpass_body(const SimDev<T>& d, int lb, unsigned char* smem) {
       }
       val = cplx<T>{-kk * val.y, kk * val.x};
     }
-    buf[e] = val;
+    buf[c * LS + p] = val;
   }
   __syncthreads();
-  line_inv<T, LG>(buf, Bx, N, 1, tw);
+  line_inv<T, LG>(buf, Bx, LS, 1, tw);
   for (int e = threadIdx.x; e < Bx * N; e += kThreads) {
     const int c = e % Bx, ix = e / Bx;
-    dst[(int64_t)ix * N + y0 + c] = buf[c * N + ix];
+    dst[(int64_t)ix * N + y0 + c] = buf[c * LS + ix];
   }
 }
 
@@ -486,20 +502,22 @@ __device__ void plane_body(const SimDev<T>& d, int lb, unsigned char* smem) {
   const int64_t off = (int64_t)kz * NN;
   const cplx<T>* src = (job == 0 ? d.SM : (job == 1 ? d.SW : d.SV)) + off;
   cplx<T>* dst = (job == 0 ? d.SM : (job == 1 ? d.SW : (job == 2 ? d.SGx : d.SGy))) + off;
-  cplx<T>* P = reinterpret_cast<cplx<T>*>(smem);  // P[i1 * N + i2]
-  cplx<T>* tw = P + NN;
+  constexpr int LS = row_stride<LG>();
+  cplx<T>* P = reinterpret_cast<cplx<T>*>(smem);  // P[i1 * LS + i2]
+  cplx<T>* tw = P + N * LS;
   for (int k = threadIdx.x; k < (N >> 1); k += NT) tw[k] = d.tw[k];
-  for (int e = threadIdx.x; e < NN; e += NT) P[e] = src[e];
+  for (int e = threadIdx.x; e < NN; e += NT) P[(e >> LG) * LS + (e & (N - 1))] = src[e];
   __syncthreads();
-  line_fwd<T, LG, false, NT>(P, N, N, 1, tw);  // along i2 (rows)
-  line_fwd<T, LG, true, NT>(P, N, 1, N, tw);   // along i1 (columns)
+  line_fwd<T, LG, false, NT>(P, N, LS, 1, tw);  // along i2 (rows)
+  line_fwd<T, LG, true, NT>(P, N, 1, LS, tw);   // along i1 (columns)
   const int qz = lap_freq(kz, N);
   const T k0 = d.two_pi_over_L;
   const T D = (T)(job == 0 ? d.D_m : d.D_w);
   const T decay = (T)(job == 0 ? d.beta : 1.0);
   for (int e = threadIdx.x; e < NN; e += NT) {
     const int kx = ufpos<LG>(e >> LG), ky = ufpos<LG>(e & (N - 1));
-    cplx<T> val = P[e];
+    const int pe = (e >> LG) * LS + (e & (N - 1));
+    cplx<T> val = P[pe];
     T lp = (T)1;
     if (d.use_lowpass) {
       const T* t = d.mtab + 2 * N;
@@ -520,12 +538,12 @@ __device__ void plane_body(const SimDev<T>& d, int lb, unsigned char* smem) {
       const T kk = k0 * (T)deriv_freq(job == 2 ? kx : ky, N) * d.inv_n3 * lp;
       val = cplx<T>{-kk * val.y, kk * val.x};
     }
-    P[e] = val;
+    P[pe] = val;
   }
   __syncthreads();
-  line_inv<T, LG, true, NT>(P, N, 1, N, tw);
-  line_inv<T, LG, false, NT>(P, N, N, 1, tw);
-  for (int e = threadIdx.x; e < NN; e += NT) dst[e] = P[e];
+  line_inv<T, LG, true, NT>(P, N, 1, LS, tw);
+  line_inv<T, LG, false, NT>(P, N, LS, 1, tw);
+  for (int e = threadIdx.x; e < NN; e += NT) dst[e] = P[(e >> LG) * LS + (e & (N - 1))];
 }
 
 template <typename T, int LG>
@@ -544,10 +562,11 @@ __device__ void zinv_body(const SimDev<T>& d, int lb, unsigned char* smem) {
   const int64_t N2 = (int64_t)N * N;
   const int64_t r0 = (int64_t)lb * B;
   const int Bh = B >> 1;
+  constexpr int LS = row_stride<LG>();
   cplx<T>* MW = reinterpret_cast<cplx<T>*>(smem);  // B lines: m + i w
-  cplx<T>* GG = MW + B * N;                       // B lines: d1 v + i d2 v
-  cplx<T>* GZ = GG + B * N;                       // B/2 lines: d3 v rows 2q + i 2q+1
-  cplx<T>* tw = GZ + Bh * N;
+  cplx<T>* GG = MW + B * LS;                      // B lines: d1 v + i d2 v
+  cplx<T>* GZ = GG + B * LS;                      // B/2 lines: d3 v rows 2q + i 2q+1
+  cplx<T>* tw = GZ + Bh * LS;
   load_twiddles(tw, d);
   constexpr int H = (N >> 1) + 1;
   const T cz = d.gz_scale;  // 2 pi / L over the transforms SV went through (N or N^2)
@@ -562,19 +581,19 @@ __device__ void zinv_body(const SimDev<T>& d, int lb, unsigned char* smem) {
       const int rr = 2 * q + h;
       const int64_t o = (int64_t)kz * N2 + r0 + rr;
       const cplx<T> M = d.SM[o], W = d.SW[o], Gx = d.SGx[o], Gy = d.SGy[o], V = d.SV[o];
-      MW[rr * N + pk] = cplx<T>{M.x - W.y, M.y + W.x};
-      GG[rr * N + pk] = cplx<T>{Gx.x - Gy.y, Gx.y + Gy.x};
+      MW[rr * LS + pk] = cplx<T>{M.x - W.y, M.y + W.x};
+      GG[rr * LS + pk] = cplx<T>{Gx.x - Gy.y, Gx.y + Gy.x};
       if (mirror) {
-        MW[rr * N + pc] = cplx<T>{M.x + W.y, W.x - M.y};
-        GG[rr * N + pc] = cplx<T>{Gx.x + Gy.y, Gy.x - Gx.y};
+        MW[rr * LS + pc] = cplx<T>{M.x + W.y, W.x - M.y};
+        GG[rr * LS + pc] = cplx<T>{Gx.x + Gy.y, Gy.x - Gx.y};
       }
       gz[h] = cplx<T>{-kk * V.y, kk * V.x};
     }
-    GZ[q * N + pk] = cplx<T>{gz[0].x - gz[1].y, gz[0].y + gz[1].x};
-    if (mirror) GZ[q * N + pc] = cplx<T>{gz[0].x + gz[1].y, gz[1].x - gz[0].y};
+    GZ[q * LS + pk] = cplx<T>{gz[0].x - gz[1].y, gz[0].y + gz[1].x};
+    if (mirror) GZ[q * LS + pc] = cplx<T>{gz[0].x + gz[1].y, gz[1].x - gz[0].y};
   }
   __syncthreads();
-  line_inv<T, LG>(MW, 2 * B + Bh, N, 1, tw);
+  line_inv<T, LG>(MW, 2 * B + Bh, LS, 1, tw);
   const bool freeze_m = d.flags & SIPF_FLAG_FREEZE_M;
   const bool freeze_w = d.flags & SIPF_FLAG_FREEZE_W;
   Acc acc;
@@ -582,9 +601,9 @@ __device__ void zinv_body(const SimDev<T>& d, int lb, unsigned char* smem) {
   for (int e = threadIdx.x; e < B * N; e += kThreads) {
     const int rr = e >> LG, iz = e & (N - 1);
     const int64_t g = (r0 + rr) * N + iz;
-    const cplx<T> mw = MW[rr * N + iz];
-    const cplx<T> gg = GG[rr * N + iz];
-    const cplx<T> gzp = GZ[(rr >> 1) * N + iz];
+    const cplx<T> mw = MW[rr * LS + iz];
+    const cplx<T> gg = GG[rr * LS + iz];
+    const cplx<T> gzp = GZ[(rr >> 1) * LS + iz];
     const T wold = d.w[g];
     d.g4[g] = vec4<T>{gg.x, gg.y, (rr & 1) ? gzp.y : gzp.x, wold};
     T mn = mw.x, wn = mw.y;
@@ -615,29 +634,36 @@ __global__ void __launch_bounds__(kThreads) k_zinv(Batch<T> bt) {
 }
 
 // ---- LDS sizes and launchers ----------------------------------------------------------------
+// LDS bytes of a kernel kind at log2 N = lg (lines of the padded row stride + twiddles)
 template <typename T>
-size_t fft_lds_bytes(int kind) {
-  const size_t E = (size_t)elems_per_block<T>();
+size_t fft_lds_bytes(int kind, int lg) {
+  const int E = elems_per_block<T>();
+  const int N = 1 << lg;
+  const size_t LS = (size_t)row_stride_rt(lg);
   const size_t c = sizeof(cplx<T>);
-  const size_t tw = 256 * c;  // N/2 <= 256
+  const size_t tw = (size_t)(N / 2) * c;
+  const size_t B = (size_t)std::min(N * N, E / N);  // rows per block (z passes)
+  const size_t Bl = (size_t)(E / N);                // lines per block (y passes)
+  const size_t Bx = (size_t)std::min(N, E / N);     // columns per block (x pass)
   switch (kind) {
-    case K_ZFWD: return (E + E / 2) * c + tw;
-    case K_YFWD: return E * c + tw;
-    case K_YINV: return E * c + tw;
-    case K_XPASS: return E * c + tw;
-    case K_ZINV: return (2 * E + E / 2) * c + tw;
+    case K_ZFWD: return (B + B / 2) * LS * c + tw;
+    case K_YFWD: return Bl * LS * c + tw;
+    case K_YINV: return Bl * LS * c + tw;
+    case K_XPASS: return Bx * LS * c + tw;
+    case K_ZINV: return (2 * B + B / 2) * LS * c + tw;
+    case K_PLANE: return (size_t)N * LS * c + tw;
     default: return 0;
   }
 }
-template size_t fft_lds_bytes<double>(int);
-template size_t fft_lds_bytes<float>(int);
+template size_t fft_lds_bytes<double>(int, int);
+template size_t fft_lds_bytes<float>(int, int);
 
 // Host-side dispatch: one kernel instantiation per log2 N, so each carries only the
 // registers its own transform length needs.
 #define SIPF_LG_CASE(KER, KIND, L)                                                          \
   case L:                                                                                   \
-    hipLaunchKernelGGL((k_##KER<T, L>), dim3(nblk), dim3(kThreads), fft_lds_bytes<T>(KIND), \
-                       st, b);                                                              \
+    hipLaunchKernelGGL((k_##KER<T, L>), dim3(nblk), dim3(kThreads),                        \
+                       fft_lds_bytes<T>(KIND, L), st, b);                                   \
     break;
 #define SIPF_LAUNCH(KER, KIND)                                                     \
   template <typename T>                                                            \
@@ -666,8 +692,7 @@ SIPF_LAUNCH(zinv, K_ZINV)
 
 template <typename T>
 size_t plane_lds_bytes(int lg) {
-  const size_t N = (size_t)1 << lg;
-  return (N * N + N / 2) * sizeof(cplx<T>);
+  return fft_lds_bytes<T>(K_PLANE, lg);
 }
 
 template <typename T>

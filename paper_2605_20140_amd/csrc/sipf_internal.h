@@ -27,7 +27,7 @@ constexpr int kChunk = 4096;
 constexpr int kBinBlock = 2048;  // particles per block of the binning count kernel
 
 // Plane pass: one block of kPlaneThreads per k3 plane and job when a plane fits in LDS.
-constexpr int kPlaneThreads = 512;
+constexpr int kPlaneThreads = 1024;
 constexpr size_t kPlaneLdsMax = 150 * 1024;
 
 template <typename T>
@@ -207,6 +207,6 @@ template <typename T> void launch_finalize(const Batch<T>& b, int nsims, hipStre
 template <typename T> void launch_diag_clear(const Batch<T>& b, int nsims, hipStream_t s);
 
 // LDS bytes the FFT kernels need (host side, for launch configuration).
-template <typename T> size_t fft_lds_bytes(int kind);
+template <typename T> size_t fft_lds_bytes(int kind, int lg);
 
 }  // namespace sipf
