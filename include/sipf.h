@@ -93,7 +93,8 @@ typedef struct {
   double mass_m;         /* h^3 sum_q m_q                                                  */
   double min_v, min_m, min_w, max_m, max_w;
   double min_a, max_a;
-  double min_u;          /* min_q ubar_q                                                    */
+  double min_u;          /* min_q ubar_q (>= 0 for the trilinear assignment only: R_h^(4)   *
+                          * has negative outer weights)                                     */
   int64_t n_nan;         /* non-finite values among particles and fields                   */
   int64_t n_neg_m, n_neg_w;
   int64_t step;          /* absolute step index n of the state                             */

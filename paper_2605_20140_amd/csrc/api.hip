@@ -58,8 +58,8 @@ int validate_params(const sipf_params* p) {
     if (!(isfinite(v) && v >= 0)) return fail(SIPF_EINVAL, "model constants must be finite, >= 0");
   if (p->precision != SIPF_FP64 && p->precision != SIPF_FP32)
     return fail(SIPF_EINVAL, "precision must be SIPF_FP64 or SIPF_FP32");
-  if (p->deposit_order != 2)
-    return fail(SIPF_EINVAL, "deposit_order must be 2 (trilinear)");
+  if (p->deposit_order != 2 && p->deposit_order != 4)
+    return fail(SIPF_EINVAL, "deposit_order must be 2 (trilinear) or 4 (fourth order)");
   if ((p->flags & SIPF_FLAG_EXP_DIFFUSION) && (p->flags & SIPF_FLAG_ALIASED_DIFFUSION))
     return fail(SIPF_EINVAL, "EXP_DIFFUSION and ALIASED_DIFFUSION are exclusive");
   if (p->flags & ~0x1FFu) return fail(SIPF_EINVAL, "unknown flag bits");
@@ -181,10 +181,10 @@ void enqueue_fft(const std::vector<FftGroup<T>>& groups, hipStream_t st) {
 // reads set 1 (and writes set 0).
 template <typename T>
 void enqueue_step(const Batch<T>& b, const int* tot, int nsims,
-                  const std::vector<FftGroup<T>>& groups, int bin, hipStream_t st) {
+                  const std::vector<FftGroup<T>>& groups, int bin, int order, hipStream_t st) {
   if (bin) launch_binning<T>(b, tot, nsims, st);
   enqueue_fft<T>(groups, st);
-  launch_particles<T>(b, tot[K_PART], bin ? 1 : 0, 0, st);
+  launch_particles<T>(b, tot[K_PART], bin ? 1 : 0, 0, order, st);
   launch_finalize<T>(b, nsims, st);
 }
 
@@ -254,6 +254,7 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   d.use_plane = plane_fits<T>(lg) ? 1 : 0;
   d.gz_scale = (T)(2.0 * M_PI / p.L / (d.use_plane ? (double)N : (double)N * N));
   if (d.use_plane) launch_plane<T>(Batch<T>{}, 0, lg, nullptr, 1);  // raise its LDS limit
+  configure_particles<T>(p.deposit_order);
   d.dt = p.dt;
   d.D_u = p.D_u;
   d.chi = p.chi;
@@ -274,6 +275,7 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   d.ntile1 = N / kTile > 0 ? N / kTile : 1;
   d.ntiles = d.ntile1 * d.ntile1 * d.ntile1;
   d.use_region = N >= 2 * kTile ? 1 : 0;
+  d.deposit_order = p.deposit_order;
   for (int k = 0; k < 2; ++k) {
     d.xs[k] = reinterpret_cast<T*>(ws + L.x[k]);
     d.ys[k] = reinterpret_cast<T*>(ws + L.y[k]);
@@ -384,7 +386,7 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   }
   sim->resort_every = p.resort_every > 0 ? p.resort_every : 8;
   sim->since_bin = 0;
-  launch_particles<T>(b, sim->counts[K_PART], 0, 1, st);  // ubar^0
+  launch_particles<T>(b, sim->counts[K_PART], 0, 1, p.deposit_order, st);  // ubar^0
   launch_diag_clear<T>(b, 1, st);
   launch_diag_init<T>(b, sim->counts[K_DIAG], 1, st);
   HIPCHK(hipGetLastError());
@@ -394,12 +396,12 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   HIPCHK(hipStreamCreateWithFlags(&sim->cap, hipStreamNonBlocking));
   const auto groups = single_groups<T>(sim, b);
   HIPCHK(hipStreamBeginCapture(sim->cap, hipStreamCaptureModeThreadLocal));
-  enqueue_step<T>(b, sim->counts, 1, groups, 0, sim->cap);
+  enqueue_step<T>(b, sim->counts, 1, groups, 0, p.deposit_order, sim->cap);
   HIPCHK(hipStreamEndCapture(sim->cap, &sim->graph));
   HIPCHK(hipGetLastError());
   HIPCHK(hipGraphInstantiate(&sim->exec, sim->graph, nullptr, nullptr, 0));
   HIPCHK(hipStreamBeginCapture(sim->cap, hipStreamCaptureModeThreadLocal));
-  enqueue_step<T>(b, sim->counts, 1, groups, 1, sim->cap);
+  enqueue_step<T>(b, sim->counts, 1, groups, 1, p.deposit_order, sim->cap);
   HIPCHK(hipStreamEndCapture(sim->cap, &sim->graph_bin));
   HIPCHK(hipGetLastError());
   HIPCHK(hipGraphInstantiate(&sim->exec_bin, sim->graph_bin, nullptr, nullptr, 0));
@@ -505,7 +507,10 @@ int fields_t(sipf_sim* sim, double* v, double* m, double* w, double* X, double* 
   if (diag) *diag = dg;
   if (p.flags & SIPF_FLAG_STRICT) {
     if (dg.n_nan != 0) return fail(SIPF_EPOS, "non-finite values in the state");
-    if (dg.min_u < 0) return fail(SIPF_EPOS, "negative deposited density");
+    // the fourth-order assignment has negative outer weights, so ubar >= 0 is only an
+    // invariant of the trilinear one
+    if (p.deposit_order == 2 && dg.min_u < 0)
+      return fail(SIPF_EPOS, "negative deposited density");
     if (!(dg.min_v > 0)) return fail(SIPF_EPOS, "non-positive ECM density v");
     if (P > 0 && !(dg.min_a > 0)) return fail(SIPF_EPOS, "non-positive particle mass");
   }
@@ -661,7 +666,8 @@ int build_batch_graph(sipf_sim* const* sims, int nsims, int dev, BatchGraph** ou
   for (int bin = 0; bin < 2 && rc == SIPF_OK; ++bin) {
     chk(hipStreamBeginCapture(g_cap_stream[dev], hipStreamCaptureModeThreadLocal), "capture");
     if (rc != SIPF_OK) break;
-    enqueue_step<T>(b, tot.data(), nsims, groups, bin, g_cap_stream[dev]);
+    enqueue_step<T>(b, tot.data(), nsims, groups, bin, sims[0]->prm.deposit_order,
+                    g_cap_stream[dev]);
     chk(hipStreamEndCapture(g_cap_stream[dev], &e->graph[bin]), "hipStreamEndCapture");
     if (rc == SIPF_OK) chk(hipGetLastError(), "batched launch");
     if (rc == SIPF_OK)
@@ -749,7 +755,7 @@ int step_timed_t(sipf_sim* sim, int nsteps, float* stage_ms) {
     (void)hipEventRecord(ev[4], st);
     launch_zinv<T>(b, c[K_ZINV], lg, st);
     (void)hipEventRecord(ev[5], st);
-    launch_particles<T>(b, c[K_PART], bin, 0, st);
+    launch_particles<T>(b, c[K_PART], bin, 0, sim->prm.deposit_order, st);
     (void)hipEventRecord(ev[6], st);
     launch_finalize<T>(b, 1, st);
     (void)hipEventRecord(ev[7], st);

@@ -13,10 +13,10 @@
 // (K_h = h^3 R_h); R_h = K_h / h^3 for the deposit.  Node indices wrap modulo N.
 //
 // Particle pass: one block per (tile, chunk of <= kChunk particles).  The block stages the
-// gather array of its tile's nodes plus a kMargin-cell margin in LDS, gathers from LDS,
+// gather array of its tile's nodes plus a drift margin in LDS, gathers from LDS,
 // deposits the new state into an LDS accumulator, and flushes every non-zero accumulator
 // node to the global density with one atomic.  A particle whose stencil leaves the region
-// (it drifted more than kMargin cells since the last binning) uses global memory instead.
+// (it drifted more than a cell since the last binning) uses global memory instead.
 #include "diag_acc.h"
 
 namespace sipf {
@@ -83,27 +83,51 @@ __device__ __forceinline__ T wrap_periodic(T x, T L) {
   return x;
 }
 
-// Region of one tile: node (ox + r1, oy + r2, oz + r3), r in [0, kRegion)^3, wrapped.
+// LDS region of one tile for deposit order ORDER: the tile's kTile^3 cells, the nodes their
+// stencils reach (one more for the trilinear stencil; one before and two after for the
+// fourth-order one) and a one-cell drift margin.
+template <int ORDER>
+struct Reg {
+  static constexpr int M = ORDER == 4 ? 2 : 1;  // nodes before the tile's first node
+  static constexpr int R = kTile + 2 * M + 1;   // nodes per axis
+  static constexpr int R3 = R * R * R;
+};
+
+// Region of one tile: node (ox + r1, oy + r2, oz + r3), r in [0, R)^3, wrapped.
 struct Region {
   int o[3];
 };
 
-// Local lower-node coordinates of a stencil inside the region, or false if any of its 8
-// nodes falls outside.
-template <typename T>
+// Local lower-node coordinates of a stencil in the region; true if the trilinear stencil
+// (nodes l .. l+1 per axis) lies inside.
+template <int R, typename T>
 __device__ __forceinline__ bool in_region(const Stencil<T>& st, const Region& rg, int N,
                                           int l[3]) {
   bool ok = true;
 #pragma unroll
   for (int j = 0; j < 3; ++j) {
     l[j] = (st.c[j] - rg.o[j]) & (N - 1);
-    ok = ok && (l[j] <= kRegion - 2);
+    ok = ok && (l[j] <= R - 2);
   }
   return ok;
 }
 
+// Same for the fourth-order stencil (nodes l-1 .. l+2 per axis).
+template <int R, typename T>
+__device__ __forceinline__ bool in_region4(const Stencil<T>& st, const Region& rg, int N,
+                                           int l[3]) {
+  bool ok = true;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    l[j] = (st.c[j] - rg.o[j]) & (N - 1);
+    ok = ok && (l[j] >= 1) && (l[j] <= R - 3);
+  }
+  return ok;
+}
+
+template <int R>
 __device__ __forceinline__ int rindex(int a, int b, int c) {
-  return (a * kRegion + b) * kRegion + c;
+  return (a * R + b) * R + c;
 }
 
 template <typename T>
@@ -144,7 +168,7 @@ constexpr int kPer = kChunk / kThreads;  // particles per thread
 template <typename T> struct LoadBatch { static constexpr int n = 8; };
 template <> struct LoadBatch<double> { static constexpr int n = 4; };
 
-template <typename T>
+template <int R, typename T>
 __device__ __forceinline__ void deposit_lds(double* acc, const Stencil<T>& st, const int l[3],
                                             T q) {
   T wx[2], wy[2], wz[2];
@@ -155,13 +179,104 @@ __device__ __forceinline__ void deposit_lds(double* acc, const Stencil<T>& st, c
     for (int bb = 0; bb < 2; ++bb)
 #pragma unroll
       for (int cc = 0; cc < 2; ++cc)
-        atomicAdd(&acc[rindex(l[0] + aa, l[1] + bb, l[2] + cc)],
+        atomicAdd(&acc[rindex<R>(l[0] + aa, l[1] + bb, l[2] + cc)],
                   (double)(q * wx[aa] * wy[bb] * wz[cc]));
 }
 
+// Fourth-order assignment R_h^(4) (Sec. 2.2.1) in factored form.  With f the fractional
+// offset on one axis, the distances of nodes c-1, c, c+1, c+2 are 1+f, f, 1-f, 2-f.  Inner
+// nodes (both inner on every axis) weigh prod(1 - p) (1 + sum_j f_j (1 - f_j) / 2); a node
+// outer on exactly one axis j weighs -(1/6) (p_j - 1)(2 - p_j)(3 - p_j) prod_{k != j} (1 - p_k),
+// i.e. -(1/6) f (1-f) (2-f) at c-1 and -(1/6) f (1-f) (1+f) at c+2.  32 nodes in all.
 template <typename T>
+struct W4 {
+  T u[3][2];  // inner factors 1 - p at nodes c, c+1
+  T o[3][2];  // outer factors at nodes c-1, c+2
+  T inner;    // 1 + sum_j f_j (1 - f_j) / 2
+};
+
+template <typename T>
+__device__ __forceinline__ W4<T> weights4(const Stencil<T>& st) {
+  W4<T> w;
+  T sig = 0;
+#pragma unroll
+  for (int j = 0; j < 3; ++j) {
+    const T f = st.f[j], g = (T)1 - f, fg = f * g;
+    w.u[j][0] = g;
+    w.u[j][1] = f;
+    w.o[j][0] = -fg * ((T)2 - f) / (T)6;
+    w.o[j][1] = -fg * ((T)1 + f) / (T)6;
+    sig += fg;
+  }
+  w.inner = (T)1 + sig / (T)2;
+  return w;
+}
+
+// visit the 32 nodes: fn(d1, d2, d3, weight) with node offsets d in {-1, 0, 1, 2}
+template <typename T, typename F>
+__device__ __forceinline__ void for_r4(const W4<T>& w, F&& fn) {
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int c = 0; c < 2; ++c) fn(a, b, c, w.u[0][a] * w.u[1][b] * w.u[2][c] * w.inner);
+#pragma unroll
+  for (int o = 0; o < 2; ++o) {
+    const int dq = o ? 2 : -1;
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        fn(dq, a, b, w.o[0][o] * w.u[1][a] * w.u[2][b]);
+        fn(a, dq, b, w.o[1][o] * w.u[0][a] * w.u[2][b]);
+        fn(a, b, dq, w.o[2][o] * w.u[0][a] * w.u[1][b]);
+      }
+  }
+}
+
+template <int R, typename T>
+__device__ __forceinline__ void deposit4_lds(double* acc, const Stencil<T>& st, const int l[3],
+                                             T q) {
+  const W4<T> w = weights4(st);
+  for_r4(w, [&](int a, int b, int c, T wt) {
+    atomicAdd(&acc[rindex<R>(l[0] + a, l[1] + b, l[2] + c)], (double)(q * wt));
+  });
+}
+
+template <typename T>
+__device__ __forceinline__ void deposit4_global(T* ubar, const Stencil<T>& st, T q, int N) {
+  const W4<T> w = weights4(st);
+  for_r4(w, [&](int a, int b, int c, T wt) {
+    unsafeAtomicAdd(&ubar[node((st.c[0] + a) & (N - 1), (st.c[1] + b) & (N - 1),
+                               (st.c[2] + c) & (N - 1), N)],
+                    q * wt);
+  });
+}
+
+// deposit of one particle with the assignment of order ORDER
+template <int ORDER, int R, typename T>
+__device__ __forceinline__ void deposit_one(T* ubar, double* acc, const Stencil<T>& st,
+                                            const Region& rg, bool use_region, int N, T q) {
+  int l[3];
+  if (ORDER == 4) {
+    if (use_region && in_region4<R>(st, rg, N, l))
+      deposit4_lds<R>(acc, st, l, q);
+    else
+      deposit4_global(ubar, st, q, N);
+  } else {
+    if (use_region && in_region<R>(st, rg, N, l))
+      deposit_lds<R>(acc, st, l, q);
+    else
+      deposit_global(ubar, st, q, N);
+  }
+}
+
+template <typename T, int ORDER>
 __global__ void __launch_bounds__(kThreads) k_particles(Batch<T> bt, int src_set,
                                                         int deposit_only) {
+  constexpr int R = Reg<ORDER>::R;
+  constexpr int R3 = Reg<ORDER>::R3;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
   const int s = find_sim(bt, K_PART, lb);
@@ -175,9 +290,9 @@ __global__ void __launch_bounds__(kThreads) k_particles(Batch<T> bt, int src_set
   const int N = d.N;
   const int nt = d.ntile1;
   Region rg;
-  rg.o[0] = (tile / (nt * nt)) * kTile - kMargin;
-  rg.o[1] = ((tile / nt) % nt) * kTile - kMargin;
-  rg.o[2] = (tile % nt) * kTile - kMargin;
+  rg.o[0] = (tile / (nt * nt)) * kTile - Reg<ORDER>::M;
+  rg.o[1] = ((tile / nt) % nt) * kTile - Reg<ORDER>::M;
+  rg.o[2] = (tile % nt) * kTile - Reg<ORDER>::M;
   const bool use_region = d.use_region;
 
   const T* xi = d.xs[src_set];
@@ -206,10 +321,10 @@ __global__ void __launch_bounds__(kThreads) k_particles(Batch<T> bt, int src_set
   load_batch(0);  // in flight while the region is staged
 
   vec4<T>* gl = reinterpret_cast<vec4<T>*>(smem_raw);  // gather array of the region
-  double* acc = reinterpret_cast<double*>(gl + kRegion3);  // deposit accumulator
+  double* acc = reinterpret_cast<double*>(gl + R3);  // deposit accumulator
   if (use_region) {
-    for (int e = threadIdx.x; e < kRegion3; e += kThreads) {
-      const int rz = e % kRegion, ry = (e / kRegion) % kRegion, rx = e / (kRegion * kRegion);
+    for (int e = threadIdx.x; e < R3; e += kThreads) {
+      const int rz = e % R, ry = (e / R) % R, rx = e / (R * R);
       if (!deposit_only)
         gl[e] = d.g4[node((rg.o[0] + rx) & (N - 1), (rg.o[1] + ry) & (N - 1),
                           (rg.o[2] + rz) & (N - 1), N)];
@@ -239,11 +354,7 @@ __global__ void __launch_bounds__(kThreads) k_particles(Batch<T> bt, int src_set
       int l[3];
       if (deposit_only) {
         const Stencil<T> s0 = make_stencil(x, y, z, d.inv_h, N);
-        const T q0 = (T)a * d.inv_h3;
-        if (use_region && in_region(s0, rg, N, l))
-          deposit_lds(acc, s0, l, q0);
-        else
-          deposit_global(d.ubar, s0, q0, N);
+        deposit_one<ORDER, R>(d.ubar, acc, s0, rg, use_region, N, (T)a * d.inv_h3);
         continue;
       }
       // gather (d1 v, d2 v, d3 v, w) at the old position
@@ -251,14 +362,14 @@ __global__ void __launch_bounds__(kThreads) k_particles(Batch<T> bt, int src_set
       T wx[2], wy[2], wz[2];
       weights(st, wx, wy, wz);
       T g0 = 0, g1 = 0, g2 = 0, gw = 0;
-      if (use_region && in_region(st, rg, N, l)) {
+      if (use_region && in_region<R>(st, rg, N, l)) {
 #pragma unroll
         for (int aa = 0; aa < 2; ++aa)
 #pragma unroll
           for (int bb = 0; bb < 2; ++bb)
 #pragma unroll
             for (int cc = 0; cc < 2; ++cc) {
-              const vec4<T> q = gl[rindex(l[0] + aa, l[1] + bb, l[2] + cc)];
+              const vec4<T> q = gl[rindex<R>(l[0] + aa, l[1] + bb, l[2] + cc)];
               const T wgt = wx[aa] * wy[bb] * wz[cc];
               g0 += wgt * q.x;
               g1 += wgt * q.y;
@@ -314,20 +425,16 @@ __global__ void __launch_bounds__(kThreads) k_particles(Batch<T> bt, int src_set
 
       // deposit of the new state: ubar^{n+1}
       const Stencil<T> sn = make_stencil(xn, yn, zz, d.inv_h, N);
-      const T q = (T)an * d.inv_h3;
-      if (use_region && in_region(sn, rg, N, l))
-        deposit_lds(acc, sn, l, q);
-      else
-        deposit_global(d.ubar, sn, q, N);
+      deposit_one<ORDER, R>(d.ubar, acc, sn, rg, use_region, N, (T)an * d.inv_h3);
     }
   }
 
   if (use_region) {
     __syncthreads();
-    for (int e = threadIdx.x; e < kRegion3; e += kThreads) {
+    for (int e = threadIdx.x; e < R3; e += kThreads) {
       const double v = acc[e];
       if (v != 0.0) {
-        const int rz = e % kRegion, ry = (e / kRegion) % kRegion, rx = e / (kRegion * kRegion);
+        const int rz = e % R, ry = (e / R) % R, rx = e / (R * R);
         unsafeAtomicAdd(&d.ubar[node((rg.o[0] + rx) & (N - 1), (rg.o[1] + ry) & (N - 1),
                                      (rg.o[2] + rz) & (N - 1), N)],
                         (T)v);
@@ -494,17 +601,18 @@ __global__ void __launch_bounds__(kThreads) k_bin_scatter(Batch<T> bt) {
   d.ids[1][dst] = d.ids[0][i];
 }
 
-template <typename T>
+template <typename T, int ORDER>
 size_t particle_lds_bytes() {
-  return kRegion3 * (sizeof(vec4<T>) + sizeof(double));
+  return Reg<ORDER>::R3 * (sizeof(vec4<T>) + sizeof(double));
 }
 
 template <typename T>
-void launch_particles(const Batch<T>& b, int nblk, int src_set, int deposit_only,
+void launch_particles(const Batch<T>& b, int nblk, int src_set, int deposit_only, int order,
                       hipStream_t st) {
   if (nblk <= 0) return;
-  hipLaunchKernelGGL(k_particles<T>, dim3(nblk), dim3(kThreads), particle_lds_bytes<T>(), st, b,
-                     src_set, deposit_only);
+  auto kern = order == 4 ? k_particles<T, 4> : k_particles<T, 2>;
+  const size_t lds = order == 4 ? particle_lds_bytes<T, 4>() : particle_lds_bytes<T, 2>();
+  hipLaunchKernelGGL(kern, dim3(nblk), dim3(kThreads), lds, st, b, src_set, deposit_only);
 }
 template <typename T>
 void launch_binning(const Batch<T>& b, const int* tot, int nsims, hipStream_t st) {
@@ -514,8 +622,23 @@ void launch_binning(const Batch<T>& b, const int* tot, int nsims, hipStream_t st
   if (tot[K_SSCATTER] > 0)
     hipLaunchKernelGGL(k_bin_scatter<T>, dim3(tot[K_SSCATTER]), dim3(kThreads), 0, st, b);
 }
-template void launch_particles<double>(const Batch<double>&, int, int, int, hipStream_t);
-template void launch_particles<float>(const Batch<float>&, int, int, int, hipStream_t);
+// raise the dynamic LDS limit of the particle kernel of this order (call outside capture)
+template <typename T>
+void configure_particles(int order) {
+  if (order == 4)
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_particles<T, 4>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)particle_lds_bytes<T, 4>());
+  else
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_particles<T, 2>),
+                              hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)particle_lds_bytes<T, 2>());
+}
+template void configure_particles<double>(int);
+template void configure_particles<float>(int);
+
+template void launch_particles<double>(const Batch<double>&, int, int, int, int, hipStream_t);
+template void launch_particles<float>(const Batch<float>&, int, int, int, int, hipStream_t);
 template void launch_binning<double>(const Batch<double>&, const int*, int, hipStream_t);
 template void launch_binning<float>(const Batch<float>&, const int*, int, hipStream_t);
 

@@ -17,12 +17,9 @@ namespace sipf {
 constexpr int kThreads = 256;  // threads per block of every kernel (4 wavefronts of 64)
 
 // Particle binning: cubic tiles of kTile^3 cells; a particle kernel block handles up to
-// kChunk particles of one tile and keeps the tile's nodes plus a kMargin-cell drift margin
-// (kRegion nodes per axis) in LDS.
+// kChunk particles of one tile and keeps the tile's nodes, plus the nodes its stencils reach
+// and a drift margin, in LDS.
 constexpr int kTile = 8;
-constexpr int kMargin = 1;
-constexpr int kRegion = kTile + 2 * kMargin + 1;
-constexpr int kRegion3 = kRegion * kRegion * kRegion;
 constexpr int kChunk = 4096;
 constexpr int kBinBlock = 2048;  // particles per block of the binning count kernel
 
@@ -97,6 +94,7 @@ struct SimDev {
   int ntile1;         // tiles per axis, max(1, N / kTile)
   int ntiles;         // ntile1^3
   int use_region;     // LDS tile regions (N >= 2 kTile, so a region never aliases itself)
+  int deposit_order;  // 2: trilinear assignment; 4: fourth-order assignment
   // particles, structure of arrays; set 0 is the state, set 1 receives the binned copy
   T *xs[2], *ys[2], *zs[2];
   double* as[2];
@@ -199,7 +197,10 @@ template <typename T>
 void launch_plane(const Batch<T>& b, int nblk, int lg, hipStream_t s, int configure);
 template <typename T> bool plane_fits(int lg);
 template <typename T>
-void launch_particles(const Batch<T>& b, int nblk, int src_set, int deposit_only, hipStream_t s);
+void launch_particles(const Batch<T>& b, int nblk, int src_set, int deposit_only, int order,
+                      hipStream_t s);
+template <typename T>
+void configure_particles(int order);
 template <typename T> void launch_binning(const Batch<T>& b, const int* tot, int nsims, hipStream_t s);
 template <typename T> void launch_diag_init(const Batch<T>& b, int nblk, int nsims, hipStream_t s);
 template <typename T> void launch_diag_u(const Batch<T>& b, int nblk, int nsims, hipStream_t s);

@@ -150,3 +150,43 @@ def test_modes64_fp64_and_fp32_prefix():
         sim.close()
         errs = compare_state(out, ref, tol)
         print("modes64 precision", precision, errs)
+
+
+# ---- fourth-order assignment R_h^(4) (Sec. 2.2.1) ----
+
+@pytest.mark.parametrize("N,P", [(8, 500), (16, 4096), (32, 4096 * 3 + 77)])
+def test_init_deposit_order4_matches_oracle(N, P):
+    """N = 8 takes the global-atomic path; N >= 16 the LDS tile regions with a 2-node margin."""
+    ic = W.make_initial_state("blob16", N=N, P=P)
+    sim = gpu_sim(ic, deposit_order=4)
+    u, _ = sim.aux()
+    out = sim.fields()
+    sim.close()
+    ref = pic.deposit(ic["X0"], ic["a0"], N, 1.0, order=4)
+    assert max(rel_errors(u, ref)) < 1e-12
+    # partition of unity: h^3 sum ubar is the particle mass for either order
+    assert out["diag"]["mass_grid"] == pytest.approx(out["diag"]["mass_particles"], rel=1e-12)
+
+
+@pytest.mark.parametrize("N,P,steps", [(8, 257, 7), (16, 4096, 30), (32, 4096 + 77, 5)])
+def test_order4_steps_fp64(N, P, steps):
+    ic = W.make_initial_state("blob16", N=N, P=P)
+    sim = gpu_sim(ic, deposit_order=4)
+    sim.step(steps)
+    out = sim.fields()
+    u, _ = sim.aux()
+    sim.close()
+    prm = oracle_params(ic["params"], deposit_order=4)
+    ref = S.run(oracle_state(ic), prm, steps)
+    compare_state(out, ref, TOL64)
+    assert max(rel_errors(u, pic.deposit(ref.X, ref.a, N, 1.0, order=4))) < 1e-10
+
+
+def test_order4_fp32():
+    ic = W.make_initial_state("blob16")
+    sim = gpu_sim(ic, precision=1, deposit_order=4)
+    sim.step(50)
+    out = sim.fields()
+    sim.close()
+    ref = S.run(oracle_state(ic), oracle_params(ic["params"], deposit_order=4), 50)
+    compare_state(out, ref, TOL32)
