@@ -111,10 +111,18 @@ def make_params(name, **over):
     return prm
 
 
+def weighted_masses(P, spread, rng):
+    """Log-normal particle masses exp(spread Z), scaled to total mass 1: the unequal weights a
+    long run accumulates (Lemma mass), for resampling inputs."""
+    a = np.exp(spread * rng.standard_normal(P))
+    return a / a.sum()
+
+
 def make_initial_state(name, **over):
     """Initial state of a named workload: dict with X0 (P,3), a0 (P,), v0, m0, w0 (N,N,N).
 
-    Overrides may change N, P, dt, steps, seed, ic_seed and the physical constants.
+    Overrides may change N, P, dt, steps, seed, ic_seed and the physical constants;
+    mass_spread > 0 draws unequal (log-normal) particle masses instead of equal ones.
     """
     w = dict(WORKLOADS[name])
     w.update(over)
@@ -128,6 +136,8 @@ def make_initial_state(name, **over):
     G = blob_field(N, L, centres, sigmas)
     X0 = blob_particles(P, L, centres, sigmas, rng)
     a0 = np.full(P, 1.0 / P) if P > 0 else np.zeros(0)
+    if w.get("mass_spread") and P > 0:
+        a0 = weighted_masses(P, w["mass_spread"], rng)
     if w["ic"] == "modes":
         v0 = random_mode_field(N, L, seed=w["ic_seed"])
     else:
