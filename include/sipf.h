@@ -170,6 +170,31 @@ int sipf_aux(sipf_sim* sim, double* u_bar, double* grad_v);
 #define SIPF_STAGE_BINNING 7   /* tile binning of the particles (when due)   */
 int sipf_step_timed(sipf_sim* sim, int32_t nsteps, float* stage_ms);
 
+/* Residual resampling (Alg. res_res) of the simulation's particles at its current step n:
+ * the P weighted particles become P particles of equal mass a0 = (1/P) sum_p a_p, with
+ * k_p = floor(a_p / a0) copies of particle p (in particle order) followed by
+ * P - sum_p k_p particles drawn with probabilities proportional to the residuals
+ * a_p - k_p a0 (in draw order).  The new particle with list index i is particle i from then
+ * on (its noise stream and its place in sipf_fields' output).  Arithmetic, so that the list
+ * is a function of the state alone: the mass sum is exact and rounded once to float64;
+ * q_p = a_p / a0 and k_p = floor(q_p) in float64; the residual enters the draws as
+ * R_p = floor((q_p - k_p) 2^32); draw j takes Philox4x32-10 words (r0, r1) at counter
+ * (j, n, sim_id_lo, sim_id_hi | 2^31), key (seed_lo, seed_hi), and selects the particle whose
+ * interval of the running sum of R holds floor((r0 + 2^32 r1) sum_p R_p / 2^64) (uniformly
+ * over all P if every R_p is 0).  Positions are copied unchanged (in SIPF_FP32, the float32
+ * positions of the state).  The deposited density and the diagnostics are recomputed for
+ * the new particles; the fields and the step index are unchanged.  Synchronous; info (may be
+ * NULL) receives a0 and the two counts.  P = 0 is a no-op.
+ * Errors: SIPF_EINVAL (P >= 2^31; sim_id >= 2^63; a mass negative or not finite; total mass
+ * zero; largest mass outside [2^-775, 2^990) or a non-zero mass below 2^-160 of the largest:
+ * the state is then unchanged), SIPF_EHIP. */
+typedef struct {
+  double a0;       /* mass of every particle after resampling                              */
+  int64_t n_det;   /* particles placed by the deterministic copies                         */
+  int64_t n_stoch; /* particles drawn                                                     */
+} sipf_resample_info;
+int sipf_resample(sipf_sim* sim, sipf_resample_info* info);
+
 /* Free the host handle and the library's HIP objects (graphs, events); the workspace
  * stays the caller's.  Waits for the simulation's outstanding work.  NULL is a no-op. */
 void sipf_destroy(sipf_sim* sim);

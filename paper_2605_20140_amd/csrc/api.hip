@@ -40,6 +40,7 @@ struct Layout {
   size_t ubar, v, m, w, g4;
   size_t SM, SW, SV, SGx, SGy;
   size_t tw, mtab;
+  size_t rs;  // resampling scratch (uint64 words)
 };
 
 bool is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
@@ -122,6 +123,7 @@ Layout make_layout(const sipf_params& p) {
   L.SGy = take(spec);
   L.tw = take((N / 2) * 2 * s);
   L.mtab = take(3 * N * s);
+  L.rs = take(resample_scratch_words((int64_t)P) * 8);
   L.total = o;
   return L;
 }
@@ -779,6 +781,60 @@ int step_timed_t(sipf_sim* sim, int nsteps, float* stage_ms) {
   return rc;
 }
 
+// Residual resampling (Alg. res_res) of the current particles, then the re-binning and the
+// deposit of ubar that the new particle list needs (as at initialisation).  Synchronous.
+template <typename T>
+int resample_t(sipf_sim* sim, sipf_resample_info* info) {
+  const sipf_params& p = sim->prm;
+  const SimDev<T>& d = *reinterpret_cast<const SimDev<T>*>(sim->host_desc);
+  const int64_t P = p.P;
+  sipf_resample_info out{0.0, 0, 0};
+  if (P == 0) {
+    if (info) *info = out;
+    return SIPF_OK;
+  }
+  hipStream_t st = sim->stream;
+  unsigned long long* rs = reinterpret_cast<unsigned long long*>(sim->ws + sim->lay.rs);
+  unsigned long long head[RS_BLOCKS];
+  HIPCHK(hipMemsetAsync(rs, 0, sizeof(head), st));
+  launch_resample_stats<T>(d, rs, st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(head, rs, sizeof(head), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  // on a rejected input the state is unchanged (only set 1, free between steps, was written)
+  if (head[RS_FLAGS] & RS_BAD_VALUE)
+    return fail(SIPF_EINVAL, "resampling needs finite, non-negative masses with a positive sum");
+  if (head[RS_FLAGS] & RS_BAD_RANGE)
+    return fail(SIPF_EINVAL,
+                "resampling needs the largest mass in [2^-775, 2^990) and every non-zero mass "
+                "above 2^-160 of the largest");
+  launch_resample_apply<T>(d, rs, st);
+  // re-bin the new list (set 0 -> set 1 by tile, back into set 0) and deposit its ubar
+  const Batch<T> b = single_batch<T>(sim);
+  launch_binning<T>(b, sim->counts, 1, st);
+  HIPCHK(hipMemcpyAsync(d.xs[0], d.xs[1], P * sizeof(T), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(d.ys[0], d.ys[1], P * sizeof(T), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(d.zs[0], d.zs[1], P * sizeof(T), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(d.as[0], d.as[1], P * sizeof(double), hipMemcpyDeviceToDevice, st));
+  HIPCHK(hipMemcpyAsync(d.ids[0], d.ids[1], P * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
+  const size_t G = (size_t)p.N * p.N * p.N;
+  HIPCHK(hipMemsetAsync(d.ubar, 0, G * sizeof(T), st));
+  launch_particles<T>(b, sim->counts[K_PART], 0, 1, p.deposit_order, st);
+  launch_diag_clear<T>(b, 1, st);
+  launch_diag_init<T>(b, sim->counts[K_DIAG], 1, st);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(head, rs, sizeof(head), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  sim->since_bin = 0;
+  double a0;
+  memcpy(&a0, &head[RS_A0], sizeof(a0));
+  out.a0 = a0;
+  out.n_det = (int64_t)std::min<unsigned long long>(head[RS_KTOT], (unsigned long long)P);
+  out.n_stoch = P - out.n_det;
+  if (info) *info = out;
+  return SIPF_OK;
+}
+
 // Work on the simulation's own stream after batched steps on another stream waits for them.
 int order_after_batch(sipf_sim* sim) {
   if (sim->last_stream && sim->last_stream != sim->stream) {
@@ -802,6 +858,17 @@ int sipf_step_timed(sipf_sim* sim, int32_t nsteps, float* stage_ms) {
                                          : step_timed_t<float>(sim, nsteps, stage_ms);
 }
 
+
+int sipf_resample(sipf_sim* sim, sipf_resample_info* info) {
+  if (!sim) return fail(SIPF_EINVAL, "sim is NULL");
+  if (sim->prm.P >= (int64_t(1) << 31)) return fail(SIPF_EINVAL, "resampling needs P < 2^31");
+  if (sim->prm.sim_id >> 63) return fail(SIPF_EINVAL, "resampling needs sim_id < 2^63");
+  int rc = order_after_batch(sim);
+  if (rc) return rc;
+  if (sim->last_stream) HIPCHK(hipStreamSynchronize(sim->last_stream));
+  return sim->prm.precision == SIPF_FP64 ? resample_t<double>(sim, info)
+                                         : resample_t<float>(sim, info);
+}
 
 int sipf_state_bytes(const sipf_params* prm, size_t* bytes) {
   int rc = validate_params(prm);

@@ -201,6 +201,28 @@ void launch_particles(const Batch<T>& b, int nblk, int src_set, int deposit_only
                       hipStream_t s);
 template <typename T>
 void configure_particles(int order);
+
+// ---- residual resampling (resample.hip) ---------------------------------------------------
+// words (uint64) at the start of the resampling scratch area
+enum RsWord {
+  RS_MAXBITS = 0,  // bit pattern of the largest mass (non-negative doubles order as integers)
+  RS_FLAGS = 1,    // RS_BAD_* bits
+  RS_DIGITS = 2,   // 8 words: fixed-point sum of the masses
+  RS_A0 = 10,      // bit pattern of a0
+  RS_KTOT = 11,    // sum_p k_p
+  RS_RTOT = 12,    // sum_p R_p
+  RS_BLOCKS = 16,  // (sum k, sum R) per scan block, then their exclusive prefix
+};
+constexpr unsigned long long RS_BAD_VALUE = 1;  // a mass that is negative or not finite
+constexpr unsigned long long RS_BAD_RANGE = 2;  // masses beyond the exact sum's range
+size_t resample_scratch_words(int64_t P);
+// largest mass, exact sum and a0 (reads set 0, leaves set 0 untouched; set 1 := set 0 in
+// particle order); scratch words 0 .. RS_BLOCKS - 1 must be zero on entry
+template <typename T>
+void launch_resample_stats(const SimDev<T>& d, unsigned long long* rs, hipStream_t s);
+// copy counts, prefix sums and the resampled list into set 0 (particle order)
+template <typename T>
+void launch_resample_apply(const SimDev<T>& d, unsigned long long* rs, hipStream_t s);
 template <typename T> void launch_binning(const Batch<T>& b, const int* tot, int nsims, hipStream_t s);
 template <typename T> void launch_diag_init(const Batch<T>& b, int nblk, int nsims, hipStream_t s);
 template <typename T> void launch_diag_u(const Batch<T>& b, int nblk, int nsims, hipStream_t s);

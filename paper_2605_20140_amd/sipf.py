@@ -29,7 +29,8 @@ ERRORS = {-1: "SIPF_EINVAL", -2: "SIPF_ENOMEM", -3: "SIPF_EHIP", -4: "SIPF_EPOS"
 
 # exported symbols, as declared in include/sipf.h
 EXPORTS = ("sipf_state_bytes", "sipf_init", "sipf_step", "sipf_set_stream", "sipf_step_batch",
-           "sipf_fields", "sipf_aux", "sipf_step_timed", "sipf_destroy", "sipf_last_error")
+           "sipf_fields", "sipf_aux", "sipf_step_timed", "sipf_resample", "sipf_destroy",
+           "sipf_last_error")
 STAGES = ("zfwd", "yfwd", "xpass", "yinv", "zinv", "particles", "finalize", "binning")
 
 
@@ -61,6 +62,10 @@ class Diag(ctypes.Structure):
         return {name: getattr(self, name) for name, _ in self._fields_}
 
 
+class ResampleInfo(ctypes.Structure):
+    _fields_ = [("a0", ctypes.c_double), ("n_det", ctypes.c_int64), ("n_stoch", ctypes.c_int64)]
+
+
 class SipfError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"{ERRORS.get(code, code)}: {msg}")
@@ -88,11 +93,13 @@ def lib():
         L.sipf_fields.argtypes = [vp, dp, dp, dp, dp, dp, ctypes.POINTER(Diag)]
         L.sipf_aux.argtypes = [vp, dp, dp]
         L.sipf_step_timed.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_float)]
+        L.sipf_resample.argtypes = [vp, ctypes.POINTER(ResampleInfo)]
         L.sipf_destroy.argtypes = [vp]
         L.sipf_destroy.restype = None
         L.sipf_last_error.restype = ctypes.c_char_p
         for name in ("sipf_state_bytes", "sipf_init", "sipf_step", "sipf_step_batch",
-                     "sipf_fields", "sipf_aux", "sipf_step_timed", "sipf_set_stream"):
+                     "sipf_fields", "sipf_aux", "sipf_step_timed", "sipf_set_stream",
+                     "sipf_resample"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -190,6 +197,12 @@ class Simulation:
         buf = (ctypes.c_float * len(STAGES))()
         _check(lib().sipf_step_timed(self.handle, int(nsteps), buf))
         return dict(zip(STAGES, list(buf)))
+
+    def resample(self):
+        """Residual resampling of the particles (synchronous); returns a0, n_det, n_stoch."""
+        info = ResampleInfo()
+        _check(lib().sipf_resample(self.handle, ctypes.byref(info)))
+        return dict(a0=info.a0, n_det=info.n_det, n_stoch=info.n_stoch)
 
     def close(self):
         if getattr(self, "handle", None):
