@@ -38,7 +38,7 @@ struct Layout {
   size_t x[2], y[2], z[2], a[2], id[2];
   size_t tcount, toff, coff, ctile, key;
   size_t ubar, v, m, w, g4;
-  size_t SM, SW, SV, SGx, SGy;
+  size_t SM, SW, SV, SGx, SGy, SVf;
   size_t tw, mtab;
   size_t rs;  // resampling scratch (uint64 words)
 };
@@ -64,8 +64,8 @@ int validate_params(const sipf_params* p) {
   if ((p->flags & SIPF_FLAG_EXP_DIFFUSION) && (p->flags & SIPF_FLAG_ALIASED_DIFFUSION))
     return fail(SIPF_EINVAL, "EXP_DIFFUSION and ALIASED_DIFFUSION are exclusive");
   if (p->flags & ~0x1FFu) return fail(SIPF_EINVAL, "unknown flag bits");
-  if (!(isfinite(p->H0) && p->H0 == 0.0))
-    return fail(SIPF_EINVAL, "the low-pass filter (H0 > 0) is not available; use H0 = 0");
+  if (!(isfinite(p->H0) && p->H0 >= 0.0))
+    return fail(SIPF_EINVAL, "H0 must be finite and >= 0 (0: no low-pass filter)");
   if (p->resort_every < 0) return fail(SIPF_EINVAL, "resort_every must be >= 0");
   if (p->flags & SIPF_FLAG_ALIASED_DIFFUSION) {
     // The aliased multiplier is the DFT of the heat kernel sampled at the nodes (Lemma
@@ -121,6 +121,7 @@ Layout make_layout(const sipf_params& p) {
   L.SV = take(spec);
   L.SGx = take(spec);
   L.SGy = take(spec);
+  L.SVf = take(p.H0 > 0 ? spec : 0);  // low-pass filtered V
   L.tw = take((N / 2) * 2 * s);
   L.mtab = take(3 * N * s);
   L.rs = take(resample_scratch_words((int64_t)P) * 8);
@@ -301,6 +302,7 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   d.SV = reinterpret_cast<cplx<T>*>(ws + L.SV);
   d.SGx = reinterpret_cast<cplx<T>*>(ws + L.SGx);
   d.SGy = reinterpret_cast<cplx<T>*>(ws + L.SGy);
+  d.SVg = p.H0 > 0 ? reinterpret_cast<cplx<T>*>(ws + L.SVf) : d.SV;
   d.tw = reinterpret_cast<cplx<T>*>(ws + L.tw);
   d.mtab = reinterpret_cast<T*>(ws + L.mtab);
   d.step = reinterpret_cast<uint64_t*>(ws + L.step);
@@ -351,6 +353,12 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
     for (int f = 0; f < 2; ++f) {
       axis_tables(p, f, t);
       for (int k = 0; k < N; ++k) hmt[f * N + k] = (T)t[k];
+    }
+  }
+  if (p.H0 > 0) {  // low-pass factor per axis: exp(-2 pi^2 q^2 / H0^2)
+    for (int k = 0; k < N; ++k) {
+      const double q = k < N / 2 ? k : k - N;
+      hmt[2 * N + k] = (T)exp(-2.0 * M_PI * M_PI * q * q / (p.H0 * p.H0));
     }
   }
   const uint64_t step0 = p.step0;

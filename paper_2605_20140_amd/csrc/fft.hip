@@ -16,10 +16,14 @@
 //   xpass: x transforms, the diagonal multipliers of eq. k_q_tilde_update (m: decay beta,
 //          diffusion D_m; w: decay 1, diffusion D_w) and the x-derivative multiplier of
 //          eq. gradv (i (2 pi/L) q_1, Nyquist zeroed), inverse x transforms -> SM, SW, SGx.
-//   yinv : inverse y transforms of SM, SW, SGx, and of SV together with the y-derivative
-//          spectrum SGy = i (2 pi/L) q_2 SV.  SV is transformed along y and z only (x stays
+//          With the low-pass filter exp(-2 pi^2 |q|^2 / H0^2) (Alg. p2g text, Alg. sipf-pic)
+//          the filter multiplies the m, w and d1 v spectra, and a fourth job writes the
+//          filtered V (x round trip undone) into a buffer of its own, SVg; without it SVg
+//          is SV itself.
+//   yinv : inverse y transforms of SM, SW, SGx, and of SVg together with the y-derivative
+//          spectrum SGy = i (2 pi/L) q_2 SVg.  SVg is transformed along y and z only (x stays
 //          in physical space), so the derivatives formed from it carry 1/N^2.
-//   zinv : forms the z-derivative spectrum i (2 pi/L) q_3 SV, inverse real z transforms of
+//   zinv : forms the z-derivative spectrum i (2 pi/L) q_3 SVg, inverse real z transforms of
 //          (SM, SW), (SGx, SGy) and of row pairs of the z derivative; writes m^{n+1},
 //          w^{n+1} and the gather array g4 = (d1 v^n, d2 v^n, d3 v^n, w^n).
 //
@@ -49,9 +53,10 @@ void block_counts(const SimDev<T>& d, int c[K_COUNT]) {
   const int64_t ny2 = (lines + Bl / 2 - 1) / (Bl / 2);
   c[K_ZFWD] = (int)(N * N / d.rows_per_blk);
   c[K_YFWD] = d.use_plane ? 0 : (int)(3 * ny);
-  c[K_XPASS] = d.use_plane ? 0 : (int)(3 * H * (N / d.cols_per_blk));
+  const int64_t nlp = d.use_lowpass ? 1 : 0;  // filtered copy of V as an extra job
+  c[K_XPASS] = d.use_plane ? 0 : (int)((3 + nlp) * H * (N / d.cols_per_blk));
   c[K_YINV] = d.use_plane ? 0 : (int)(3 * ny + ny2);
-  c[K_PLANE] = d.use_plane ? (int)(4 * H) : 0;
+  c[K_PLANE] = d.use_plane ? (int)((4 + nlp) * H) : 0;
   c[K_ZINV] = c[K_ZFWD];
   const int64_t pb = (d.P + kThreads - 1) / kThreads;
   c[K_PART] = d.max_chunks;  // bound on the number of (tile, chunk) items
@@ -383,7 +388,7 @@ __device__ void yinv_body(const SimDev<T>& d, int lb, unsigned char* smem) {
     const int Bh = Bl >> 1;
     const int64_t l0 = (int64_t)(lb - 3 * nb1) * Bh;
     const int nl = (int)((lines - l0) < Bh ? (lines - l0) : Bh);
-    const cplx<T>* SV = d.SV + l0 * N;
+    const cplx<T>* SV = d.SVg + l0 * N;
     const T c = d.two_pi_over_L * d.inv_n2;
     for (int e = threadIdx.x; e < nl * N; e += kThreads) {
       const int line = e >> LG, p = e & (N - 1);
@@ -394,7 +399,7 @@ __device__ void yinv_body(const SimDev<T>& d, int lb, unsigned char* smem) {
     }
     __syncthreads();
     line_inv<T, LG>(buf, 2 * nl, LS, 1, tw);
-    cplx<T>* dV = d.SV + l0 * N;
+    cplx<T>* dV = d.SVg + l0 * N;
     cplx<T>* dG = d.SGy + l0 * N;
     for (int e = threadIdx.x; e < nl * N; e += kThreads) {
       const int line = e >> LG, j = e & (N - 1);
@@ -426,7 +431,7 @@ __device__ void xpass_body(const SimDev<T>& d, int lb, unsigned char* smem) {
   const int y0 = (rem - kz * ncb) * Bx;
   const int64_t N2 = (int64_t)N * N;
   const cplx<T>* src = (f == 0 ? d.SM : (f == 1 ? d.SW : d.SV)) + (int64_t)kz * N2;
-  cplx<T>* dst = (f == 0 ? d.SM : (f == 1 ? d.SW : d.SGx)) + (int64_t)kz * N2;
+  cplx<T>* dst = (f == 0 ? d.SM : (f == 1 ? d.SW : (f == 2 ? d.SGx : d.SVg))) + (int64_t)kz * N2;
   constexpr int LS = row_stride<LG>();
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);  // Bx lines of N along i1
   cplx<T>* tw = buf + Bx * LS;
@@ -462,13 +467,17 @@ __device__ void xpass_body(const SimDev<T>& d, int lb, unsigned char* smem) {
         mult *= lp[kx] * lp[ky] * lp[kz];
       }
       val = cscale(val, mult);
-    } else {
+    } else if (f == 2) {
       T kk = k0 * (T)deriv_freq(kx, N) * d.inv_n3;
       if (d.use_lowpass) {
         const T* lp = d.mtab + 2 * N;
         kk *= lp[kx] * lp[ky] * lp[kz];
       }
       val = cplx<T>{-kk * val.y, kk * val.x};
+    } else {
+      // low-pass filtered V for the y and z derivatives; 1/N undoes this x round trip
+      const T* lp = d.mtab + 2 * N;
+      val = cscale(val, lp[kx] * lp[ky] * lp[kz] / (T)N);
     }
     buf[c * LS + p] = val;
   }
@@ -492,16 +501,21 @@ __global__ void __launch_bounds__(kThreads) k_xpass(Batch<T> bt) {
 // Replaces yfwd + xpass + yinv when a k3 plane of a half spectrum (N^2 complex values,
 // contiguous in the S[k3][i1][i2] layout) fits in LDS.  Four jobs per plane: M, W (diffusion
 // multipliers), and from V the x- and y-derivative spectra.  V itself is not written: it
-// stays transformed along z only, and zinv forms the z derivative from it (scale 1/N).
+// stays transformed along z only, and zinv forms the z derivative from it (scale 1/N).  With
+// the low-pass filter a fifth job writes the filtered V plane (x, y round trip undone) into
+// SVg, from which zinv then forms the z derivative.
 template <typename T, int LG>
 __device__ void plane_body(const SimDev<T>& d, int lb, unsigned char* smem) {
   constexpr int N = 1 << LG;
   constexpr int NN = N * N;
   constexpr int NT = kPlaneThreads;
-  const int job = lb & 3, kz = lb >> 2;
+  const int nj = d.use_lowpass ? 5 : 4;
+  const int kz = lb / nj, job = lb - kz * nj;
   const int64_t off = (int64_t)kz * NN;
   const cplx<T>* src = (job == 0 ? d.SM : (job == 1 ? d.SW : d.SV)) + off;
-  cplx<T>* dst = (job == 0 ? d.SM : (job == 1 ? d.SW : (job == 2 ? d.SGx : d.SGy))) + off;
+  cplx<T>* dst =
+      (job == 0 ? d.SM : (job == 1 ? d.SW : (job == 2 ? d.SGx : (job == 3 ? d.SGy : d.SVg)))) +
+      off;
   constexpr int LS = row_stride<LG>();
   cplx<T>* P = reinterpret_cast<cplx<T>*>(smem);  // P[i1 * LS + i2]
   cplx<T>* tw = P + N * LS;
@@ -534,9 +548,12 @@ __device__ void plane_body(const SimDev<T>& d, int lb, unsigned char* smem) {
         mult = (T)exp(-(T)d.dt * decay) * tab[kx] * tab[ky] * tab[kz];
       }
       val = cscale(val, mult * d.inv_n3 * lp);
-    } else {
+    } else if (job < 4) {
       const T kk = k0 * (T)deriv_freq(job == 2 ? kx : ky, N) * d.inv_n3 * lp;
       val = cplx<T>{-kk * val.y, kk * val.x};
+    } else {
+      // low-pass filtered V for the z derivative; 1/N^2 undoes this x, y round trip
+      val = cscale(val, lp * d.inv_n2);
     }
     P[pe] = val;
   }
@@ -580,7 +597,7 @@ __device__ void zinv_body(const SimDev<T>& d, int lb, unsigned char* smem) {
     for (int h = 0; h < 2; ++h) {
       const int rr = 2 * q + h;
       const int64_t o = (int64_t)kz * N2 + r0 + rr;
-      const cplx<T> M = d.SM[o], W = d.SW[o], Gx = d.SGx[o], Gy = d.SGy[o], V = d.SV[o];
+      const cplx<T> M = d.SM[o], W = d.SW[o], Gx = d.SGx[o], Gy = d.SGy[o], V = d.SVg[o];
       MW[rr * LS + pk] = cplx<T>{M.x - W.y, M.y + W.x};
       GG[rr * LS + pk] = cplx<T>{Gx.x - Gy.y, Gx.y + Gy.x};
       if (mirror) {

@@ -111,6 +111,8 @@ struct SimDev {
   vec4<T>* g4;        // gather field per node: (d1 v, d2 v, d3 v, w^n)
   // spectra, half-spectrum layout S[k3][i1][i2], k3 in [0, N/2]
   cplx<T> *SM, *SW, *SV, *SGx, *SGy;
+  cplx<T>* SVg;       // V spectrum the y and z derivatives are formed from: SV, or with the
+                      // low-pass filter its filtered copy (a sixth spectrum buffer)
   cplx<T>* tw;        // exp(-2 pi i k / N), k < N/2
   T* mtab;            // separable multiplier tables: [field m | field w | lowpass] x N each
   uint64_t* step;     // absolute step index n (device-resident, advanced once per step)

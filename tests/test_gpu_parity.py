@@ -190,3 +190,29 @@ def test_order4_fp32():
     sim.close()
     ref = S.run(oracle_state(ic), oracle_params(ic["params"], deposit_order=4), 50)
     compare_state(out, ref, TOL32)
+
+
+# ---- low-pass filter exp(-2 pi^2 |q|^2 / H0^2) (Alg. p2g text, Alg. sipf-pic) ----
+
+@pytest.mark.parametrize("N,P,steps,precision", [(16, 4096, 20, 0), (64, 30000, 3, 0),
+                                                 (128, 20000, 2, 0), (32, 4096, 20, 1)])
+def test_lowpass_filter(N, P, steps, precision):
+    """N <= 64 (float64) and N <= 128 (float32) take the plane kernel; N = 128 in float64 the
+    three-pass path."""
+    ic = W.make_initial_state("modes64", N=N, P=P)
+    H0 = N / 2
+    sim = gpu_sim(ic, precision=precision, H0=H0)
+    sim.step(steps)
+    out = sim.fields()
+    _, g = sim.aux()
+    sim.close()
+    prm = oracle_params(ic["params"], H0=H0)
+    ref, aux = None, None
+    st = oracle_state(ic)
+    for _ in range(steps):
+        ref, aux = S.step(st, prm, return_aux=True)
+        st = ref
+    compare_state(out, ref, TOL64 if precision == 0 else TOL32)
+    if precision == 0:
+        for j in range(3):
+            assert max(rel_errors(g[j], aux["grad"][j])) < 1e-11, j
