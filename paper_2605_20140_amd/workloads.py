@@ -179,3 +179,38 @@ def served_initial_state(req, nblobs=4):
     prm.update(N=N, P=P, dt=req["dt"], chi=req["chi"], seed=req["seed"], steps=req["steps"])
     return dict(params=prm, X0=X0, a0=np.full(P, 1.0 / P), v0=1.0 - 0.5 * G, m0=0.5 * G,
                 w0=np.ones((N, N, N)))
+
+
+# ---- the paper's three-dimensional example (Sec. numerical experiments, 3D simulation) ----
+# Periodic cube [0, 6]^3; u0 = 3 on the ball |x - (3,3,3)| <= sqrt(0.3), m0 = u0,
+# v0 = 0.05 cos(5 pi x1^2 / 18) sin(13 pi x2^2 / 72) cos(pi x3^2 / 12) + 0.3, w0 = 4 v0;
+# chi = 0.4, D_u = D_m = D_w = 0.01, alpha = 5, beta = 0.01, gamma = 5; tau = 1e-3 to T = 6
+# (6000 steps); P = 2^22 particles.
+PAPER3D_PARAMS = dict(L=6.0, D_u=0.01, chi=0.4, D_m=0.01, D_w=0.01, alpha=5.0, beta=0.01,
+                      gamma=5.0, dt=1e-3, steps=6000, seed=21)
+PAPER3D_BALL = dict(centre=(3.0, 3.0, 3.0), radius=math.sqrt(0.3), height=3.0)
+
+
+def paper3d_initial_state(N, P=1 << 22, ic_seed=21, **over):
+    """Initial state of the paper's 3D example on an N^3 grid: particles i.i.d. uniform in the
+    ball (the normalised u0), equal masses 3 |ball| / P; fields sampled at the nodes."""
+    prm = dict(PAPER3D_PARAMS)
+    prm.update(over)
+    prm.update(N=N, P=P)
+    L = prm["L"]
+    c = np.asarray(PAPER3D_BALL["centre"])
+    r0 = PAPER3D_BALL["radius"]
+    rng = _rng(ic_seed)
+    d = rng.standard_normal((P, 3))
+    d /= np.linalg.norm(d, axis=1)[:, None]
+    r = r0 * rng.random(P) ** (1.0 / 3.0)
+    X0 = _wrap_unit(c + r[:, None] * d, L)
+    mass = PAPER3D_BALL["height"] * 4.0 / 3.0 * math.pi * r0 ** 3
+    a0 = np.full(P, mass / P) if P > 0 else np.zeros(0)
+    x = np.arange(N) * (L / N)
+    X1, X2, X3 = np.meshgrid(x, x, x, indexing="ij")
+    inside = (X1 - c[0]) ** 2 + (X2 - c[1]) ** 2 + (X3 - c[2]) ** 2 <= r0 * r0
+    m0 = np.where(inside, PAPER3D_BALL["height"], 0.0)
+    v0 = (0.05 * np.cos(5.0 * math.pi * X1 ** 2 / 18.0) * np.sin(13.0 * math.pi * X2 ** 2 / 72.0)
+          * np.cos(math.pi * X3 ** 2 / 12.0) + 0.3)
+    return dict(params=prm, X0=X0, a0=a0, v0=v0, m0=m0, w0=4.0 * v0)
