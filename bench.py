@@ -11,6 +11,8 @@ resident in HBM before the timed region; the timed region replays the captured s
 Prints one JSON line.  `python bench.py --gpus N --steps K --warmup W`.
 """
 import argparse
+import ctypes
+import hashlib
 import json
 import os
 import sys
@@ -34,8 +36,8 @@ def stage_bytes(N, P, s):
         "xpass": 6 * half,
         "yinv": 9 * half,
         "zinv": 5 * half + G * s + G * 6 * s,
-        # particles: read x,y,z,a; write x,y,z,a (SURVEY per-particle figure; the 4-byte
-        # noise key is not counted) + gather array read once + deposit target written once
+        # particles: read x,y,z,a; write x,y,z,a (the 4-byte particle index that keys the
+        # noise is not counted) + gather array read once + deposit target written once
         "particles": P * (6 * s + 16) + G * 5 * s,
         "finalize": 0,
         # binning, per binning: count reads x,y,z and writes (tile, rank); scatter reads the
@@ -46,8 +48,61 @@ def stage_bytes(N, P, s):
 
 RESORT_EVERY = 8  # library default binning period
 
+# Kernel behind each stage (the roofline names the dominant one) and the sources it is built
+# from: a byte-counter summary under profiles/ only applies while these are unchanged.
+STAGE_KERNEL = {"particles": ("k_particles<float, 2>", "k_particles<double, 2>"),
+                "xpass": ("k_plane<float, 7>", "k_xpass<double, 7>")}
+KERNEL_SOURCES = ("paper_2605_20140_amd/csrc/particles.hip",
+                  "paper_2605_20140_amd/csrc/sipf_internal.h",
+                  "paper_2605_20140_amd/csrc/diag_acc.h")
+COPY_CAL_BYTES = 512 << 20
 
-def run_form(ic, precision, steps, warmup, profile_steps):
+
+def sources_digest():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload, precision):
+    """HBM bytes per launch of the particle kernel from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, each divided by what the counter read for a device
+    copy of COPY_CAL_BYTES), or None if there is none or the kernel changed since."""
+    path = os.path.join(ROOT, "profiles", f"pmc_traffic_particles_{workload}.txt")
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("#") or "=" not in line:
+                continue
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    if kv.get("sources_digest") != sources_digest():
+        return None
+    key = "traffic_bytes_fp32" if precision == 1 else "traffic_bytes_fp64"
+    return float(kv[key]) if key in kv else None
+
+
+def copy_calibration():
+    """One device-to-device copy of COPY_CAL_BYTES (a blit kernel of known size: the
+    reference the byte counters are scaled by)."""
+    import torch
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                                   ctypes.c_int, ctypes.c_void_p]
+    src = torch.ones(COPY_CAL_BYTES // 4, dtype=torch.float32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    st = torch.cuda.current_stream().cuda_stream
+    rc = hip.hipMemcpyAsync(dst.data_ptr(), src.data_ptr(), COPY_CAL_BYTES, 3, st)
+    torch.cuda.synchronize()
+    assert rc == 0 and bool((dst == 1).all())
+
+
+def run_form(ic, precision, steps, warmup, profile_steps, workload):
     import torch
     from paper_2605_20140_amd import sipf
     prm = ic["params"]
@@ -79,14 +134,17 @@ def run_form(ic, precision, steps, warmup, profile_steps):
                          GBs=round(nbytes / (avg * 1e-3) / 1e9, 1) if avg > 0 and nbytes else None)
     dominant = max(stages, key=lambda k: stages[k]["ms"])
     ach = sb[dominant] / (stages[dominant]["ms"] * 1e-3) / 1e9
+    kname = STAGE_KERNEL.get(dominant, (dominant, dominant))[0 if precision == 1 else 1]
+    traffic = measured_traffic(workload, precision) if dominant == "particles" else None
     return dict(
         value=prm["P"] * steps / (ms * 1e-3),
         ms_per_step=ms / steps,
         wall_ms_per_step=wall * 1e3 / steps,
         stages=stages,
-        roofline=dict(bound="hbm", kernel=dominant, achieved=round(ach, 1), peak=HBM_PEAK_GBS,
-                      unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4), traffic=None,
-                      algorithmic_bytes=sb[dominant]),
+        roofline=dict(bound="hbm", kernel=kname, achieved=round(ach, 1), peak=HBM_PEAK_GBS,
+                      unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4), traffic=traffic,
+                      algorithmic_bytes=sb[dominant],
+                      avg_launch_ms=stages[dominant]["ms"]),
         check=dict(n_nan=d["n_nan"], step=d["step"],
                    mass_rel_gap=abs(d["mass_grid"] / d["mass_particles"] - 1.0)),
     )
@@ -147,11 +205,12 @@ def main():
     ap.add_argument("--served-requests", type=int, default=48,
                     help="requests in the served-mix run (0: skip it)")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="also run one device copy of 512 MiB (reference for byte counters)")
+                    help="also run one device-to-device copy of 512 MiB (the reference "
+                         "the byte counters are scaled by)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): this build has no "
-              "multi-GPU path; the sharding design is described in DESIGN.md.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}): the library has no "
+              "multi-GPU path.", file=sys.stderr)
         sys.exit(2)
     import torch
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -159,15 +218,11 @@ def main():
     from paper_2605_20140_amd import workloads as W
     ic = W.make_initial_state(args.workload)
     prm = ic["params"]
-    r32 = run_form(ic, 1, args.steps, args.warmup, args.profile_steps)
-    r64 = None if args.no_fp64 else run_form(ic, 0, args.steps, args.warmup, args.profile_steps)
+    r32 = run_form(ic, 1, args.steps, args.warmup, args.profile_steps, args.workload)
+    r64 = (None if args.no_fp64 else
+           run_form(ic, 0, args.steps, args.warmup, args.profile_steps, args.workload))
     if args.copy_calibration:
-        src = torch.empty(512 << 20, dtype=torch.uint8, device="cuda:0").fill_(1)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+        copy_calibration()
     srv = served(args.served_requests, 32) if args.served_requests > 0 else None
     cpu = None if args.no_cpu_baseline else cpu_baseline(ic)
     line = {
