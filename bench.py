@@ -107,7 +107,11 @@ def run_form(ic, precision, steps, warmup, profile_steps, workload):
     from paper_2605_20140_amd import sipf
     prm = ic["params"]
     p = sipf.make_params(precision=precision, **prm)
+    torch.cuda.synchronize()
+    ti = time.perf_counter()
     sim = sipf.Simulation(p, ic["X0"], ic["a0"], ic["v0"], ic["m0"], ic["w0"], device="cuda:0")
+    torch.cuda.synchronize()
+    init_s = time.perf_counter() - ti
     stream = torch.cuda.current_stream()
     sim.step(warmup)
     torch.cuda.synchronize()
@@ -140,6 +144,7 @@ def run_form(ic, precision, steps, warmup, profile_steps, workload):
         value=prm["P"] * steps / (ms * 1e-3),
         ms_per_step=ms / steps,
         wall_ms_per_step=wall * 1e3 / steps,
+        init_s=init_s,
         stages=stages,
         roofline=dict(bound="hbm", kernel=kname, achieved=round(ach, 1), peak=HBM_PEAK_GBS,
                       unit="GB/s", frac=round(ach / HBM_PEAK_GBS, 4), traffic=traffic,
@@ -243,11 +248,13 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": r32["roofline"],
         "cpu_baseline": cpu,
+        "init_s": r32["init_s"],
         "stages": r32["stages"],
         "check": r32["check"],
         "served": srv,
         "fp64": None if r64 is None else {
             "value": r64["value"], "ms_per_step": r64["ms_per_step"], "dtype": "f64",
+            "init_s": r64["init_s"],
             "roofline": r64["roofline"], "stages": r64["stages"], "check": r64["check"]},
     }
     print(json.dumps(line), flush=True)
