@@ -1,11 +1,12 @@
 """Particle-in-cell transfers (oracle side; test infrastructure only).
 
-Grid: N nodes per axis on the periodic cube [0, L)^3, node q = (q1, q2, q3) at position q*h,
-h = L/N.  Grid arrays are indexed [q1, q2, q3] (q1 slowest).  Particle positions X have shape
-(P, 3).
+Grid: N nodes per axis on the periodic cube [0, L)^d (d = 3, or d = 2 for the
+two-dimensional example), node q = (q1, .., qd) at position q*h, h = L/N.  Grid arrays are
+indexed [q1, .., qd] (q1 slowest).  Particle positions X have shape (P, d).
 
-* Trilinear assignment (Sec. 2.2.1): R_h(x, qh) = h^-3 prod_j max(1 - |x_j - q_j h| / h, 0);
-  nonzero only on the 8 vertices of the cell that contains x.
+* Multilinear assignment (Sec. 2.2.1): R_h(x, qh) = h^-d prod_j max(1 - |x_j - q_j h| / h, 0);
+  nonzero only on the 2^d vertices of the cell that contains x (trilinear for d = 3,
+  bilinear for d = 2).
 * Particle-to-grid (Alg. p2g): ubar(qh) = sum_p a_p R_h(X_p, qh).  The density factor that
   appears in eq. def_u_overline is read as a typesetting slip: the algorithm adds a_p R_h.
 * Grid-to-particle (Alg. g2p, eq. g2p): f(X) = sum_q K_h(X, qh) f(qh) with K_h = h^3 R_h,
@@ -28,28 +29,31 @@ def _cell_and_frac(X, N, L):
     return i0, s
 
 
-def cic_weights(X, N, L):
-    """Trilinear stencil of every particle.
+def _flat(qw, N):
+    """Row-major flat index of wrapped node coordinates qw (P, d)."""
+    f = qw[:, 0].copy()
+    for j in range(1, qw.shape[1]):
+        f = f * N + qw[:, j]
+    return f
 
-    Returns (idx, wgt): idx (8, P) flat node indices (periodically wrapped), wgt (8, P) the
-    interaction weights K_h = h^3 R_h = prod_j max(1 - |s_j - q_j|, 0).
+
+def cic_weights(X, N, L):
+    """Multilinear stencil of every particle (d = X.shape[1]).
+
+    Returns (idx, wgt): idx (2^d, P) flat node indices (periodically wrapped), wgt (2^d, P)
+    the interaction weights K_h = h^d R_h = prod_j max(1 - |s_j - q_j|, 0).
     """
     i0, s = _cell_and_frac(X, N, L)
-    P = s.shape[0]
-    idx = np.empty((8, P), dtype=np.int64)
-    wgt = np.empty((8, P), dtype=np.float64)
-    c = 0
-    for c1 in (0, 1):
-        for c2 in (0, 1):
-            for c3 in (0, 1):
-                q = i0 + np.array([c1, c2, c3], dtype=np.int64)
-                w = np.ones(P)
-                for j in range(3):
-                    w = w * np.maximum(1.0 - np.abs(s[:, j] - q[:, j]), 0.0)
-                qw = q % N
-                idx[c] = (qw[:, 0] * N + qw[:, 1]) * N + qw[:, 2]
-                wgt[c] = w
-                c += 1
+    P, d = s.shape[0], s.shape[1]
+    idx = np.empty((2 ** d, P), dtype=np.int64)
+    wgt = np.empty((2 ** d, P), dtype=np.float64)
+    for c, corner in enumerate(np.ndindex(*([2] * d))):
+        q = i0 + np.array(corner, dtype=np.int64)
+        w = np.ones(P)
+        for j in range(d):
+            w = w * np.maximum(1.0 - np.abs(s[:, j] - q[:, j]), 0.0)
+        idx[c] = _flat(q % N, N)
+        wgt[c] = w
     return idx, wgt
 
 
@@ -100,8 +104,11 @@ def r4_weights(X, N, L):
 
 
 def deposit(X, a, N, L, order=2):
-    """Alg. p2g: ubar(qh) = sum_p a_p R_h(X_p, qh); returns an (N, N, N) float64 array."""
+    """Alg. p2g: ubar(qh) = sum_p a_p R_h(X_p, qh); returns an (N,)*d float64 array."""
     h = L / N
+    d = np.asarray(X).shape[1]
+    if order == 4 and d != 3:
+        raise ValueError("the fourth-order assignment is stated for d = 3")
     if order == 2:
         idx, wgt = cic_weights(X, N, L)
     elif order == 4:
@@ -109,21 +116,21 @@ def deposit(X, a, N, L, order=2):
     else:
         raise ValueError("deposit order must be 2 or 4")
     a = np.asarray(a, dtype=np.float64)
-    u = np.zeros(N ** 3)
+    u = np.zeros(N ** d)
     for c in range(idx.shape[0]):
-        u += np.bincount(idx[c], weights=a * wgt[c], minlength=N ** 3)
-    return (u / h ** 3).reshape(N, N, N)
+        u += np.bincount(idx[c], weights=a * wgt[c], minlength=N ** d)
+    return (u / h ** d).reshape((N,) * d)
 
 
 def gather(fields, X, N, L):
-    """Alg. g2p with K_h = h^3 R_h (trilinear): values of each grid field at the particles.
+    """Alg. g2p with K_h = h^d R_h (multilinear): values of each grid field at the particles.
 
-    fields: sequence of (N, N, N) arrays.  Returns an array of shape (len(fields), P).
+    fields: sequence of (N,)*d arrays.  Returns an array of shape (len(fields), P).
     """
     idx, wgt = cic_weights(X, N, L)
     out = np.zeros((len(fields), idx.shape[1]))
     for f, field in enumerate(fields):
         flat = np.asarray(field, dtype=np.float64).reshape(-1)
-        for c in range(8):
+        for c in range(idx.shape[0]):
             out[f] += wgt[c] * flat[idx[c]]
     return out

@@ -1,4 +1,5 @@
-"""Spectral operators on the periodic N^3 grid (oracle side; test infrastructure only).
+"""Spectral operators on the periodic N^d grid, d = 3 or 2 (oracle side; test infrastructure
+only).
 
 Fourier convention: numpy's fftn / ifftn (forward sum with e^{-2 pi i q.x / L}, inverse with
 the 1/N^3 factor), integer frequencies q_j in standard DFT order {0, 1, ..., N/2-1, -N/2, ...,
@@ -27,23 +28,32 @@ def freqs(N):
     return np.fft.fftfreq(N, d=1.0 / N)
 
 
-def k_squared(N, L):
-    """(2 pi / L)^2 |q|^2 on the full (N, N, N) frequency grid."""
-    q = freqs(N)
-    q2 = q[:, None, None] ** 2 + q[None, :, None] ** 2 + q[None, None, :] ** 2
-    return (2.0 * np.pi / L) ** 2 * q2
+def _q2(N, d):
+    """|q|^2 on the full (N,)*d frequency grid."""
+    q = freqs(N) ** 2
+    out = np.zeros((N,) * d)
+    for j in range(d):
+        shape = [1] * d
+        shape[j] = N
+        out = out + q.reshape(shape)
+    return out
 
 
-def implicit_multiplier(N, L, dt, D, decay):
-    return 1.0 / (1.0 + dt * (decay + D * k_squared(N, L)))
+def k_squared(N, L, d=3):
+    """(2 pi / L)^2 |q|^2 on the full (N,)*d frequency grid."""
+    return (2.0 * np.pi / L) ** 2 * _q2(N, d)
 
 
-def exp_multiplier(N, L, dt, D, decay):
-    return np.exp(-dt * (decay + D * k_squared(N, L)))
+def implicit_multiplier(N, L, dt, D, decay, d=3):
+    return 1.0 / (1.0 + dt * (decay + D * k_squared(N, L, d)))
 
 
-def aliased_multiplier(N, L, dt, D, decay, nmax=None):
-    """sum_{n in Z^3} exp(-tau (decay + D (2 pi/L)^2 |q + n N|^2)), truncated at |n_j| <= nmax."""
+def exp_multiplier(N, L, dt, D, decay, d=3):
+    return np.exp(-dt * (decay + D * k_squared(N, L, d)))
+
+
+def aliased_multiplier(N, L, dt, D, decay, nmax=None, d=3):
+    """sum_{n in Z^d} exp(-tau (decay + D (2 pi/L)^2 |q + n N|^2)), truncated at |n_j| <= nmax."""
     q = freqs(N)
     c = dt * D * (2.0 * np.pi / L) ** 2
     if nmax is None:
@@ -53,13 +63,16 @@ def aliased_multiplier(N, L, dt, D, decay, nmax=None):
             nmax += 1
     n = np.arange(-nmax, nmax + 1, dtype=np.float64)
     s1 = np.exp(-c * (q[:, None] + n[None, :] * N) ** 2).sum(axis=1)
-    return np.exp(-dt * decay) * s1[:, None, None] * s1[None, :, None] * s1[None, None, :]
+    out = np.exp(-dt * decay) * np.ones((N,) * d)
+    for j in range(d):
+        shape = [1] * d
+        shape[j] = N
+        out = out * s1.reshape(shape)
+    return out
 
 
-def lowpass(N, H0):
-    q = freqs(N)
-    q2 = q[:, None, None] ** 2 + q[None, :, None] ** 2 + q[None, None, :] ** 2
-    return np.exp(-2.0 * np.pi ** 2 * q2 / H0 ** 2)
+def lowpass(N, H0, d=3):
+    return np.exp(-2.0 * np.pi ** 2 * _q2(N, d) / H0 ** 2)
 
 
 def apply_multiplier(f, mult):
@@ -75,15 +88,15 @@ def derivative_freqs(N, L):
 
 
 def gradient(v, L, mult=None):
-    """(d1 v, d2 v, d3 v) on the nodes via eq. gradv; optional extra spectral multiplier."""
-    N = v.shape[0]
+    """(d_1 v, .., d_d v) on the nodes via eq. gradv; optional extra spectral multiplier."""
+    N, d = v.shape[0], v.ndim
     V = np.fft.fftn(v)
     if mult is not None:
         V = V * mult
     ik = derivative_freqs(N, L)
     out = []
-    for j in range(3):
-        shape = [1, 1, 1]
+    for j in range(d):
+        shape = [1] * d
         shape[j] = N
         out.append(np.real(np.fft.ifftn(V * ik.reshape(shape))))
     return out

@@ -1,7 +1,9 @@
 """One SIPF-W time step, Alg. sipf-pic, in float64 (oracle side; test infrastructure only).
 
-State at step n: particles (X_p, a_p), X_p in [0, L)^3, a_p > 0; nodal fields v, m, w on the
-N^3 grid (nodes at q h, h = L / N); the absolute step index n.
+State at step n: particles (X_p, a_p), X_p in [0, L)^d, a_p > 0; nodal fields v, m, w on the
+N^d grid (nodes at q h, h = L / N); the absolute step index n.  d = 3, or d = 2 for the
+paper's two-dimensional example (the method is stated for general d; the 2D step uses the
+bilinear assignment and the first two normals of the Philox block).
 
 One step n -> n+1, every right-hand side taken at time n (explicit operator splitting,
 eq. g_hat_phy; Euler-Maruyama, eq. u_hat_update):
@@ -82,17 +84,17 @@ def eta(u):
     return 2.0 * u / (1.0 + u)
 
 
-def diffusion_multiplier(prm, D, decay):
+def diffusion_multiplier(prm, D, decay, d=3):
     if prm.diffusion == "implicit":
-        mult = spectral.implicit_multiplier(prm.N, prm.L, prm.dt, D, decay)
+        mult = spectral.implicit_multiplier(prm.N, prm.L, prm.dt, D, decay, d=d)
     elif prm.diffusion == "exp":
-        mult = spectral.exp_multiplier(prm.N, prm.L, prm.dt, D, decay)
+        mult = spectral.exp_multiplier(prm.N, prm.L, prm.dt, D, decay, d=d)
     elif prm.diffusion == "aliased":
-        mult = spectral.aliased_multiplier(prm.N, prm.L, prm.dt, D, decay)
+        mult = spectral.aliased_multiplier(prm.N, prm.L, prm.dt, D, decay, d=d)
     else:
         raise ValueError(prm.diffusion)
     if prm.H0 > 0:
-        mult = mult * spectral.lowpass(prm.N, prm.H0)
+        mult = mult * spectral.lowpass(prm.N, prm.H0, d=d)
     return mult
 
 
@@ -106,14 +108,14 @@ def step(state, prm, return_aux=False):
     """Advance one step; returns the new State (and a dict of intermediates if asked)."""
     N, L, dt = prm.N, prm.L, prm.dt
     X, a, v, m, w = state.X, state.a, state.v, state.m, state.w
-    P = X.shape[0]
+    P, d = X.shape[0], v.ndim
 
     # 1. particle-to-grid
     ubar = pic.deposit(X, a, N, L, order=prm.deposit_order)
     # 2. spectral gradient of the old v
-    grad = spectral.gradient(v, L, mult=spectral.lowpass(N, prm.H0) if prm.H0 > 0 else None)
+    grad = spectral.gradient(v, L, mult=spectral.lowpass(N, prm.H0, d=d) if prm.H0 > 0 else None)
     # 3. grid-to-particle at the old positions
-    g = pic.gather([grad[0], grad[1], grad[2], w], X, N, L)
+    g = pic.gather(list(grad) + [w], X, N, L)
     # 4. explicit reaction on the old fields
     m_star = m + dt * ubar
     w_star = w + dt * (prm.gamma * v - eta(ubar) * w)
@@ -122,8 +124,8 @@ def step(state, prm, return_aux=False):
     else:
         v_new = v * np.exp(-prm.alpha * dt * m)
     # 5. diffusion + linear decay
-    m_new = spectral.apply_multiplier(m_star, diffusion_multiplier(prm, prm.D_m, prm.beta))
-    w_new = spectral.apply_multiplier(w_star, diffusion_multiplier(prm, prm.D_w, 1.0))
+    m_new = spectral.apply_multiplier(m_star, diffusion_multiplier(prm, prm.D_m, prm.beta, d))
+    w_new = spectral.apply_multiplier(w_star, diffusion_multiplier(prm, prm.D_w, 1.0, d))
     if prm.freeze_v:
         v_new = v.copy()
     if prm.freeze_m:
@@ -132,11 +134,11 @@ def step(state, prm, return_aux=False):
         w_new = w.copy()
     # 6. Euler-Maruyama push and mass update
     if prm.no_noise or P == 0:
-        z = np.zeros((P, 3))
+        z = np.zeros((P, d))
     else:
-        z = philox.step_normals(np.arange(P), state.n, prm.sim_id, prm.seed)
-    X_new = wrap(X + prm.chi * dt * g[:3].T + np.sqrt(2.0 * prm.D_u * dt) * z, L)
-    w_p = g[3]
+        z = philox.step_normals(np.arange(P), state.n, prm.sim_id, prm.seed)[:, :d]
+    X_new = wrap(X + prm.chi * dt * g[:d].T + np.sqrt(2.0 * prm.D_u * dt) * z, L)
+    w_p = g[d]
     if prm.linear_mass:
         a_new = a * (1.0 + dt * rho(w_p) - dt)
     else:
@@ -157,7 +159,7 @@ def run(state, prm, nsteps):
 def diagnostics(state, prm):
     """Mass sums and positivity figures of a state (Lemma mass, Corollary mass, positivity)."""
     N, L = prm.N, prm.L
-    h3 = (L / N) ** 3
+    h3 = (L / N) ** state.v.ndim   # cell volume h^d
     ubar = pic.deposit(state.X, state.a, N, L, order=prm.deposit_order)
     return dict(
         mass_particles=float(np.sum(state.a)),

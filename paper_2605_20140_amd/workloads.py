@@ -214,3 +214,52 @@ def paper3d_initial_state(N, P=1 << 22, ic_seed=21, **over):
     v0 = (0.05 * np.cos(5.0 * math.pi * X1 ** 2 / 18.0) * np.sin(13.0 * math.pi * X2 ** 2 / 72.0)
           * np.cos(math.pi * X3 ** 2 / 12.0) + 0.3)
     return dict(params=prm, X0=X0, a0=a0, v0=v0, m0=m0, w0=4.0 * v0)
+
+
+# ---- two-dimensional inputs (Sec. numerical experiments, 2D simulation) -------------------
+def blob2d_initial_state(N=32, P=4096, seed=0, ic_seed=0, dt=1e-3, sigma=0.1, **over):
+    """2D counterpart of the single-blob workload on the unit square: G = exp(-d^2/(2 s^2))
+    (peak 1), particles c + s Z (wrapped), masses 1/P, v0 = 1 - 0.5 G, m0 = 0.5 G, w0 = 1."""
+    prm = dict(BASE_PARAMS)
+    prm.update(over)
+    prm.update(N=N, P=P, dt=dt, seed=seed, steps=100, dim=2)
+    L = prm["L"]
+    rng = _rng(ic_seed)
+    c = np.array([0.5, 0.5])
+    x = np.arange(N) * (L / N)
+    d2 = np.zeros((N, N))
+    for j, shape in enumerate([(N, 1), (1, N)]):
+        dj = np.abs(x - c[j])
+        dj = np.minimum(dj, L - dj)
+        d2 = d2 + (dj ** 2).reshape(shape)
+    G = np.exp(-d2 / (2.0 * sigma * sigma))
+    X0 = _wrap_unit(c + sigma * rng.standard_normal((P, 2)), L)
+    a0 = np.full(P, 1.0 / P) if P > 0 else np.zeros(0)
+    if over.get("mass_spread") and P > 0:
+        a0 = weighted_masses(P, over["mass_spread"], rng)
+    return dict(params=prm, X0=X0, a0=a0, v0=1.0 - 0.5 * G, m0=0.5 * G, w0=np.ones((N, N)))
+
+
+# The paper's 2D example: periodic square [0, 6]^2; u0 = 5 max(r0^2 - |x - (3,3)|^2, 0) with
+# r0 = sqrt(0.3), m0 = u0, v0 = 0.05 cos(5 pi x1^2 / 18) sin(13 pi x2^2 / 72) + 0.3, w0 = 4 v0;
+# the same constants as the 3D example; tau = 1e-3 to T = 6; P = 2^22.
+def paper2d_initial_state(N, P=1 << 22, ic_seed=22, **over):
+    """Particles i.i.d. from the normalised u0 (radius r with r^2 = r0^2 (1 - sqrt(1 - U)),
+    uniform angle), equal masses; fields sampled at the nodes."""
+    prm = dict(PAPER3D_PARAMS)
+    prm.update(over)
+    prm.update(N=N, P=P, dim=2, seed=22)
+    L = prm["L"]
+    c = np.array([3.0, 3.0])
+    r0sq = 0.3
+    rng = _rng(ic_seed)
+    r = np.sqrt(r0sq * (1.0 - np.sqrt(1.0 - rng.random(P))))
+    th = 2.0 * math.pi * rng.random(P)
+    X0 = _wrap_unit(c + np.stack([r * np.cos(th), r * np.sin(th)], axis=1), L)
+    mass = 5.0 * math.pi * r0sq * r0sq / 2.0
+    a0 = np.full(P, mass / P) if P > 0 else np.zeros(0)
+    x = np.arange(N) * (L / N)
+    X1, X2 = np.meshgrid(x, x, indexing="ij")
+    m0 = 5.0 * np.maximum(r0sq - (X1 - c[0]) ** 2 - (X2 - c[1]) ** 2, 0.0)
+    v0 = 0.05 * np.cos(5.0 * math.pi * X1 ** 2 / 18.0) * np.sin(13.0 * math.pi * X2 ** 2 / 72.0) + 0.3
+    return dict(params=prm, X0=X0, a0=a0, v0=v0, m0=m0, w0=4.0 * v0)
