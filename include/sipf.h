@@ -30,6 +30,8 @@
  *   - host arrays are float64, owned by the caller, read (or written) during the call only;
  *   - grid arrays are row-major [i1][i2][i3] (i3 fastest), N^3 entries; particle positions
  *     are structure-of-arrays X[0..P) = x1, X[P..2P) = x2, X[2P..3P) = x3;
+ *   - with dim = 2 every N^3 below reads N^2 ([i1][i2]), every 3P reads 2P, and the gradient
+ *     has two components;
  *   - the device workspace is owned by the caller (for example a torch uint8 tensor); the
  *     library owns the layout inside it and keeps all state there, so several simulations
  *     can be resident at once, each in its own workspace;
@@ -71,8 +73,11 @@ extern "C" {
 /* Parameters (eq. haptotaxis-system, eq. g_t: D = diag(0, D_m, D_w), R = diag(0, beta, 1)). */
 typedef struct {
   double L;              /* period of the cube, > 0                                      */
-  int32_t N;             /* grid nodes per axis: power of two in [4, 512]                 */
-  int32_t reserved0;     /* must be 0                                                     */
+  int32_t N;             /* grid nodes per axis: power of two in [4, 512] (2D: [4, 1024],   *
+                          * float64 [4, 512])                                              */
+  int32_t dim;           /* 0 or 3: the 3D system; 2: the paper's two-dimensional form     *
+                          * (grids N^2, positions 2P, bilinear transfers, deposit_order 2, *
+                          * two Wiener components: the first two normals of the block)    */
   int64_t P;             /* particles, 0 <= P < 2^32                                      */
   double dt;             /* time step tau, 0 < dt <= 0.5 (positivity lemma)               */
   double D_u, chi, D_m, D_w, alpha, beta, gamma; /* model constants, all >= 0             */

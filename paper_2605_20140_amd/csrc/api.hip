@@ -45,11 +45,27 @@ struct Layout {
 
 bool is_pow2(int64_t n) { return n > 0 && (n & (n - 1)) == 0; }
 
+// spatial dimension (0 in the parameters means 3)
+int dim_of(const sipf_params& p) { return p.dim == 2 ? 2 : 3; }
+size_t grid_nodes(const sipf_params& p) {
+  size_t g = 1;
+  for (int j = 0; j < dim_of(p); ++j) g *= (size_t)p.N;
+  return g;
+}
+
 int validate_params(const sipf_params* p) {
   if (!p) return fail(SIPF_EINVAL, "params is NULL");
-  if (!(p->N >= 4 && p->N <= 512 && is_pow2(p->N)))
+  if (p->dim != 0 && p->dim != 2 && p->dim != 3)
+    return fail(SIPF_EINVAL, "dim must be 0 or 3 (three-dimensional) or 2");
+  if (p->dim == 2) {
+    const int nmax = p->precision == SIPF_FP64 ? 512 : 1024;
+    if (!(p->N >= 4 && p->N <= nmax && is_pow2(p->N)))
+      return fail(SIPF_EINVAL, "2D: N must be a power of two in [4, 1024] (float64: 512)");
+    if (p->deposit_order != 2)
+      return fail(SIPF_EINVAL, "2D: only the bilinear deposit (deposit_order 2)");
+  } else if (!(p->N >= 4 && p->N <= 512 && is_pow2(p->N))) {
     return fail(SIPF_EINVAL, "N must be a power of two in [4, 512]");
-  if (p->reserved0 != 0) return fail(SIPF_EINVAL, "reserved0 must be 0");
+  }
   if (p->P < 0 || p->P >= (int64_t(1) << 32))
     return fail(SIPF_EINVAL, "P must satisfy 0 <= P < 2^32");
   if (!(isfinite(p->L) && p->L > 0)) return fail(SIPF_EINVAL, "L must be finite and > 0");
@@ -84,7 +100,8 @@ int validate_params(const sipf_params* p) {
 
 Layout make_layout(const sipf_params& p) {
   const size_t s = p.precision == SIPF_FP32 ? 4 : 8;
-  const size_t N = (size_t)p.N, G = N * N * N, P = (size_t)p.P, H = N / 2 + 1;
+  const int dim = dim_of(p);
+  const size_t N = (size_t)p.N, G = grid_nodes(p), P = (size_t)p.P, H = N / 2 + 1;
   Layout L;
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -99,12 +116,13 @@ Layout make_layout(const sipf_params& p) {
   for (int k = 0; k < 2; ++k) {
     L.x[k] = take(P * s);
     L.y[k] = take(P * s);
-    L.z[k] = take(P * s);
+    L.z[k] = take(dim == 3 ? P * s : 0);
     L.a[k] = take(P * 8);
     L.id[k] = take(P * 4);
   }
-  const size_t nt1 = N / kTile > 0 ? N / kTile : 1;
-  const size_t ntiles = nt1 * nt1 * nt1;
+  const size_t tside = dim == 3 ? kTile : kTile2;
+  const size_t nt1 = N / tside > 0 ? N / tside : 1;
+  const size_t ntiles = dim == 3 ? nt1 * nt1 * nt1 : nt1 * nt1;
   L.tcount = take(ntiles * 4);
   L.toff = take((ntiles + 1) * 4);
   L.coff = take((ntiles + 1) * 4);
@@ -115,7 +133,7 @@ Layout make_layout(const sipf_params& p) {
   L.m = take(G * s);
   L.w = take(G * s);
   L.g4 = take(G * 4 * s);
-  const size_t spec = H * N * N * 2 * s;
+  const size_t spec = H * (G / N) * 2 * s;  // half spectrum: (N/2+1) N^(dim-1) complex
   L.SM = take(spec);
   L.SW = take(spec);
   L.SV = take(spec);
@@ -184,10 +202,11 @@ void enqueue_fft(const std::vector<FftGroup<T>>& groups, hipStream_t st) {
 // reads set 1 (and writes set 0).
 template <typename T>
 void enqueue_step(const Batch<T>& b, const int* tot, int nsims,
-                  const std::vector<FftGroup<T>>& groups, int bin, int order, hipStream_t st) {
-  if (bin) launch_binning<T>(b, tot, nsims, st);
+                  const std::vector<FftGroup<T>>& groups, int bin, int order, int dim,
+                  hipStream_t st) {
+  if (bin) launch_binning<T>(b, tot, nsims, dim, st);
   enqueue_fft<T>(groups, st);
-  launch_particles<T>(b, tot[K_PART], bin ? 1 : 0, 0, order, st);
+  launch_particles<T>(b, tot[K_PART], bin ? 1 : 0, 0, order, dim, st);
   launch_finalize<T>(b, nsims, st);
 }
 
@@ -232,32 +251,40 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   const Layout& L = sim->lay;
   const int N = p.N;
   const int64_t P = p.P;
-  const size_t G = (size_t)N * N * N;
+  const int dim = dim_of(p);
+  const size_t G = grid_nodes(p);
   unsigned char* ws = sim->ws;
 
   SimDev<T> d;
   memset(&d, 0, sizeof(d));
   d.N = N;
+  d.dim = dim;
+  d.G = (int64_t)G;
+  d.nrows = (int64_t)(G / N);
+  d.inv_nd = (T)(1.0 / (double)G);
   int lg = 0;
   while ((1 << lg) < N) ++lg;
   d.log2N = lg;
   d.P = P;
   const int E = elems_per_block<T>();
-  d.rows_per_blk = (int)std::min<int64_t>((int64_t)N * N, E / N);
+  d.rows_per_blk = (int)std::min<int64_t>(d.nrows, E / N);
   d.lines_per_blk = E / N;
   d.cols_per_blk = std::min(N, E / N);
   d.flags = (int)p.flags;
   d.L = (T)p.L;
   d.inv_h = (T)(N / p.L);
   const double h = p.L / N;
-  d.inv_h3 = (T)(1.0 / (h * h * h));
+  const double hd = dim == 3 ? h * h * h : h * h;  // cell volume h^dim
+  d.inv_h3 = (T)(1.0 / hd);
   d.two_pi_over_L = (T)(2.0 * M_PI / p.L);
   d.inv_n3 = (T)(1.0 / ((double)N * N * N));
   d.inv_n2 = (T)(1.0 / ((double)N * N));
-  d.use_plane = plane_fits<T>(lg) ? 1 : 0;
-  d.gz_scale = (T)(2.0 * M_PI / p.L / (d.use_plane ? (double)N : (double)N * N));
+  d.use_plane = dim == 3 && plane_fits<T>(lg) ? 1 : 0;
+  // the z (2D: x2) derivative is formed from V transformed along that axis only (plane and
+  // 2D paths) or along y as well (three-pass path)
+  d.gz_scale = (T)(2.0 * M_PI / p.L / (dim == 3 && !d.use_plane ? (double)N * N : (double)N));
   if (d.use_plane) launch_plane<T>(Batch<T>{}, 0, lg, nullptr, 1);  // raise its LDS limit
-  configure_particles<T>(p.deposit_order);
+  configure_particles<T>(p.deposit_order, dim);
   d.dt = p.dt;
   d.D_u = p.D_u;
   d.chi = p.chi;
@@ -268,21 +295,22 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   d.gamma = p.gamma;
   d.noise_amp = (T)sqrt(2.0 * p.D_u * p.dt);
   d.drift = (T)(p.chi * p.dt);
-  d.h3 = h * h * h;
+  d.h3 = hd;
   d.seed_lo = (uint32_t)(p.seed & 0xFFFFFFFFu);
   d.seed_hi = (uint32_t)(p.seed >> 32);
   d.sim_lo = (uint32_t)(p.sim_id & 0xFFFFFFFFu);
   d.sim_hi = (uint32_t)(p.sim_id >> 32);
   d.mult_kind = (p.flags & (SIPF_FLAG_EXP_DIFFUSION | SIPF_FLAG_ALIASED_DIFFUSION)) ? 1 : 0;
   d.use_lowpass = p.H0 > 0 ? 1 : 0;
-  d.ntile1 = N / kTile > 0 ? N / kTile : 1;
-  d.ntiles = d.ntile1 * d.ntile1 * d.ntile1;
-  d.use_region = N >= 2 * kTile ? 1 : 0;
+  const int tside = dim == 3 ? kTile : kTile2;
+  d.ntile1 = N / tside > 0 ? N / tside : 1;
+  d.ntiles = dim == 3 ? d.ntile1 * d.ntile1 * d.ntile1 : d.ntile1 * d.ntile1;
+  d.use_region = N >= 2 * tside ? 1 : 0;
   d.deposit_order = p.deposit_order;
   for (int k = 0; k < 2; ++k) {
     d.xs[k] = reinterpret_cast<T*>(ws + L.x[k]);
     d.ys[k] = reinterpret_cast<T*>(ws + L.y[k]);
-    d.zs[k] = reinterpret_cast<T*>(ws + L.z[k]);
+    d.zs[k] = dim == 3 ? reinterpret_cast<T*>(ws + L.z[k]) : nullptr;
     d.as[k] = reinterpret_cast<double*>(ws + L.a[k]);
     d.ids[k] = reinterpret_cast<uint32_t*>(ws + L.id[k]);
   }
@@ -317,12 +345,12 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   }
 
   // host staging in the working precision
-  std::vector<T> hx(P), hy(P), hz(P);
+  std::vector<T> hx(P), hy(P), hz(dim == 3 ? P : 0);
   const T LT = (T)p.L;
   for (int64_t i = 0; i < P; ++i) {
-    double c3[3] = {X0[i], X0[P + i], X0[2 * P + i]};
+    double c3[3] = {X0[i], X0[P + i], dim == 3 ? X0[2 * P + i] : 0.0};
     T out[3];
-    for (int j = 0; j < 3; ++j) {
+    for (int j = 0; j < dim; ++j) {
       double q = c3[j] - p.L * floor(c3[j] / p.L);
       if (q >= p.L || q < 0) q = 0.0;
       T t = (T)q;
@@ -331,7 +359,7 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
     }
     hx[i] = out[0];
     hy[i] = out[1];
-    hz[i] = out[2];
+    if (dim == 3) hz[i] = out[2];
   }
   std::vector<uint32_t> hid(P);
   for (int64_t i = 0; i < P; ++i) hid[i] = (uint32_t)i;
@@ -370,7 +398,8 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   if (P > 0) {
     HIPCHK(hipMemcpyAsync(d.xs[0], hx.data(), P * sizeof(T), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(d.ys[0], hy.data(), P * sizeof(T), hipMemcpyHostToDevice, st));
-    HIPCHK(hipMemcpyAsync(d.zs[0], hz.data(), P * sizeof(T), hipMemcpyHostToDevice, st));
+    if (dim == 3)
+      HIPCHK(hipMemcpyAsync(d.zs[0], hz.data(), P * sizeof(T), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(d.as[0], a0, P * sizeof(double), hipMemcpyHostToDevice, st));
     HIPCHK(hipMemcpyAsync(d.ids[0], hid.data(), P * sizeof(uint32_t), hipMemcpyHostToDevice,
                           st));
@@ -383,20 +412,24 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   HIPCHK(hipMemsetAsync(d.ubar, 0, G * sizeof(T), st));
   HIPCHK(hipMemsetAsync(d.g4, 0, G * sizeof(vec4<T>), st));
   HIPCHK(hipMemsetAsync(d.tcount, 0, (size_t)d.ntiles * sizeof(uint32_t), st));
+  // 2D: no y derivative spectrum is ever formed; the inverse row pass reads zeros from it
+  if (dim == 2)
+    HIPCHK(hipMemsetAsync(d.SGy, 0, (size_t)(N / 2 + 1) * d.nrows * sizeof(cplx<T>), st));
   const Batch<T> b = single_batch<T>(sim);
   // initial binning: set 0 -> set 1 by tile, then back into set 0
-  launch_binning<T>(b, sim->counts, 1, st);
+  launch_binning<T>(b, sim->counts, 1, dim, st);
   if (P > 0) {
     HIPCHK(hipMemcpyAsync(d.xs[0], d.xs[1], P * sizeof(T), hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemcpyAsync(d.ys[0], d.ys[1], P * sizeof(T), hipMemcpyDeviceToDevice, st));
-    HIPCHK(hipMemcpyAsync(d.zs[0], d.zs[1], P * sizeof(T), hipMemcpyDeviceToDevice, st));
+    if (dim == 3)
+      HIPCHK(hipMemcpyAsync(d.zs[0], d.zs[1], P * sizeof(T), hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemcpyAsync(d.as[0], d.as[1], P * sizeof(double), hipMemcpyDeviceToDevice, st));
     HIPCHK(hipMemcpyAsync(d.ids[0], d.ids[1], P * sizeof(uint32_t), hipMemcpyDeviceToDevice,
                           st));
   }
   sim->resort_every = p.resort_every > 0 ? p.resort_every : 8;
   sim->since_bin = 0;
-  launch_particles<T>(b, sim->counts[K_PART], 0, 1, p.deposit_order, st);  // ubar^0
+  launch_particles<T>(b, sim->counts[K_PART], 0, 1, p.deposit_order, dim, st);  // ubar^0
   launch_diag_clear<T>(b, 1, st);
   launch_diag_init<T>(b, sim->counts[K_DIAG], 1, st);
   HIPCHK(hipGetLastError());
@@ -406,12 +439,12 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   HIPCHK(hipStreamCreateWithFlags(&sim->cap, hipStreamNonBlocking));
   const auto groups = single_groups<T>(sim, b);
   HIPCHK(hipStreamBeginCapture(sim->cap, hipStreamCaptureModeThreadLocal));
-  enqueue_step<T>(b, sim->counts, 1, groups, 0, p.deposit_order, sim->cap);
+  enqueue_step<T>(b, sim->counts, 1, groups, 0, p.deposit_order, dim, sim->cap);
   HIPCHK(hipStreamEndCapture(sim->cap, &sim->graph));
   HIPCHK(hipGetLastError());
   HIPCHK(hipGraphInstantiate(&sim->exec, sim->graph, nullptr, nullptr, 0));
   HIPCHK(hipStreamBeginCapture(sim->cap, hipStreamCaptureModeThreadLocal));
-  enqueue_step<T>(b, sim->counts, 1, groups, 1, p.deposit_order, sim->cap);
+  enqueue_step<T>(b, sim->counts, 1, groups, 1, p.deposit_order, dim, sim->cap);
   HIPCHK(hipStreamEndCapture(sim->cap, &sim->graph_bin));
   HIPCHK(hipGetLastError());
   HIPCHK(hipGraphInstantiate(&sim->exec_bin, sim->graph_bin, nullptr, nullptr, 0));
@@ -450,7 +483,8 @@ int fields_t(sipf_sim* sim, double* v, double* m, double* w, double* X, double* 
              sipf_diag* diag) {
   const sipf_params& p = sim->prm;
   const SimDev<T>& d = *reinterpret_cast<const SimDev<T>*>(sim->host_desc);
-  const size_t G = (size_t)p.N * p.N * p.N;
+  const size_t G = grid_nodes(p);
+  const int dim = dim_of(p);
   const int64_t P = p.P;
   if (sim->last_stream) HIPCHK(hipStreamSynchronize(sim->last_stream));
   HIPCHK(hipStreamSynchronize(sim->stream));
@@ -470,7 +504,7 @@ int fields_t(sipf_sim* sim, double* v, double* m, double* w, double* X, double* 
     HIPCHK(hipMemcpy(id.data(), d.ids[0], P * sizeof(uint32_t), hipMemcpyDeviceToHost));
     if (X) {
       const T* comp[3] = {d.xs[0], d.ys[0], d.zs[0]};
-      for (int j = 0; j < 3; ++j) {
+      for (int j = 0; j < dim; ++j) {
         HIPCHK(hipMemcpy(buf.data(), comp[j], P * sizeof(T), hipMemcpyDeviceToHost));
         for (int64_t i = 0; i < P; ++i) X[(int64_t)j * P + id[i]] = (double)buf[i];
       }
@@ -531,7 +565,7 @@ template <typename T>
 int aux_t(sipf_sim* sim, double* u_bar, double* grad_v) {
   const sipf_params& p = sim->prm;
   const SimDev<T>& d = *reinterpret_cast<const SimDev<T>*>(sim->host_desc);
-  const size_t G = (size_t)p.N * p.N * p.N;
+  const size_t G = grid_nodes(p);
   if (sim->last_stream) HIPCHK(hipStreamSynchronize(sim->last_stream));
   HIPCHK(hipStreamSynchronize(sim->stream));
   if (u_bar) {
@@ -544,8 +578,12 @@ int aux_t(sipf_sim* sim, double* u_bar, double* grad_v) {
     HIPCHK(hipMemcpy(buf.data(), d.g4, G * sizeof(vec4<T>), hipMemcpyDeviceToHost));
     for (size_t i = 0; i < G; ++i) {
       grad_v[i] = (double)buf[i].x;
-      grad_v[G + i] = (double)buf[i].y;
-      grad_v[2 * G + i] = (double)buf[i].z;
+      if (dim_of(p) == 3) {
+        grad_v[G + i] = (double)buf[i].y;
+        grad_v[2 * G + i] = (double)buf[i].z;
+      } else {  // 2D: the x2 derivative sits in the third slot of the gather array
+        grad_v[G + i] = (double)buf[i].z;
+      }
     }
   }
   return SIPF_OK;
@@ -676,7 +714,7 @@ int build_batch_graph(sipf_sim* const* sims, int nsims, int dev, BatchGraph** ou
   for (int bin = 0; bin < 2 && rc == SIPF_OK; ++bin) {
     chk(hipStreamBeginCapture(g_cap_stream[dev], hipStreamCaptureModeThreadLocal), "capture");
     if (rc != SIPF_OK) break;
-    enqueue_step<T>(b, tot.data(), nsims, groups, bin, sims[0]->prm.deposit_order,
+    enqueue_step<T>(b, tot.data(), nsims, groups, bin, sims[0]->prm.deposit_order, 3,
                     g_cap_stream[dev]);
     chk(hipStreamEndCapture(g_cap_stream[dev], &e->graph[bin]), "hipStreamEndCapture");
     if (rc == SIPF_OK) chk(hipGetLastError(), "batched launch");
@@ -752,7 +790,7 @@ int step_timed_t(sipf_sim* sim, int nsteps, float* stage_ms) {
   for (int s = 0; s < nsteps && rc == SIPF_OK; ++s) {
     const int bin = sim->since_bin >= sim->resort_every;
     (void)hipEventRecord(ev[SIPF_NUM_STAGES], st);
-    if (bin) launch_binning<T>(b, c, 1, st);
+    if (bin) launch_binning<T>(b, c, 1, dim_of(sim->prm), st);
     (void)hipEventRecord(ev[0], st);
     launch_zfwd<T>(b, c[K_ZFWD], lg, st);
     (void)hipEventRecord(ev[1], st);
@@ -765,7 +803,7 @@ int step_timed_t(sipf_sim* sim, int nsteps, float* stage_ms) {
     (void)hipEventRecord(ev[4], st);
     launch_zinv<T>(b, c[K_ZINV], lg, st);
     (void)hipEventRecord(ev[5], st);
-    launch_particles<T>(b, c[K_PART], bin, 0, sim->prm.deposit_order, st);
+    launch_particles<T>(b, c[K_PART], bin, 0, sim->prm.deposit_order, dim_of(sim->prm), st);
     (void)hipEventRecord(ev[6], st);
     launch_finalize<T>(b, 1, st);
     (void)hipEventRecord(ev[7], st);
@@ -819,15 +857,17 @@ int resample_t(sipf_sim* sim, sipf_resample_info* info) {
   launch_resample_apply<T>(d, rs, st);
   // re-bin the new list (set 0 -> set 1 by tile, back into set 0) and deposit its ubar
   const Batch<T> b = single_batch<T>(sim);
-  launch_binning<T>(b, sim->counts, 1, st);
+  const int dim = dim_of(p);
+  launch_binning<T>(b, sim->counts, 1, dim, st);
   HIPCHK(hipMemcpyAsync(d.xs[0], d.xs[1], P * sizeof(T), hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(d.ys[0], d.ys[1], P * sizeof(T), hipMemcpyDeviceToDevice, st));
-  HIPCHK(hipMemcpyAsync(d.zs[0], d.zs[1], P * sizeof(T), hipMemcpyDeviceToDevice, st));
+  if (dim == 3)
+    HIPCHK(hipMemcpyAsync(d.zs[0], d.zs[1], P * sizeof(T), hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(d.as[0], d.as[1], P * sizeof(double), hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(d.ids[0], d.ids[1], P * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
-  const size_t G = (size_t)p.N * p.N * p.N;
+  const size_t G = grid_nodes(p);
   HIPCHK(hipMemsetAsync(d.ubar, 0, G * sizeof(T), st));
-  launch_particles<T>(b, sim->counts[K_PART], 0, 1, p.deposit_order, st);
+  launch_particles<T>(b, sim->counts[K_PART], 0, 1, p.deposit_order, dim, st);
   launch_diag_clear<T>(b, 1, st);
   launch_diag_init<T>(b, sim->counts[K_DIAG], 1, st);
   HIPCHK(hipGetLastError());
@@ -894,10 +934,10 @@ int sipf_init(const sipf_params* prm, void* d_workspace, size_t bytes, void* hip
   if (!out) return fail(SIPF_EINVAL, "out is NULL");
   *out = nullptr;
   const sipf_params& p = *prm;
-  const size_t G = (size_t)p.N * p.N * p.N;
+  const size_t G = grid_nodes(p);
   if (p.P > 0 && (!X0 || !a0)) return fail(SIPF_EINVAL, "X0 / a0 is NULL");
   if (!v0 || !m0 || !w0) return fail(SIPF_EINVAL, "v0 / m0 / w0 is NULL");
-  if (p.P > 0 && !finite_array(X0, 3 * (size_t)p.P, false, false))
+  if (p.P > 0 && !finite_array(X0, (size_t)dim_of(p) * (size_t)p.P, false, false))
     return fail(SIPF_EINVAL, "X0 has non-finite entries");
   if (p.P > 0 && !finite_array(a0, (size_t)p.P, false, true))
     return fail(SIPF_EINVAL, "a0 must be finite and > 0");
@@ -981,6 +1021,8 @@ int sipf_step_batch(sipf_sim* const* sims, int32_t nsims, int32_t nsteps) {
       return fail(SIPF_EINVAL, "mixed precision in one batch");
     if (sims[i]->prm.deposit_order != sims[0]->prm.deposit_order)
       return fail(SIPF_EINVAL, "mixed deposit order in one batch");
+    if (dim_of(sims[i]->prm) != 3)
+      return fail(SIPF_EINVAL, "batched steps are three-dimensional only");
     if (sims[i]->device != sims[0]->device)
       return fail(SIPF_EINVAL, "simulations on different devices");
     for (int j = 0; j < i; ++j)

@@ -77,7 +77,8 @@ __global__ void __launch_bounds__(kThreads) k_diag_full(Batch<T> bt, int state, 
     for (int64_t i = (int64_t)lb * kThreads + threadIdx.x; i < d.P; i += stride) {
       const double am = d.as[0][i];
       const bool bad = !isfinite(am) || !isfinite((double)d.xs[0][i]) ||
-                       !isfinite((double)d.ys[0][i]) || !isfinite((double)d.zs[0][i]);
+                       !isfinite((double)d.ys[0][i]) ||
+                       (d.dim == 3 && !isfinite((double)d.zs[0][i]));
       if (bad) {
         a.cnt[0] += 1;
       } else {
@@ -87,7 +88,7 @@ __global__ void __launch_bounds__(kThreads) k_diag_full(Batch<T> bt, int state, 
       }
     }
   }
-  const int64_t G = (int64_t)d.N * d.N * d.N;
+  const int64_t G = d.G;
   for (int64_t i = (int64_t)lb * kThreads + threadIdx.x; i < G; i += stride) {
     if (u) {
       const double uu = d.ubar[i];

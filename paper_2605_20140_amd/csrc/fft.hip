@@ -51,19 +51,26 @@ void block_counts(const SimDev<T>& d, int c[K_COUNT]) {
   const int64_t Bl = d.lines_per_blk;
   const int64_t ny = (lines + Bl - 1) / Bl;
   const int64_t ny2 = (lines + Bl / 2 - 1) / (Bl / 2);
-  c[K_ZFWD] = (int)(N * N / d.rows_per_blk);
-  c[K_YFWD] = d.use_plane ? 0 : (int)(3 * ny);
+  c[K_ZFWD] = (int)(d.nrows / d.rows_per_blk);
   const int64_t nlp = d.use_lowpass ? 1 : 0;  // filtered copy of V as an extra job
-  c[K_XPASS] = d.use_plane ? 0 : (int)((3 + nlp) * H * (N / d.cols_per_blk));
-  c[K_YINV] = d.use_plane ? 0 : (int)(3 * ny + ny2);
-  c[K_PLANE] = d.use_plane ? (int)((4 + nlp) * H) : 0;
+  if (d.dim == 2) {  // row pass, one column pass (k_xpass), inverse row pass
+    c[K_YFWD] = 0;
+    c[K_XPASS] = (int)((3 + nlp) * ((H + d.cols_per_blk - 1) / d.cols_per_blk));
+    c[K_YINV] = 0;
+    c[K_PLANE] = 0;
+  } else {
+    c[K_YFWD] = d.use_plane ? 0 : (int)(3 * ny);
+    c[K_XPASS] = d.use_plane ? 0 : (int)((3 + nlp) * H * (N / d.cols_per_blk));
+    c[K_YINV] = d.use_plane ? 0 : (int)(3 * ny + ny2);
+    c[K_PLANE] = d.use_plane ? (int)((4 + nlp) * H) : 0;
+  }
   c[K_ZINV] = c[K_ZFWD];
   const int64_t pb = (d.P + kThreads - 1) / kThreads;
   c[K_PART] = d.max_chunks;  // bound on the number of (tile, chunk) items
   c[K_SCOUNT] = (int)((d.P + kBinBlock - 1) / kBinBlock);
   c[K_SSCAN] = 1;
   c[K_SSCATTER] = (int)pb;
-  const int64_t work = d.P > N * N * N ? d.P : N * N * N;
+  const int64_t work = d.P > d.G ? d.P : d.G;
   int64_t db = (work + kThreads * 8 - 1) / (kThreads * 8);
   if (db < 1) db = 1;
   if (db > 1024) db = 1024;
@@ -268,7 +275,7 @@ template <typename T, int LG>
 __device__ void zfwd_body(const SimDev<T>& d, int lb, unsigned char* smem) {
   constexpr int N = 1 << LG;
   const int B = d.rows_per_blk;
-  const int64_t N2 = (int64_t)N * N;
+  const int64_t N2 = d.nrows;  // rows per k3 plane of the spectra (N^2; N in 2D)
   const int64_t r0 = (int64_t)lb * B;
   constexpr int LS = row_stride<LG>();
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);  // B lines: m* + i w*
@@ -489,12 +496,76 @@ __device__ void xpass_body(const SimDev<T>& d, int lb, unsigned char* smem) {
   }
 }
 
+// ---- two-dimensional column pass ---------------------------------------------------------
+// In 2D the spectra are S[k2][i1] (k2 in [0, N/2]): after the row pass every k2 line along
+// i1 is contiguous.  Per line: forward transform, the multipliers of eq. k_q_tilde_update
+// with |k|^2 = (2 pi/L)^2 (q1^2 + q2^2) (m, w), the d1 multiplier (V -> SGx), or with the
+// low-pass filter the filtered V (1/N undoes this round trip) into SVg; inverse transform.
+// The d2 derivative is formed by the inverse row pass from SVg, as d3 is in 3D.
+template <typename T, int LG>
+__device__ void col2d_body(const SimDev<T>& d, int lb, unsigned char* smem) {
+  constexpr int N = 1 << LG;
+  constexpr int H = (N >> 1) + 1;
+  const int Bl = d.cols_per_blk;
+  const int nbf = (H + Bl - 1) / Bl;
+  const int f = lb / nbf;
+  const int kl0 = (lb - f * nbf) * Bl;
+  const int nl = H - kl0 < Bl ? H - kl0 : Bl;
+  const cplx<T>* src = (f == 0 ? d.SM : (f == 1 ? d.SW : d.SV)) + (int64_t)kl0 * N;
+  cplx<T>* dst = (f == 0 ? d.SM : (f == 1 ? d.SW : (f == 2 ? d.SGx : d.SVg))) + (int64_t)kl0 * N;
+  constexpr int LS = row_stride<LG>();
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* tw = buf + Bl * LS;
+  load_twiddles(tw, d);
+  for (int e = threadIdx.x; e < nl * N; e += kThreads)
+    buf[(e >> LG) * LS + (e & (N - 1))] = src[e];
+  __syncthreads();
+  line_fwd<T, LG>(buf, nl, LS, 1, tw);
+  const T k0 = d.two_pi_over_L;
+  const T D = (T)(f == 0 ? d.D_m : d.D_w);
+  const T decay = (T)(f == 0 ? d.beta : 1.0);
+  for (int e = threadIdx.x; e < nl * N; e += kThreads) {
+    const int line = e >> LG, p = e & (N - 1);
+    const int k1 = ufpos<LG>(p), k2 = kl0 + line;
+    cplx<T> val = buf[line * LS + p];
+    T lp = (T)1;
+    if (d.use_lowpass) {
+      const T* t = d.mtab + 2 * N;
+      lp = t[k1] * t[k2];
+    }
+    if (f < 2) {
+      T mult;
+      if (d.mult_kind == 0) {
+        const int q1 = lap_freq(k1, N), q2 = lap_freq(k2, N);
+        mult = (T)1 / ((T)1 + (T)d.dt * (decay + D * k0 * k0 * (T)(q1 * q1 + q2 * q2)));
+      } else {
+        const T* tab = d.mtab + f * N;
+        mult = (T)exp(-(T)d.dt * decay) * tab[k1] * tab[k2];
+      }
+      val = cscale(val, mult * d.inv_nd * lp);
+    } else if (f == 2) {
+      const T kk = k0 * (T)deriv_freq(k1, N) * d.inv_nd * lp;
+      val = cplx<T>{-kk * val.y, kk * val.x};
+    } else {
+      val = cscale(val, lp / (T)N);
+    }
+    buf[line * LS + p] = val;
+  }
+  __syncthreads();
+  line_inv<T, LG>(buf, nl, LS, 1, tw);
+  for (int e = threadIdx.x; e < nl * N; e += kThreads)
+    dst[e] = buf[(e >> LG) * LS + (e & (N - 1))];
+}
+
 template <typename T, int LG>
 __global__ void __launch_bounds__(kThreads) k_xpass(Batch<T> bt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
   const int s = find_sim(bt, K_XPASS, lb);
-  xpass_body<T, LG>(bt.sims[s], lb, smem_raw);
+  if (bt.sims[s].dim == 2)
+    col2d_body<T, LG>(bt.sims[s], lb, smem_raw);
+  else
+    xpass_body<T, LG>(bt.sims[s], lb, smem_raw);
 }
 
 // ---- plane pass: y, x, multipliers, x^-1, y^-1 on one k3 plane in LDS --------------------
@@ -576,7 +647,7 @@ template <typename T, int LG>
 __device__ void zinv_body(const SimDev<T>& d, int lb, unsigned char* smem) {
   constexpr int N = 1 << LG;
   const int B = d.rows_per_blk;
-  const int64_t N2 = (int64_t)N * N;
+  const int64_t N2 = d.nrows;  // rows per k3 plane of the spectra (N^2; N in 2D)
   const int64_t r0 = (int64_t)lb * B;
   const int Bh = B >> 1;
   constexpr int LS = row_stride<LG>();
@@ -695,6 +766,7 @@ template size_t fft_lds_bytes<float>(int, int);
       SIPF_LG_CASE(KER, KIND, 7)                                                   \
       SIPF_LG_CASE(KER, KIND, 8)                                                   \
       SIPF_LG_CASE(KER, KIND, 9)                                                   \
+      SIPF_LG_CASE(KER, KIND, 10)                                                  \
       default: break;                                                              \
     }                                                                              \
   }                                                                                \

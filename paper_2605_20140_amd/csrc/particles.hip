@@ -444,6 +444,185 @@ __global__ void __launch_bounds__(kThreads) k_particles(Batch<T> bt, int src_set
   if (!deposit_only) acc_flush(dg, diag_stripe(d));
 }
 
+// ---- two-dimensional particle pass ---------------------------------------------------------
+// The same pass on an N^2 grid (the paper's two-dimensional example): bilinear stencils,
+// square tiles of kTile2^2 cells with a (kTile2 + 3)^2-node LDS region, two Wiener
+// components (the first two normals of the Philox block).  The gather array holds
+// (d1 v, -, d2 v, w) per node.
+constexpr int kR2 = kTile2 + 3;  // nodes per axis of a 2D region (one-cell margin each side)
+constexpr int kR2sq = kR2 * kR2;
+
+template <typename T>
+__device__ __forceinline__ Stencil<T> make_stencil2(T x, T y, T inv_h, int N) {
+  Stencil<T> st;
+  const T s[2] = {x * inv_h, y * inv_h};
+#pragma unroll
+  for (int j = 0; j < 2; ++j) {
+    const T fl = floor(s[j]);
+    st.f[j] = s[j] - fl;
+    st.c[j] = ((int)fl) & (N - 1);
+  }
+  st.f[2] = (T)0;
+  st.c[2] = 0;
+  return st;
+}
+
+template <typename T>
+__device__ __forceinline__ bool in_region2(const Stencil<T>& st, const Region& rg, int N,
+                                           int l[2]) {
+  l[0] = (st.c[0] - rg.o[0]) & (N - 1);
+  l[1] = (st.c[1] - rg.o[1]) & (N - 1);
+  return l[0] <= kR2 - 2 && l[1] <= kR2 - 2;
+}
+
+__device__ __forceinline__ void box_muller2(uint32_t r0, uint32_t r1, double z[2]) {
+  const double u0 = fma((double)r0, 0x1p-32, 0x1p-33);
+  const double u1 = fma((double)r1, 0x1p-32, 0x1p-33);
+  const double ra = sqrt(-2.0 * log(u0));
+  double s1, c1;
+  sincospi(2.0 * u1, &s1, &c1);
+  z[0] = ra * c1;
+  z[1] = ra * s1;
+}
+
+__device__ __forceinline__ void box_muller2(uint32_t r0, uint32_t r1, float z[2]) {
+  const float u0 = fmaf((float)r0, 0x1p-32f, 0x1p-33f);
+  const float u1 = fmaf((float)r1, 0x1p-32f, 0x1p-33f);
+  const float ra = __builtin_amdgcn_sqrtf(-2.0f * 0.69314718055994531f * __builtin_amdgcn_logf(u0));
+  z[0] = ra * __builtin_amdgcn_cosf(u1);
+  z[1] = ra * __builtin_amdgcn_sinf(u1);
+}
+
+template <typename T>
+__device__ __forceinline__ void deposit2(T* ubar, double* acc, const Stencil<T>& st,
+                                         const Region& rg, bool use_region, int N, T q) {
+  const T wx[2] = {(T)1 - st.f[0], st.f[0]};
+  const T wy[2] = {(T)1 - st.f[1], st.f[1]};
+  int l[2];
+  if (use_region && in_region2(st, rg, N, l)) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        atomicAdd(&acc[(l[0] + a) * kR2 + l[1] + b], (double)(q * wx[a] * wy[b]));
+  } else {
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+        unsafeAtomicAdd(&ubar[(int64_t)((st.c[0] + a) & (N - 1)) * N + ((st.c[1] + b) & (N - 1))],
+                        q * wx[a] * wy[b]);
+  }
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_set,
+                                                         int deposit_only) {
+  extern __shared__ __align__(16) unsigned char smem_raw[];
+  int lb;
+  const int s = find_sim(bt, K_PART, lb);
+  const SimDev<T>& d = bt.sims[s];
+  const int nchunks = (int)d.coff[d.ntiles];
+  if (lb >= nchunks) return;
+  const int tile = (int)d.ctile[lb];
+  const uint32_t start = d.toff[tile] + (uint32_t)(lb - (int)d.coff[tile]) * kChunk;
+  const uint32_t tend = d.toff[tile + 1];
+  const uint32_t end = start + kChunk < tend ? start + kChunk : tend;
+  const int N = d.N;
+  const int nt = d.ntile1;
+  Region rg;
+  rg.o[0] = (tile / nt) * kTile2 - 1;
+  rg.o[1] = (tile % nt) * kTile2 - 1;
+  rg.o[2] = 0;
+  const bool use_region = d.use_region;
+  const T* xi = d.xs[src_set];
+  const T* yi = d.ys[src_set];
+  const double* ai = d.as[src_set];
+  const uint32_t* idi = d.ids[src_set];
+
+  vec4<T>* gl = reinterpret_cast<vec4<T>*>(smem_raw);
+  double* acc = reinterpret_cast<double*>(gl + kR2sq);
+  if (use_region) {
+    for (int e = threadIdx.x; e < kR2sq; e += kThreads) {
+      const int ry = e % kR2, rx = e / kR2;
+      if (!deposit_only)
+        gl[e] = d.g4[(int64_t)((rg.o[0] + rx) & (N - 1)) * N + ((rg.o[1] + ry) & (N - 1))];
+      acc[e] = 0.0;
+    }
+    __syncthreads();
+  }
+  const uint32_t n = (uint32_t)(*d.step);
+  const bool linear_mass = d.flags & SIPF_FLAG_LINEAR_MASS;
+  const bool noise = !(d.flags & SIPF_FLAG_NO_NOISE);
+  Acc dg;
+  acc_init(dg);
+  for (uint32_t i = start + threadIdx.x; i < end; i += kThreads) {
+    const T x = xi[i], y = yi[i];
+    const double a = ai[i];
+    if (deposit_only) {
+      deposit2(d.ubar, acc, make_stencil2(x, y, d.inv_h, N), rg, use_region, N,
+               (T)a * d.inv_h3);
+      continue;
+    }
+    const uint32_t pid = idi[i];
+    const Stencil<T> st = make_stencil2(x, y, d.inv_h, N);
+    const T wx[2] = {(T)1 - st.f[0], st.f[0]};
+    const T wy[2] = {(T)1 - st.f[1], st.f[1]};
+    T g0 = 0, g1 = 0, gw = 0;
+    int l[2];
+    const bool inside = use_region && in_region2(st, rg, N, l);
+#pragma unroll
+    for (int aa = 0; aa < 2; ++aa)
+#pragma unroll
+      for (int bb = 0; bb < 2; ++bb) {
+        const vec4<T> q =
+            inside ? gl[(l[0] + aa) * kR2 + l[1] + bb]
+                   : d.g4[(int64_t)((st.c[0] + aa) & (N - 1)) * N + ((st.c[1] + bb) & (N - 1))];
+        const T wgt = wx[aa] * wy[bb];
+        g0 += wgt * q.x;
+        g1 += wgt * q.z;
+        gw += wgt * q.w;
+      }
+    T zn[2] = {0, 0};
+    if (noise) {
+      uint32_t c0 = pid, c1 = n, c2 = d.sim_lo, c3 = d.sim_hi;
+      philox4x32_10(c0, c1, c2, c3, d.seed_lo, d.seed_hi);
+      box_muller2(c0, c1, zn);
+    }
+    const T xn = wrap_periodic(x + d.drift * g0 + d.noise_amp * zn[0], d.L);
+    const T yn = wrap_periodic(y + d.drift * g1 + d.noise_amp * zn[1], d.L);
+    const T rho = (T)2 * gw / ((T)1 + gw);
+    const double an = linear_mass ? a * (1.0 + d.dt * (double)rho - d.dt)
+                                  : a * exp(d.dt * ((double)rho - 1.0));
+    d.xs[0][i] = xn;
+    d.ys[0][i] = yn;
+    d.as[0][i] = an;
+    if (src_set) d.ids[0][i] = pid;
+    if (isfinite(an) && isfinite((double)xn) && isfinite((double)yn)) {
+      dg.sum[0] += an;
+      acc_min(dg, D_MIN_A, an);
+      acc_min(dg, D_MAX_A, an);
+    } else {
+      dg.cnt[0] += 1;
+    }
+    deposit2(d.ubar, acc, make_stencil2(xn, yn, d.inv_h, N), rg, use_region, N,
+             (T)an * d.inv_h3);
+  }
+  if (use_region) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < kR2sq; e += kThreads) {
+      const double v = acc[e];
+      if (v != 0.0) {
+        const int ry = e % kR2, rx = e / kR2;
+        unsafeAtomicAdd(&d.ubar[(int64_t)((rg.o[0] + rx) & (N - 1)) * N +
+                                ((rg.o[1] + ry) & (N - 1))],
+                        (T)v);
+      }
+    }
+  }
+  if (!deposit_only) acc_flush(dg, diag_stripe(d));
+}
+
 // ---- binning ----------------------------------------------------------------------------
 // Tile of every particle of set 0 and its rank among the particles of that tile.  A block
 // takes kBinChunk consecutive particles: wavefronts aggregate equal tiles (one LDS atomic per
@@ -458,7 +637,7 @@ constexpr int kHash = 512;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr uint32_t kGlobalFlag = 0x80000000u;
 
-template <typename T>
+template <typename T, int DIM>
 __global__ void __launch_bounds__(kThreads) k_bin_count(Batch<T> bt) {
   int lb;
   const int s = find_sim(bt, K_SCOUNT, lb);
@@ -479,10 +658,16 @@ __global__ void __launch_bounds__(kThreads) k_bin_count(Batch<T> bt) {
     const bool valid = i < d.P;
     uint32_t tile = 0;
     if (valid) {
-      const Stencil<T> st = make_stencil(d.xs[0][i], d.ys[0][i], d.zs[0][i], d.inv_h, N);
-      const int tx = st.c[0] / kTile, ty = st.c[1] / kTile, tz = st.c[2] / kTile;
-      tile = (uint32_t)(((tx < nt ? tx : nt - 1) * nt + (ty < nt ? ty : nt - 1)) * nt +
-                        (tz < nt ? tz : nt - 1));
+      if (DIM == 2) {
+        const Stencil<T> st = make_stencil2(d.xs[0][i], d.ys[0][i], d.inv_h, N);
+        const int tx = st.c[0] / kTile2, ty = st.c[1] / kTile2;
+        tile = (uint32_t)((tx < nt ? tx : nt - 1) * nt + (ty < nt ? ty : nt - 1));
+      } else {
+        const Stencil<T> st = make_stencil(d.xs[0][i], d.ys[0][i], d.zs[0][i], d.inv_h, N);
+        const int tx = st.c[0] / kTile, ty = st.c[1] / kTile, tz = st.c[2] / kTile;
+        tile = (uint32_t)(((tx < nt ? tx : nt - 1) * nt + (ty < nt ? ty : nt - 1)) * nt +
+                          (tz < nt ? tz : nt - 1));
+      }
     }
     tiles[j] = tile;
     slot[j] = kEmpty;
@@ -586,7 +771,7 @@ __global__ void __launch_bounds__(kThreads) k_bin_scan(Batch<T> bt) {
   }
 }
 
-template <typename T>
+template <typename T, int DIM>
 __global__ void __launch_bounds__(kThreads) k_bin_scatter(Batch<T> bt) {
   int lb;
   const int s = find_sim(bt, K_SSCATTER, lb);
@@ -596,7 +781,7 @@ __global__ void __launch_bounds__(kThreads) k_bin_scatter(Batch<T> bt) {
   const uint32_t dst = d.toff[d.key[2 * i]] + d.key[2 * i + 1];
   d.xs[1][dst] = d.xs[0][i];
   d.ys[1][dst] = d.ys[0][i];
-  d.zs[1][dst] = d.zs[0][i];
+  if (DIM == 3) d.zs[1][dst] = d.zs[0][i];
   d.as[1][dst] = d.as[0][i];
   d.ids[1][dst] = d.ids[0][i];
 }
@@ -608,23 +793,37 @@ size_t particle_lds_bytes() {
 
 template <typename T>
 void launch_particles(const Batch<T>& b, int nblk, int src_set, int deposit_only, int order,
-                      hipStream_t st) {
+                      int dim, hipStream_t st) {
   if (nblk <= 0) return;
+  if (dim == 2) {
+    hipLaunchKernelGGL(k_particles2<T>, dim3(nblk), dim3(kThreads),
+                       kR2sq * (sizeof(vec4<T>) + sizeof(double)), st, b, src_set, deposit_only);
+    return;
+  }
   auto kern = order == 4 ? k_particles<T, 4> : k_particles<T, 2>;
   const size_t lds = order == 4 ? particle_lds_bytes<T, 4>() : particle_lds_bytes<T, 2>();
   hipLaunchKernelGGL(kern, dim3(nblk), dim3(kThreads), lds, st, b, src_set, deposit_only);
 }
 template <typename T>
-void launch_binning(const Batch<T>& b, const int* tot, int nsims, hipStream_t st) {
-  if (tot[K_SCOUNT] > 0)
-    hipLaunchKernelGGL(k_bin_count<T>, dim3(tot[K_SCOUNT]), dim3(kThreads), 0, st, b);
+void launch_binning(const Batch<T>& b, const int* tot, int nsims, int dim, hipStream_t st) {
+  if (tot[K_SCOUNT] > 0) {
+    if (dim == 2)
+      hipLaunchKernelGGL((k_bin_count<T, 2>), dim3(tot[K_SCOUNT]), dim3(kThreads), 0, st, b);
+    else
+      hipLaunchKernelGGL((k_bin_count<T, 3>), dim3(tot[K_SCOUNT]), dim3(kThreads), 0, st, b);
+  }
   hipLaunchKernelGGL(k_bin_scan<T>, dim3(tot[K_SSCAN]), dim3(kThreads), 0, st, b);
-  if (tot[K_SSCATTER] > 0)
-    hipLaunchKernelGGL(k_bin_scatter<T>, dim3(tot[K_SSCATTER]), dim3(kThreads), 0, st, b);
+  if (tot[K_SSCATTER] > 0) {
+    if (dim == 2)
+      hipLaunchKernelGGL((k_bin_scatter<T, 2>), dim3(tot[K_SSCATTER]), dim3(kThreads), 0, st, b);
+    else
+      hipLaunchKernelGGL((k_bin_scatter<T, 3>), dim3(tot[K_SSCATTER]), dim3(kThreads), 0, st, b);
+  }
 }
 // raise the dynamic LDS limit of the particle kernel of this order (call outside capture)
 template <typename T>
-void configure_particles(int order) {
+void configure_particles(int order, int dim) {
+  if (dim == 2) return;  // its region fits the default limit
   if (order == 4)
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_particles<T, 4>),
                               hipFuncAttributeMaxDynamicSharedMemorySize,
@@ -634,12 +833,13 @@ void configure_particles(int order) {
                               hipFuncAttributeMaxDynamicSharedMemorySize,
                               (int)particle_lds_bytes<T, 2>());
 }
-template void configure_particles<double>(int);
-template void configure_particles<float>(int);
+template void configure_particles<double>(int, int);
+template void configure_particles<float>(int, int);
 
-template void launch_particles<double>(const Batch<double>&, int, int, int, int, hipStream_t);
-template void launch_particles<float>(const Batch<float>&, int, int, int, int, hipStream_t);
-template void launch_binning<double>(const Batch<double>&, const int*, int, hipStream_t);
-template void launch_binning<float>(const Batch<float>&, const int*, int, hipStream_t);
+template void launch_particles<double>(const Batch<double>&, int, int, int, int, int,
+                                       hipStream_t);
+template void launch_particles<float>(const Batch<float>&, int, int, int, int, int, hipStream_t);
+template void launch_binning<double>(const Batch<double>&, const int*, int, int, hipStream_t);
+template void launch_binning<float>(const Batch<float>&, const int*, int, int, hipStream_t);
 
 }  // namespace sipf

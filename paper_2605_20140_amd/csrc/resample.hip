@@ -127,7 +127,7 @@ __global__ void __launch_bounds__(kRsThreads)
     const double a = a0[e];
     x1[p] = x0[e];
     y1[p] = y0[e];
-    z1[p] = z0[e];
+    if (z0) z1[p] = z0[e];  // no z coordinate in 2D
     a1[p] = a;
     if (!(a >= 0.0) || !isfinite(a)) {
       bad |= RS_BAD_VALUE;
@@ -361,7 +361,7 @@ __global__ void __launch_bounds__(kRsThreads)
   }
   x0[i] = x1[src];
   y0[i] = y1[src];
-  z0[i] = z1[src];
+  if (z0) z0[i] = z1[src];
   a0s[i] = __longlong_as_double((long long)rs[RS_A0]);
   id0[i] = (uint32_t)i;
 }
@@ -380,9 +380,10 @@ size_t resample_scratch_words(int64_t P) {
 template <typename T>
 void launch_resample_stats(const SimDev<T>& d, unsigned long long* rs, hipStream_t st) {
   const int64_t P = d.P;
+  const bool z = d.dim == 3;
   hipLaunchKernelGGL(k_rs_unsort<T>, dim3(grid_for(P)), dim3(kRsThreads), 0, st, d.xs[0],
-                     d.ys[0], d.zs[0], d.as[0], d.ids[0], d.xs[1], d.ys[1], d.zs[1], d.as[1], P,
-                     rs);
+                     d.ys[0], z ? d.zs[0] : nullptr, d.as[0], d.ids[0], d.xs[1], d.ys[1],
+                     z ? d.zs[1] : nullptr, d.as[1], P, rs);
   hipLaunchKernelGGL(k_rs_sum, dim3(grid_for(P)), dim3(kRsThreads), 0, st, d.as[1], P, rs);
   hipLaunchKernelGGL(k_rs_mean, dim3(1), dim3(64), 0, st, P, rs);
 }
@@ -397,9 +398,11 @@ void launch_resample_apply(const SimDev<T>& d, unsigned long long* rs, hipStream
   hipLaunchKernelGGL(k_rs_offsets, dim3(1), dim3(kOffThreads), 0, st, nb, rs);
   hipLaunchKernelGGL(k_rs_prefix, dim3(nb), dim3(kRsThreads), 0, st, d.as[1], P, rs, kex, rin);
   const int ng = (int)((P + kRsThreads - 1) / kRsThreads);
+  const bool z = d.dim == 3;
   hipLaunchKernelGGL(k_rs_gather<T>, dim3(ng), dim3(kRsThreads), 0, st, d.xs[1], d.ys[1],
-                     d.zs[1], kex, rin, P, rs, d.step, d.seed_lo, d.seed_hi, d.sim_lo,
-                     d.sim_hi, d.xs[0], d.ys[0], d.zs[0], d.as[0], d.ids[0]);
+                     z ? d.zs[1] : nullptr, kex, rin, P, rs, d.step, d.seed_lo, d.seed_hi,
+                     d.sim_lo, d.sim_hi, d.xs[0], d.ys[0], z ? d.zs[0] : nullptr, d.as[0],
+                     d.ids[0]);
 }
 
 template void launch_resample_stats<double>(const SimDev<double>&, unsigned long long*,

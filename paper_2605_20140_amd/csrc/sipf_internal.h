@@ -20,6 +20,7 @@ constexpr int kThreads = 256;  // threads per block of every kernel (4 wavefront
 // kChunk particles of one tile and keeps the tile's nodes, plus the nodes its stencils reach
 // and a drift margin, in LDS.
 constexpr int kTile = 8;
+constexpr int kTile2 = 16;  // square tiles of the two-dimensional form
 constexpr int kChunk = 4096;
 constexpr int kBinBlock = 2048;  // particles per block of the binning count kernel
 
@@ -93,7 +94,11 @@ struct SimDev {
   int use_lowpass;
   int ntile1;         // tiles per axis, max(1, N / kTile)
   int ntiles;         // ntile1^3
-  int use_region;     // LDS tile regions (N >= 2 kTile, so a region never aliases itself)
+  int use_region;     // LDS tile regions (N >= 2 tile sides, so a region never aliases itself)
+  int dim;            // 3, or 2 for the two-dimensional form (z arrays unused)
+  int64_t nrows;      // rows of N nodes along the last axis: N^(dim-1)
+  int64_t G;          // grid nodes N^dim
+  T inv_nd;           // 1 / N^dim
   int deposit_order;  // 2: trilinear assignment; 4: fourth-order assignment
   // particles, structure of arrays; set 0 is the state, set 1 receives the binned copy
   T *xs[2], *ys[2], *zs[2];
@@ -200,9 +205,9 @@ void launch_plane(const Batch<T>& b, int nblk, int lg, hipStream_t s, int config
 template <typename T> bool plane_fits(int lg);
 template <typename T>
 void launch_particles(const Batch<T>& b, int nblk, int src_set, int deposit_only, int order,
-                      hipStream_t s);
+                      int dim, hipStream_t s);
 template <typename T>
-void configure_particles(int order);
+void configure_particles(int order, int dim);
 
 // ---- residual resampling (resample.hip) ---------------------------------------------------
 // words (uint64) at the start of the resampling scratch area
@@ -225,7 +230,8 @@ void launch_resample_stats(const SimDev<T>& d, unsigned long long* rs, hipStream
 // copy counts, prefix sums and the resampled list into set 0 (particle order)
 template <typename T>
 void launch_resample_apply(const SimDev<T>& d, unsigned long long* rs, hipStream_t s);
-template <typename T> void launch_binning(const Batch<T>& b, const int* tot, int nsims, hipStream_t s);
+template <typename T>
+void launch_binning(const Batch<T>& b, const int* tot, int nsims, int dim, hipStream_t s);
 template <typename T> void launch_diag_init(const Batch<T>& b, int nblk, int nsims, hipStream_t s);
 template <typename T> void launch_diag_u(const Batch<T>& b, int nblk, int nsims, hipStream_t s);
 template <typename T> void launch_finalize(const Batch<T>& b, int nsims, hipStream_t s);

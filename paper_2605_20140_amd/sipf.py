@@ -36,7 +36,7 @@ STAGES = ("zfwd", "yfwd", "xpass", "yinv", "zinv", "particles", "finalize", "bin
 
 class Params(ctypes.Structure):
     _fields_ = [
-        ("L", ctypes.c_double), ("N", ctypes.c_int32), ("reserved0", ctypes.c_int32),
+        ("L", ctypes.c_double), ("N", ctypes.c_int32), ("dim", ctypes.c_int32),
         ("P", ctypes.c_int64), ("dt", ctypes.c_double),
         ("D_u", ctypes.c_double), ("chi", ctypes.c_double), ("D_m", ctypes.c_double),
         ("D_w", ctypes.c_double), ("alpha", ctypes.c_double), ("beta", ctypes.c_double),
@@ -116,8 +116,8 @@ def _dptr(a):
 
 def make_params(N, P, dt, L=1.0, D_u=1e-3, chi=5e-3, D_m=1e-3, D_w=5e-3, alpha=10.0,
                 beta=0.5, gamma=0.5, seed=0, sim_id=0, step0=0, precision=SIPF_FP64,
-                deposit_order=2, flags=0, resort_every=0, H0=0.0, **_ignored):
-    return Params(L=L, N=N, reserved0=0, P=P, dt=dt, D_u=D_u, chi=chi, D_m=D_m, D_w=D_w,
+                deposit_order=2, flags=0, resort_every=0, H0=0.0, dim=0, **_ignored):
+    return Params(L=L, N=N, dim=dim, P=P, dt=dt, D_u=D_u, chi=chi, D_m=D_m, D_w=D_w,
                   alpha=alpha, beta=beta, gamma=gamma, seed=seed, sim_id=sim_id, step0=step0,
                   precision=precision, deposit_order=deposit_order, flags=flags,
                   resort_every=resort_every, H0=H0)
@@ -132,24 +132,26 @@ def state_bytes(params):
 class Simulation:
     """One resident simulation: workspace tensor + library handle.
 
-    X0: (P, 3) float64 positions; a0: (P,) masses; v0, m0, w0: (N, N, N) fields.
+    X0: (P, d) float64 positions; a0: (P,) masses; v0, m0, w0: (N,)*d fields; d = 3, or 2
+    when params.dim == 2.
     """
 
     def __init__(self, params, X0, a0, v0, m0, w0, device="cuda", stream=None):
         import torch
         self.params = params
         N, P = params.N, params.P
+        self.d = d = 2 if params.dim == 2 else 3
         nbytes = state_bytes(params)
         self.workspace = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
         if stream is None:
             stream = torch.cuda.current_stream(self.workspace.device)
         self.stream = stream
-        X0 = np.ascontiguousarray(np.asarray(X0, dtype=np.float64).reshape(P, 3).T)
+        X0 = np.ascontiguousarray(np.asarray(X0, dtype=np.float64).reshape(P, d).T)
         a0 = np.ascontiguousarray(a0, dtype=np.float64)
         v0 = np.ascontiguousarray(v0, dtype=np.float64).reshape(-1)
         m0 = np.ascontiguousarray(m0, dtype=np.float64).reshape(-1)
         w0 = np.ascontiguousarray(w0, dtype=np.float64).reshape(-1)
-        assert v0.size == m0.size == w0.size == N ** 3 and a0.size == P
+        assert v0.size == m0.size == w0.size == N ** d and a0.size == P
         h = ctypes.c_void_p()
         _check(lib().sipf_init(ctypes.byref(params), ctypes.c_void_p(self.workspace.data_ptr()),
                                nbytes, ctypes.c_void_p(stream.cuda_stream),
@@ -161,31 +163,32 @@ class Simulation:
         _check(lib().sipf_step(self.handle, int(nsteps)))
 
     def fields(self, particles=True):
-        N, P = self.params.N, self.params.P
-        v = np.empty(N ** 3)
-        m = np.empty(N ** 3)
-        w = np.empty(N ** 3)
-        X = np.empty(3 * P) if particles else None
+        N, P, d = self.params.N, self.params.P, self.d
+        v = np.empty(N ** d)
+        m = np.empty(N ** d)
+        w = np.empty(N ** d)
+        X = np.empty(d * P) if particles else None
         a = np.empty(P) if particles else None
         d = Diag()
         rc = lib().sipf_fields(self.handle, _dptr(v), _dptr(m), _dptr(w), _dptr(X), _dptr(a),
                                ctypes.byref(d))
-        out = dict(v=v.reshape(N, N, N), m=m.reshape(N, N, N), w=w.reshape(N, N, N),
+        shape = (N,) * self.d
+        out = dict(v=v.reshape(shape), m=m.reshape(shape), w=w.reshape(shape),
                    diag=d.as_dict(), rc=rc)
         if particles:
-            out["X"] = X.reshape(3, P).T.copy()
+            out["X"] = X.reshape(self.d, P).T.copy()
             out["a"] = a
         if rc not in (0, -4):
             _check(rc)
         return out
 
     def aux(self):
-        N = self.params.N
-        u = np.empty(N ** 3)
-        g = np.empty(3 * N ** 3)
+        N, d = self.params.N, self.d
+        G = N ** d
+        u = np.empty(G)
+        g = np.empty(d * G)
         _check(lib().sipf_aux(self.handle, _dptr(u), _dptr(g)))
-        return u.reshape(N, N, N), [g[j * N ** 3:(j + 1) * N ** 3].reshape(N, N, N)
-                                    for j in range(3)]
+        return u.reshape((N,) * d), [g[j * G:(j + 1) * G].reshape((N,) * d) for j in range(d)]
 
     def set_stream(self, stream):
         """Move the simulation's work to a torch stream (queued work is ordered before)."""
