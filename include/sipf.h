@@ -73,8 +73,7 @@ extern "C" {
 /* Parameters (eq. haptotaxis-system, eq. g_t: D = diag(0, D_m, D_w), R = diag(0, beta, 1)). */
 typedef struct {
   double L;              /* period of the cube, > 0                                      */
-  int32_t N;             /* grid nodes per axis: power of two in [4, 512] (2D: [4, 1024],   *
-                          * float64 [4, 512])                                              */
+  int32_t N;             /* grid nodes per axis: power of two in [4, 512] (2D: [4, 1024])  */
   int32_t dim;           /* 0 or 3: the 3D system; 2: the paper's two-dimensional form     *
                           * (grids N^2, positions 2P, bilinear transfers, deposit_order 2, *
                           * two Wiener components: the first two normals of the block)    */

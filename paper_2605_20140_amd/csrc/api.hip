@@ -58,9 +58,8 @@ int validate_params(const sipf_params* p) {
   if (p->dim != 0 && p->dim != 2 && p->dim != 3)
     return fail(SIPF_EINVAL, "dim must be 0 or 3 (three-dimensional) or 2");
   if (p->dim == 2) {
-    const int nmax = p->precision == SIPF_FP64 ? 512 : 1024;
-    if (!(p->N >= 4 && p->N <= nmax && is_pow2(p->N)))
-      return fail(SIPF_EINVAL, "2D: N must be a power of two in [4, 1024] (float64: 512)");
+    if (!(p->N >= 4 && p->N <= 1024 && is_pow2(p->N)))
+      return fail(SIPF_EINVAL, "2D: N must be a power of two in [4, 1024]");
     if (p->deposit_order != 2)
       return fail(SIPF_EINVAL, "2D: only the bilinear deposit (deposit_order 2)");
   } else if (!(p->N >= 4 && p->N <= 512 && is_pow2(p->N))) {
@@ -267,7 +266,7 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   d.log2N = lg;
   d.P = P;
   const int E = elems_per_block<T>();
-  d.rows_per_blk = (int)std::min<int64_t>(d.nrows, E / N);
+  d.rows_per_blk = (int)std::min<int64_t>(d.nrows, std::max(2, E / N));
   d.lines_per_blk = E / N;
   d.cols_per_blk = std::min(N, E / N);
   d.flags = (int)p.flags;
@@ -285,6 +284,7 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   d.gz_scale = (T)(2.0 * M_PI / p.L / (dim == 3 && !d.use_plane ? (double)N * N : (double)N));
   if (d.use_plane) launch_plane<T>(Batch<T>{}, 0, lg, nullptr, 1);  // raise its LDS limit
   configure_particles<T>(p.deposit_order, dim);
+  configure_fft<T>(lg);
   d.dt = p.dt;
   d.D_u = p.D_u;
   d.chi = p.chi;

@@ -48,7 +48,8 @@ void block_counts(const SimDev<T>& d, int c[K_COUNT]) {
   const int64_t N = d.N;
   const int64_t H = N / 2 + 1;
   const int64_t lines = H * N;
-  const int64_t Bl = d.lines_per_blk;
+  // y passes (3D only; there N <= 512, so at least two lines per block)
+  const int64_t Bl = d.lines_per_blk > 1 ? d.lines_per_blk : 2;
   const int64_t ny = (lines + Bl - 1) / Bl;
   const int64_t ny2 = (lines + Bl / 2 - 1) / (Bl / 2);
   c[K_ZFWD] = (int)(d.nrows / d.rows_per_blk);
@@ -730,7 +731,7 @@ size_t fft_lds_bytes(int kind, int lg) {
   const size_t LS = (size_t)row_stride_rt(lg);
   const size_t c = sizeof(cplx<T>);
   const size_t tw = (size_t)(N / 2) * c;
-  const size_t B = (size_t)std::min(N * N, E / N);  // rows per block (z passes)
+  const size_t B = (size_t)std::min(N * N, std::max(2, E / N));  // rows per block (z passes)
   const size_t Bl = (size_t)(E / N);                // lines per block (y passes)
   const size_t Bx = (size_t)std::min(N, E / N);     // columns per block (x pass)
   switch (kind) {
@@ -745,6 +746,21 @@ size_t fft_lds_bytes(int kind, int lg) {
 }
 template size_t fft_lds_bytes<double>(int, int);
 template size_t fft_lds_bytes<float>(int, int);
+
+// Raise the dynamic LDS limit of the row passes where they need more than the default 64 KiB
+// (float64 rows of 1024 nodes, two per block).  Call once, outside capture.
+template <typename T>
+void configure_fft(int lg) {
+  if (lg != 10) return;
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_zfwd<T, 10>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)fft_lds_bytes<T>(K_ZFWD, 10));
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_zinv<T, 10>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)fft_lds_bytes<T>(K_ZINV, 10));
+}
+template void configure_fft<double>(int);
+template void configure_fft<float>(int);
 
 // Host-side dispatch: one kernel instantiation per log2 N, so each carries only the
 // registers its own transform length needs.

@@ -203,6 +203,7 @@ template <typename T> void launch_zinv(const Batch<T>& b, int nblk, int lg, hipS
 template <typename T>
 void launch_plane(const Batch<T>& b, int nblk, int lg, hipStream_t s, int configure);
 template <typename T> bool plane_fits(int lg);
+template <typename T> void configure_fft(int lg);
 template <typename T>
 void launch_particles(const Batch<T>& b, int nblk, int src_set, int deposit_only, int order,
                       int dim, hipStream_t s);

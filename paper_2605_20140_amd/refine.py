@@ -1,16 +1,18 @@
-"""Grid-refinement study of the paper's three-dimensional example (Sec. numerical
-experiments, 3D simulation): the example is run to T = 6 at H = N = 2^4 .. 2^8 with the same
-particles and the same Wiener increments, and each run's cell density at T is compared with
-the finest run's.  The convergence order is the slope of log2 E against log2 N.
+"""Grid-refinement studies of the paper's examples (Sec. numerical experiments): the
+three-dimensional example run to T = 6 at H = N = 2^4 .. 2^8, and the two-dimensional one at
+H = 2^6 .. 2^10, each with the same particles and the same Wiener increments at every
+resolution; each run's cell density at T is compared with the finest run's.  The
+convergence order is the slope of log2 E against log2 N.
 
-Error measure (the paper's, stated for its 2D example and used here in 3D): every density
-is downsampled by Fourier truncation to a 16^3 grid and
-    E = ||u_1 - u_2||_2 / max(||u_1||_2, ||u_2||_2),  ||u||_2 = (L / 16)^(3/2) (sum u_ijk^2)^(1/2).
+Error measure (the paper's, stated for its 2D example and used in 3D by analogy): every
+density is downsampled by Fourier truncation to a 16^d grid and
+    E = ||u_1 - u_2||_2 / max(||u_1||_2, ||u_2||_2),  ||u||_2 = (L / 16)^(d/2) (sum u^2)^(1/2).
 The density of a run is its particle-to-grid deposit ubar on its own grid.  The truncation
 keeps the integer frequencies |q_j| <= 7 (the 16-point Nyquist mode is dropped so the result
 stays real).
 
-    python -m paper_2605_20140_amd.refine [--steps 6000] [--particles 4194304] [--fp32]
+    python -m paper_2605_20140_amd.refine [--dim 3|2] [--steps 6000] [--particles 4194304]
+                                          [--grids 16,32,64,128,256] [--fp32]
 """
 import argparse
 import json
@@ -27,29 +29,29 @@ COARSE = 16
 
 
 def downsample(u, n=COARSE):
-    """Fourier truncation of an (N, N, N) periodic grid field to (n, n, n), keeping values."""
-    N = u.shape[0]
+    """Fourier truncation of an (N,)*d periodic grid field to (n,)*d, keeping values."""
+    N, d = u.shape[0], u.ndim
     F = np.fft.fftn(u)
     h = n // 2
     src = np.r_[0:h, N - h + 1:N]
     dst = np.r_[0:h, n - h + 1:n]
-    G = np.zeros((n, n, n), dtype=complex)
-    G[np.ix_(dst, dst, dst)] = F[np.ix_(src, src, src)]
-    return np.real(np.fft.ifftn(G)) * (n / N) ** 3
+    G = np.zeros((n,) * d, dtype=complex)
+    G[np.ix_(*([dst] * d))] = F[np.ix_(*([src] * d))]
+    return np.real(np.fft.ifftn(G)) * (n / N) ** d
 
 
 def norm(u, L):
-    return (L / u.shape[0]) ** 1.5 * math.sqrt(float((u * u).sum()))
+    return (L / u.shape[0]) ** (u.ndim / 2.0) * math.sqrt(float((u * u).sum()))
 
 
 def rel_error(u1, u2, L):
     return norm(u1 - u2, L) / max(norm(u1, L), norm(u2, L))
 
 
-def run_one(N, P, steps, precision, log=None):
-    ic = W.paper3d_initial_state(N, P=P)
+def run_one(N, P, steps, precision, log=None, dim=3):
+    ic = (W.paper3d_initial_state if dim == 3 else W.paper2d_initial_state)(N, P=P)
     prm = dict(ic["params"])
-    p = sipf.make_params(precision=precision, **prm)
+    p = sipf.make_params(precision=precision, **prm)  # prm carries dim
     t0 = time.perf_counter()
     sim = sipf.Simulation(p, ic["X0"], ic["a0"], ic["v0"], ic["m0"], ic["w0"])
     del ic
@@ -69,11 +71,15 @@ def run_one(N, P, steps, precision, log=None):
     return downsample(u), diag, dict(init_s=t1 - t0, run_s=t2 - t1)
 
 
-def study(Ns=(16, 32, 64, 128, 256), P=1 << 22, steps=6000, precision=0, log=None):
+GRIDS = {3: (16, 32, 64, 128, 256), 2: (64, 128, 256, 512, 1024)}
+
+
+def study(Ns=None, P=1 << 22, steps=6000, precision=0, log=None, dim=3):
     L = W.PAPER3D_PARAMS["L"]
+    Ns = GRIDS[dim] if Ns is None else Ns
     dens, info = {}, {}
     for N in Ns:
-        dens[N], diag, tm = run_one(N, P, steps, precision, log)
+        dens[N], diag, tm = run_one(N, P, steps, precision, log, dim)
         info[N] = dict(mass_particles=diag["mass_particles"], min_v=diag["min_v"],
                        n_nan=diag["n_nan"], **tm)
     ref = max(Ns)
@@ -81,7 +87,8 @@ def study(Ns=(16, 32, 64, 128, 256), P=1 << 22, steps=6000, precision=0, log=Non
     xs = np.log2([N for N in errs])
     ys = np.log2([errs[N] for N in errs])
     slope = float(np.polyfit(xs, ys, 1)[0]) if len(xs) >= 2 else None
-    return dict(errors={int(k): v for k, v in errs.items()}, slope=slope, reference_N=ref,
+    return dict(dim=dim, errors={int(k): v for k, v in errs.items()}, slope=slope,
+                reference_N=ref,
                 runs={int(k): v for k, v in info.items()}, steps=steps, particles=P,
                 precision="f32" if precision else "f64")
 
@@ -90,12 +97,13 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
     ap.add_argument("--steps", type=int, default=W.PAPER3D_PARAMS["steps"])
     ap.add_argument("--particles", type=int, default=1 << 22)
-    ap.add_argument("--grids", type=str, default="16,32,64,128,256")
+    ap.add_argument("--grids", type=str, default=None, help="default: 16..256 (3D), 64..1024 (2D)")
+    ap.add_argument("--dim", type=int, default=3, choices=(2, 3))
     ap.add_argument("--fp32", action="store_true")
     a = ap.parse_args(argv)
-    Ns = tuple(int(x) for x in a.grids.split(","))
+    Ns = tuple(int(x) for x in a.grids.split(",")) if a.grids else None
     res = study(Ns, a.particles, a.steps, 1 if a.fp32 else 0,
-                log=lambda s: print(s, file=sys.stderr, flush=True))
+                log=lambda s: print(s, file=sys.stderr, flush=True), dim=a.dim)
     print(json.dumps(res))
 
 

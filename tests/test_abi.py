@@ -44,7 +44,6 @@ def _p(**kw):
                                  dict(flags=0x80 | 0x100), dict(flags=0x4000),
                                  dict(H0=-1.0), dict(flags=0x100), dict(dim=1), dict(dim=4),
                                  dict(dim=2, N=2048, precision=1),
-                                 dict(dim=2, N=1024, precision=0),
                                  dict(dim=2, deposit_order=4)])
 def test_state_bytes_rejects_invalid_params(bad):
     with pytest.raises(sipf.SipfError) as e:
@@ -121,12 +120,12 @@ def test_null_handles():
 
 
 def test_two_dimensional_state_bytes():
-    """dim = 2: N^2 grids and two coordinates per particle; N up to 1024 in float32."""
+    """dim = 2: N^2 grids and two coordinates per particle; N up to 1024."""
     b2 = sipf.state_bytes(_p(N=64, P=1 << 16, dim=2))
     b3 = sipf.state_bytes(_p(N=64, P=1 << 16))
     assert b2 < b3
     N, P = 64, 1 << 16
     expect = P * (2 * (16 + 12) + 8) + N ** 2 * 8 * 8 + 5 * (N // 2 + 1) * N * 16
     assert expect <= b2 < expect + 64 * 1024
-    assert sipf.state_bytes(_p(N=1024, P=100, dim=2, precision=1)) > 0
+    assert sipf.state_bytes(_p(N=1024, P=100, dim=2)) > 0
     assert sipf.state_bytes(_p(N=512, P=100, dim=3)) == sipf.state_bytes(_p(N=512, P=100, dim=0))

@@ -115,3 +115,12 @@ def test_2d_batch_rejected():
     with pytest.raises(sipf.SipfError):
         sipf.step_batch([sim], 1)
     sim.close()
+
+
+def test_2d_fp64_largest_grid():
+    """1024^2 in float64: two rows per block in the row passes (raised LDS limit)."""
+    ic = W.blob2d_initial_state(N=1024, P=1 << 16)
+    out, _, g, ref, aux = _run(ic, 2)
+    compare_state(out, ref, TOL64)
+    for j in range(2):
+        assert max(rel_errors(g[j], aux["grad"][j])) < 1e-11, j

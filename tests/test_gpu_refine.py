@@ -1,4 +1,4 @@
-"""Grid refinement of the paper's 3D example (Sec. numerical experiments, 3D simulation) on
+"""Grid refinement of the paper's 3D and 2D examples (Sec. numerical experiments, 3D simulation) on
 the GPU: H = 2^4 .. 2^7 against H = 2^8, P = 2^22, tau = 1e-3 to T = 6, float64.  The paper
 measures a slope of -1.407 for log2 E against log2 H (theory: -16/13); this run measured
 -1.64.  The check is a band around both, plus monotone errors and a finite state."""
@@ -15,5 +15,17 @@ def test_paper3d_refinement_slope():
     e = res["errors"]
     assert e[16] > e[32] > e[64] > e[128] > 0
     assert -2.0 < res["slope"] < -1.1
+    for run in res["runs"].values():
+        assert run["n_nan"] == 0 and run["min_v"] >= 0
+
+
+def test_paper2d_refinement_slope():
+    """The paper's 2D example: H = 2^6 .. 2^9 against 2^10, P = 2^22, T = 6, float64.  The
+    paper measures -2.109; this run measured -1.98."""
+    res = R.study(dim=2, log=lambda s: print(s, flush=True))
+    print(res["errors"], res["slope"])
+    e = res["errors"]
+    assert e[64] > e[128] > e[256] > e[512] > 0
+    assert -2.6 < res["slope"] < -1.5
     for run in res["runs"].values():
         assert run["n_nan"] == 0 and run["min_v"] >= 0
