@@ -102,10 +102,10 @@ def copy_calibration():
     assert rc == 0 and bool((dst == 1).all())
 
 
-def run_form(ic, precision, steps, warmup, profile_steps, workload):
+def run_form(ic, precision, steps, warmup, profile_steps, workload, **over):
     import torch
     from paper_2605_20140_amd import sipf
-    prm = ic["params"]
+    prm = dict(ic["params"], **over)
     p = sipf.make_params(precision=precision, **prm)
     torch.cuda.synchronize()
     ti = time.perf_counter()
@@ -130,6 +130,11 @@ def run_form(ic, precision, steps, warmup, profile_steps, workload):
     d = out["diag"]
     s = 4 if precision == 1 else 8
     sb = stage_bytes(prm["N"], prm["P"], s)
+    if prm.get("dim") == 2:
+        return dict(value=prm["P"] * steps / (ms * 1e-3), ms_per_step=ms / steps,
+                    init_s=init_s,
+                    stages={k: round(v / profile_steps, 5) for k, v in stage_ms.items()},
+                    check=dict(n_nan=d["n_nan"], step=d["step"]))
     stages = {}
     for k, tot in stage_ms.items():
         avg = tot / profile_steps  # per step (binning: amortised over its period)
@@ -139,7 +144,8 @@ def run_form(ic, precision, steps, warmup, profile_steps, workload):
     dominant = max(stages, key=lambda k: stages[k]["ms"])
     ach = sb[dominant] / (stages[dominant]["ms"] * 1e-3) / 1e9
     kname = STAGE_KERNEL.get(dominant, (dominant, dominant))[0 if precision == 1 else 1]
-    traffic = measured_traffic(workload, precision) if dominant == "particles" else None
+    traffic = (measured_traffic(workload, precision)
+               if dominant == "particles" and not over else None)
     return dict(
         value=prm["P"] * steps / (ms * 1e-3),
         ms_per_step=ms / steps,
@@ -155,8 +161,8 @@ def run_form(ic, precision, steps, warmup, profile_steps, workload):
     )
 
 
-def cpu_baseline(ic):
-    """FP64 numpy oracle, one step of the same workload on the host (bounded sample)."""
+def cpu_baseline(ic, steps=3):
+    """FP64 numpy oracle, a few steps of the same workload on the host (bounded sample)."""
     from oracle import step as S
     prm = ic["params"]
     op = S.Params(N=prm["N"], dt=prm["dt"], L=prm["L"], D_u=prm["D_u"], chi=prm["chi"],
@@ -164,11 +170,48 @@ def cpu_baseline(ic):
                   gamma=prm["gamma"], seed=prm["seed"])
     st = S.State(ic["X0"], ic["a0"], ic["v0"], ic["m0"], ic["w0"], 0)
     t = time.perf_counter()
-    S.step(st, op)
+    S.run(st, op, steps)
     dt = time.perf_counter() - t
-    return dict(value=prm["P"] / dt, unit="particle-steps/s", cores=1, kind="oracle",
-                sample=f"1 step of the full workload ({prm['N']}^3 grid, {prm['P']} particles), "
-                       "float64 numpy oracle, single thread", seconds=round(dt, 2))
+    return dict(value=prm["P"] * steps / dt, unit="particle-steps/s", cores=1, kind="oracle",
+                sample=f"{steps} steps of the full workload ({prm['N']}^3 grid, {prm['P']} "
+                       "particles), float64 numpy oracle, single thread", seconds=round(dt, 2))
+
+
+def next_rows(ic, steps=50, warmup=5, profile_steps=8):
+    """The rows beyond the plain step, each timed on its own: the fourth-order deposit and
+    the low-pass filter on the benchmark workload (float32), one residual resampling of its
+    particles with log-normal masses, and the paper's 2D example at 1024^2 / 2^22 (float32)."""
+    import numpy as np
+    import torch
+    from paper_2605_20140_amd import sipf, workloads as W
+    out = {}
+    prm = ic["params"]
+    for name, over in (("order4", dict(deposit_order=4)), ("lowpass", dict(H0=prm["N"] / 2.0))):
+        r = run_form(ic, 1, steps, warmup, profile_steps, "", **over)
+        out[name] = dict(value=r["value"], unit="particle-steps/s", ms_per_step=r["ms_per_step"],
+                         particles_ms=r["stages"]["particles"]["ms"],
+                         xpass_ms=r["stages"]["xpass"]["ms"], check=r["check"], **over)
+    # resampling: log-normal masses (the spread a long run accumulates)
+    rng = np.random.Generator(np.random.Philox(7))
+    a0 = W.weighted_masses(prm["P"], 1.0, rng)
+    p = sipf.make_params(precision=1, **prm)
+    sim = sipf.Simulation(p, ic["X0"], a0, ic["v0"], ic["m0"], ic["w0"], device="cuda:0")
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    info = sim.resample()
+    rs_s = time.perf_counter() - t
+    sim.step(2)
+    d = sim.fields(particles=False)["diag"]
+    sim.close()
+    out["resample"] = dict(ms=rs_s * 1e3, particles_per_s=prm["P"] / rs_s, n_stoch=info["n_stoch"],
+                           a0=info["a0"], note="one synchronous call incl. re-binning and "
+                           "deposit, float32 form", check=dict(n_nan=d["n_nan"]))
+    ic2 = W.paper2d_initial_state(1024)
+    r = run_form(ic2, 1, steps, warmup, profile_steps, "")
+    out["paper2d"] = dict(value=r["value"], unit="particle-steps/s",
+                          ms_per_step=r["ms_per_step"], N=1024, P=ic2["params"]["P"],
+                          stages_ms=r["stages"], check=r["check"])
+    return out
 
 
 def served(nreq, budget_gib, seed=4):
@@ -207,6 +250,8 @@ def main():
     ap.add_argument("--profile-steps", type=int, default=24)
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 comparison run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-next-rows", action="store_true",
+                    help="skip the order-4 / low-pass / resampling / 2D measurements")
     ap.add_argument("--served-requests", type=int, default=48,
                     help="requests in the served-mix run (0: skip it)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -228,6 +273,7 @@ def main():
            run_form(ic, 0, args.steps, args.warmup, args.profile_steps, args.workload))
     if args.copy_calibration:
         copy_calibration()
+    nxt = None if args.no_next_rows else next_rows(ic)
     srv = served(args.served_requests, 32) if args.served_requests > 0 else None
     cpu = None if args.no_cpu_baseline else cpu_baseline(ic)
     line = {
@@ -252,6 +298,7 @@ def main():
         "stages": r32["stages"],
         "check": r32["check"],
         "served": srv,
+        "next_rows": nxt,
         "fp64": None if r64 is None else {
             "value": r64["value"], "ms_per_step": r64["ms_per_step"], "dtype": "f64",
             "init_s": r64["init_s"],
