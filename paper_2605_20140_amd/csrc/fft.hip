@@ -63,7 +63,8 @@ void block_counts(const SimDev<T>& d, int c[K_COUNT]) {
     c[K_YFWD] = d.use_plane ? 0 : (int)(3 * ny);
     c[K_XPASS] = d.use_plane ? 0 : (int)((3 + nlp) * H * (N / d.cols_per_blk));
     c[K_YINV] = d.use_plane ? 0 : (int)(3 * ny + ny2);
-    c[K_PLANE] = d.use_plane ? (int)((4 + nlp) * H) : 0;
+    // plane jobs: M, W and one for both V derivatives; with the filter M, W, d1 V, d2 V, V
+    c[K_PLANE] = d.use_plane ? (int)((nlp ? 5 : 3) * H) : 0;
   }
   c[K_ZINV] = c[K_ZFWD];
   const int64_t pb = (d.P + kThreads - 1) / kThreads;
@@ -571,19 +572,58 @@ __global__ void __launch_bounds__(kThreads) k_xpass(Batch<T> bt) {
 
 // ---- plane pass: y, x, multipliers, x^-1, y^-1 on one k3 plane in LDS --------------------
 // Replaces yfwd + xpass + yinv when a k3 plane of a half spectrum (N^2 complex values,
-// contiguous in the S[k3][i1][i2] layout) fits in LDS.  Four jobs per plane: M, W (diffusion
-// multipliers), and from V the x- and y-derivative spectra.  V itself is not written: it
-// stays transformed along z only, and zinv forms the z derivative from it (scale 1/N).  With
-// the low-pass filter a fifth job writes the filtered V plane (x, y round trip undone) into
-// SVg, from which zinv then forms the z derivative.
+// contiguous in the S[k3][i1][i2] layout) fits in LDS.  Three jobs per plane: M, W (2D
+// transforms and the diffusion multipliers), and one that forms both derivative spectra of V
+// with 1D transforms only (x for d1 v, then y for d2 v: a derivative needs only its own
+// axis), so that one block per job and plane fits the chip in a single round.  V itself is
+// not written: it stays transformed along z only, and zinv forms the z derivative from it
+// (scale 1/N).  With the low-pass filter (which needs both axes) the jobs are M, W, d1 V,
+// d2 V with full 2D transforms, and a fifth writes the filtered V plane (x, y round trip
+// undone) into SVg, from which zinv then forms the z derivative.
 template <typename T, int LG>
 __device__ void plane_body(const SimDev<T>& d, int lb, unsigned char* smem) {
   constexpr int N = 1 << LG;
   constexpr int NN = N * N;
   constexpr int NT = kPlaneThreads;
-  const int nj = d.use_lowpass ? 5 : 4;
+  const int nj = d.use_lowpass ? 5 : 3;
   const int kz = lb / nj, job = lb - kz * nj;
   const int64_t off = (int64_t)kz * NN;
+  if (!d.use_lowpass && job == 2) {
+    // d1 v and d2 v need only the transform along their own axis: x round trip for SGx,
+    // then (from a fresh copy of the plane) y round trip for SGy; 1/N^2 undoes the z and
+    // own-axis round trips
+    constexpr int LSv = row_stride<LG>();
+    cplx<T>* Q = reinterpret_cast<cplx<T>*>(smem);
+    cplx<T>* twv = Q + N * LSv;
+    for (int k = threadIdx.x; k < (N >> 1); k += NT) twv[k] = d.tw[k];
+    const T c = d.two_pi_over_L * d.inv_n2;
+    for (int pass = 0; pass < 2; ++pass) {
+      const cplx<T>* src = d.SV + off;
+      for (int e = threadIdx.x; e < NN; e += NT) Q[(e >> LG) * LSv + (e & (N - 1))] = src[e];
+      __syncthreads();
+      if (pass == 0)
+        line_fwd<T, LG, true, NT>(Q, N, 1, LSv, twv);  // along i1
+      else
+        line_fwd<T, LG, false, NT>(Q, N, LSv, 1, twv);  // along i2
+      for (int e = threadIdx.x; e < NN; e += NT) {
+        const int i1 = e >> LG, i2 = e & (N - 1);
+        const int q = deriv_freq(ufpos<LG>(pass == 0 ? i1 : i2), N);
+        const int pe = i1 * LSv + i2;
+        const cplx<T> val = Q[pe];
+        const T kk = c * (T)q;
+        Q[pe] = cplx<T>{-kk * val.y, kk * val.x};
+      }
+      __syncthreads();
+      if (pass == 0)
+        line_inv<T, LG, true, NT>(Q, N, 1, LSv, twv);
+      else
+        line_inv<T, LG, false, NT>(Q, N, LSv, 1, twv);
+      cplx<T>* dst = (pass == 0 ? d.SGx : d.SGy) + off;
+      for (int e = threadIdx.x; e < NN; e += NT) dst[e] = Q[(e >> LG) * LSv + (e & (N - 1))];
+      __syncthreads();
+    }
+    return;
+  }
   const cplx<T>* src = (job == 0 ? d.SM : (job == 1 ? d.SW : d.SV)) + off;
   cplx<T>* dst =
       (job == 0 ? d.SM : (job == 1 ? d.SW : (job == 2 ? d.SGx : (job == 3 ? d.SGy : d.SVg)))) +
