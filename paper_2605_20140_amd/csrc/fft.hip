@@ -199,7 +199,7 @@ struct TaskMap {
 
 // forward transforms: natural order -> fpos order
 template <typename T, int LG, bool LINE_FAST = false, int NT = kThreads>
-__device__ void line_fwd(cplx<T>* buf, int nlines, int ls, int es, const cplx<T>* tw) {
+__device__ __forceinline__ void line_fwd(cplx<T>* buf, int nlines, int ls, int es, const cplx<T>* tw) {
   using S = Split<LG>;
   for (int t = threadIdx.x; t < nlines * S::N1; t += NT) {
     int line, n1;
@@ -231,7 +231,7 @@ __device__ void line_fwd(cplx<T>* buf, int nlines, int ls, int es, const cplx<T>
 
 // inverse (unnormalised) transforms: fpos order -> natural order
 template <typename T, int LG, bool LINE_FAST = false, int NT = kThreads>
-__device__ void line_inv(cplx<T>* buf, int nlines, int ls, int es, const cplx<T>* tw) {
+__device__ __forceinline__ void line_inv(cplx<T>* buf, int nlines, int ls, int es, const cplx<T>* tw) {
   using S = Split<LG>;
   for (int t = threadIdx.x; t < nlines * S::N2; t += NT) {
     int line, a2;
@@ -274,7 +274,7 @@ __device__ __forceinline__ int lap_freq(int k, int N) { return k < (N >> 1) ? k 
 
 // ---- zfwd ---------------------------------------------------------------------------------
 template <typename T, int LG>
-__device__ void zfwd_body(const SimDev<T>& d, int lb, unsigned char* smem) {
+__device__ __forceinline__ void zfwd_body(const SimDev<T>& d, int lb, unsigned char* smem) {
   constexpr int N = 1 << LG;
   const int B = d.rows_per_blk;
   const int64_t N2 = d.nrows;  // rows per k3 plane of the spectra (N^2; N in 2D)
@@ -343,7 +343,7 @@ __global__ void __launch_bounds__(kThreads) k_zfwd(Batch<T> bt) {
 // ---- y passes -------------------------------------------------------------------------------
 // Along y the spectra stay in fpos order between yfwd and yinv.
 template <typename T, int LG>
-__device__ void yfwd_body(const SimDev<T>& d, int lb, unsigned char* smem) {
+__device__ __forceinline__ void yfwd_body(const SimDev<T>& d, int lb, unsigned char* smem) {
   constexpr int N = 1 << LG;
   const int Bl = d.lines_per_blk;
   const int64_t lines = (int64_t)((N >> 1) + 1) * N;
@@ -371,7 +371,7 @@ __global__ void __launch_bounds__(kThreads) k_yfwd(Batch<T> bt) {
 }
 
 template <typename T, int LG>
-__device__ void yinv_body(const SimDev<T>& d, int lb, unsigned char* smem) {
+__device__ __forceinline__ void yinv_body(const SimDev<T>& d, int lb, unsigned char* smem) {
   constexpr int N = 1 << LG;
   const int Bl = d.lines_per_blk;
   const int64_t lines = (int64_t)((N >> 1) + 1) * N;
@@ -428,7 +428,7 @@ __global__ void __launch_bounds__(kThreads) k_yinv(Batch<T> bt) {
 
 // ---- x pass: forward x transform, multipliers, inverse x transform ------------------------
 template <typename T, int LG>
-__device__ void xpass_body(const SimDev<T>& d, int lb, unsigned char* smem) {
+__device__ __forceinline__ void xpass_body(const SimDev<T>& d, int lb, unsigned char* smem) {
   constexpr int N = 1 << LG;
   const int Bx = d.cols_per_blk;
   constexpr int H = (N >> 1) + 1;
@@ -505,7 +505,7 @@ __device__ void xpass_body(const SimDev<T>& d, int lb, unsigned char* smem) {
 // low-pass filter the filtered V (1/N undoes this round trip) into SVg; inverse transform.
 // The d2 derivative is formed by the inverse row pass from SVg, as d3 is in 3D.
 template <typename T, int LG>
-__device__ void col2d_body(const SimDev<T>& d, int lb, unsigned char* smem) {
+__device__ __forceinline__ void col2d_body(const SimDev<T>& d, int lb, unsigned char* smem) {
   constexpr int N = 1 << LG;
   constexpr int H = (N >> 1) + 1;
   const int Bl = d.cols_per_blk;
@@ -581,7 +581,7 @@ __global__ void __launch_bounds__(kThreads) k_xpass(Batch<T> bt) {
 // d2 V with full 2D transforms, and a fifth writes the filtered V plane (x, y round trip
 // undone) into SVg, from which zinv then forms the z derivative.
 template <typename T, int LG>
-__device__ void plane_body(const SimDev<T>& d, int lb, unsigned char* smem) {
+__device__ __forceinline__ void plane_body(const SimDev<T>& d, int lb, unsigned char* smem) {
   constexpr int N = 1 << LG;
   constexpr int NN = N * N;
   constexpr int NT = kPlaneThreads;
@@ -685,7 +685,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane(Batch<T> bt) {
 
 // ---- zinv ---------------------------------------------------------------------------------
 template <typename T, int LG>
-__device__ void zinv_body(const SimDev<T>& d, int lb, unsigned char* smem) {
+__device__ __forceinline__ void zinv_body(const SimDev<T>& d, int lb, unsigned char* smem) {
   constexpr int N = 1 << LG;
   const int B = d.rows_per_blk;
   const int64_t N2 = d.nrows;  // rows per k3 plane of the spectra (N^2; N in 2D)
