@@ -156,6 +156,14 @@ constexpr int row_stride() {
   return (1 << LG) + (LG >= 4 ? 4 : 0);
 }
 inline int row_stride_rt(int lg) { return (1 << lg) + (lg >= 4 ? 4 : 0); }
+// The z and y passes also read and write their lines across rows (one row per thread when
+// packing spectra), so they pad by one complex value (an odd stride spreads consecutive rows
+// over all LDS banks) and map consecutive threads to consecutive lines in the transforms.
+template <int LG>
+constexpr int zy_stride() {
+  return (1 << LG) + 1;
+}
+inline int zy_stride_rt(int lg) { return (1 << lg) + 1; }
 
 // position of frequency k after a forward line transform, and its inverse map
 template <int LG>
@@ -279,7 +287,7 @@ __device__ __forceinline__ void zfwd_body(const SimDev<T>& d, int lb, unsigned c
   const int B = d.rows_per_blk;
   const int64_t N2 = d.nrows;  // rows per k3 plane of the spectra (N^2; N in 2D)
   const int64_t r0 = (int64_t)lb * B;
-  constexpr int LS = row_stride<LG>();
+  constexpr int LS = zy_stride<LG>();
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);  // B lines: m* + i w*
   cplx<T>* Vp = A + B * LS;                       // B/2 lines: v(row 2q) + i v(row 2q+1)
   cplx<T>* tw = Vp + (B >> 1) * LS;
@@ -308,7 +316,7 @@ __device__ __forceinline__ void zfwd_body(const SimDev<T>& d, int lb, unsigned c
     vp[rr & 1] = vv;
   }
   __syncthreads();
-  line_fwd<T, LG>(A, B + (B >> 1), LS, 1, tw);
+  line_fwd<T, LG, true>(A, B + (B >> 1), LS, 1, tw);
   constexpr int H = (N >> 1) + 1;
   for (int e = threadIdx.x; e < H * B; e += kThreads) {
     const int kz = e / B, rr = e - kz * B;
@@ -352,13 +360,13 @@ __device__ __forceinline__ void yfwd_body(const SimDev<T>& d, int lb, unsigned c
   const int64_t l0 = (int64_t)(lb - f * nbf) * Bl;
   const int nl = (int)((lines - l0) < Bl ? (lines - l0) : Bl);
   cplx<T>* S = (f == 0 ? d.SM : (f == 1 ? d.SW : d.SV)) + l0 * N;
-  constexpr int LS = row_stride<LG>();
+  constexpr int LS = zy_stride<LG>();
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* tw = buf + Bl * LS;
   load_twiddles(tw, d);
   for (int e = threadIdx.x; e < nl * N; e += kThreads) buf[(e >> LG) * LS + (e & (N - 1))] = S[e];
   __syncthreads();
-  line_fwd<T, LG>(buf, nl, LS, 1, tw);
+  line_fwd<T, LG, true>(buf, nl, LS, 1, tw);
   for (int e = threadIdx.x; e < nl * N; e += kThreads) S[e] = buf[(e >> LG) * LS + (e & (N - 1))];
 }
 
@@ -376,7 +384,7 @@ __device__ __forceinline__ void yinv_body(const SimDev<T>& d, int lb, unsigned c
   const int Bl = d.lines_per_blk;
   const int64_t lines = (int64_t)((N >> 1) + 1) * N;
   const int nb1 = (int)((lines + Bl - 1) / Bl);
-  constexpr int LS = row_stride<LG>();
+  constexpr int LS = zy_stride<LG>();
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* tw = buf + Bl * LS;
   load_twiddles(tw, d);
@@ -388,7 +396,7 @@ __device__ __forceinline__ void yinv_body(const SimDev<T>& d, int lb, unsigned c
     for (int e = threadIdx.x; e < nl * N; e += kThreads)
       buf[(e >> LG) * LS + (e & (N - 1))] = S[e];
     __syncthreads();
-    line_inv<T, LG>(buf, nl, LS, 1, tw);
+    line_inv<T, LG, true>(buf, nl, LS, 1, tw);
     for (int e = threadIdx.x; e < nl * N; e += kThreads)
       S[e] = buf[(e >> LG) * LS + (e & (N - 1))];
   } else {
@@ -407,7 +415,7 @@ __device__ __forceinline__ void yinv_body(const SimDev<T>& d, int lb, unsigned c
       buf[(2 * line + 1) * LS + p] = cplx<T>{-kk * V.y, kk * V.x};
     }
     __syncthreads();
-    line_inv<T, LG>(buf, 2 * nl, LS, 1, tw);
+    line_inv<T, LG, true>(buf, 2 * nl, LS, 1, tw);
     cplx<T>* dV = d.SVg + l0 * N;
     cplx<T>* dG = d.SGy + l0 * N;
     for (int e = threadIdx.x; e < nl * N; e += kThreads) {
@@ -691,7 +699,7 @@ __device__ __forceinline__ void zinv_body(const SimDev<T>& d, int lb, unsigned c
   const int64_t N2 = d.nrows;  // rows per k3 plane of the spectra (N^2; N in 2D)
   const int64_t r0 = (int64_t)lb * B;
   const int Bh = B >> 1;
-  constexpr int LS = row_stride<LG>();
+  constexpr int LS = zy_stride<LG>();
   cplx<T>* MW = reinterpret_cast<cplx<T>*>(smem);  // B lines: m + i w
   cplx<T>* GG = MW + B * LS;                      // B lines: d1 v + i d2 v
   cplx<T>* GZ = GG + B * LS;                      // B/2 lines: d3 v rows 2q + i 2q+1
@@ -722,7 +730,7 @@ __device__ __forceinline__ void zinv_body(const SimDev<T>& d, int lb, unsigned c
     if (mirror) GZ[q * LS + pc] = cplx<T>{gz[0].x + gz[1].y, gz[1].x - gz[0].y};
   }
   __syncthreads();
-  line_inv<T, LG>(MW, 2 * B + Bh, LS, 1, tw);
+  line_inv<T, LG, true>(MW, 2 * B + Bh, LS, 1, tw);
   const bool freeze_m = d.flags & SIPF_FLAG_FREEZE_M;
   const bool freeze_w = d.flags & SIPF_FLAG_FREEZE_W;
   Acc acc;
@@ -768,18 +776,19 @@ template <typename T>
 size_t fft_lds_bytes(int kind, int lg) {
   const int E = elems_per_block<T>();
   const int N = 1 << lg;
-  const size_t LS = (size_t)row_stride_rt(lg);
+  const size_t LS = (size_t)row_stride_rt(lg);    // x pass, plane
+  const size_t LZ = (size_t)zy_stride_rt(lg);     // z and y passes
   const size_t c = sizeof(cplx<T>);
   const size_t tw = (size_t)(N / 2) * c;
   const size_t B = (size_t)std::min(N * N, std::max(2, E / N));  // rows per block (z passes)
   const size_t Bl = (size_t)(E / N);                // lines per block (y passes)
   const size_t Bx = (size_t)std::min(N, E / N);     // columns per block (x pass)
   switch (kind) {
-    case K_ZFWD: return (B + B / 2) * LS * c + tw;
-    case K_YFWD: return Bl * LS * c + tw;
-    case K_YINV: return Bl * LS * c + tw;
+    case K_ZFWD: return (B + B / 2) * LZ * c + tw;
+    case K_YFWD: return Bl * LZ * c + tw;
+    case K_YINV: return Bl * LZ * c + tw;
     case K_XPASS: return Bx * LS * c + tw;
-    case K_ZINV: return (2 * B + B / 2) * LS * c + tw;
+    case K_ZINV: return (2 * B + B / 2) * LZ * c + tw;
     case K_PLANE: return (size_t)N * LS * c + tw;
     default: return 0;
   }
