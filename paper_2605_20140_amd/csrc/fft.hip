@@ -164,6 +164,12 @@ constexpr int zy_stride() {
   return (1 << LG) + 1;
 }
 inline int zy_stride_rt(int lg) { return (1 << lg) + 1; }
+// The plane kernel transforms rows and columns of one plane with one line per thread; a
+// stride of N + 2 spreads consecutive rows over the LDS banks and keeps rows 16-byte aligned.
+template <int LG>
+constexpr int plane_stride() {
+  return (1 << LG) + 2;
+}
 
 // position of frequency k after a forward line transform, and its inverse map
 template <int LG>
@@ -600,7 +606,7 @@ __device__ __forceinline__ void plane_body(const SimDev<T>& d, int lb, unsigned 
     // d1 v and d2 v need only the transform along their own axis: x round trip for SGx,
     // then (from a fresh copy of the plane) y round trip for SGy; 1/N^2 undoes the z and
     // own-axis round trips
-    constexpr int LSv = row_stride<LG>();
+    constexpr int LSv = plane_stride<LG>();
     cplx<T>* Q = reinterpret_cast<cplx<T>*>(smem);
     cplx<T>* twv = Q + N * LSv;
     for (int k = threadIdx.x; k < (N >> 1); k += NT) twv[k] = d.tw[k];
@@ -612,7 +618,7 @@ __device__ __forceinline__ void plane_body(const SimDev<T>& d, int lb, unsigned 
       if (pass == 0)
         line_fwd<T, LG, true, NT>(Q, N, 1, LSv, twv);  // along i1
       else
-        line_fwd<T, LG, false, NT>(Q, N, LSv, 1, twv);  // along i2
+        line_fwd<T, LG, true, NT>(Q, N, LSv, 1, twv);  // along i2
       for (int e = threadIdx.x; e < NN; e += NT) {
         const int i1 = e >> LG, i2 = e & (N - 1);
         const int q = deriv_freq(ufpos<LG>(pass == 0 ? i1 : i2), N);
@@ -625,7 +631,7 @@ __device__ __forceinline__ void plane_body(const SimDev<T>& d, int lb, unsigned 
       if (pass == 0)
         line_inv<T, LG, true, NT>(Q, N, 1, LSv, twv);
       else
-        line_inv<T, LG, false, NT>(Q, N, LSv, 1, twv);
+        line_inv<T, LG, true, NT>(Q, N, LSv, 1, twv);
       cplx<T>* dst = (pass == 0 ? d.SGx : d.SGy) + off;
       for (int e = threadIdx.x; e < NN; e += NT) dst[e] = Q[(e >> LG) * LSv + (e & (N - 1))];
       __syncthreads();
@@ -636,13 +642,13 @@ __device__ __forceinline__ void plane_body(const SimDev<T>& d, int lb, unsigned 
   cplx<T>* dst =
       (job == 0 ? d.SM : (job == 1 ? d.SW : (job == 2 ? d.SGx : (job == 3 ? d.SGy : d.SVg)))) +
       off;
-  constexpr int LS = row_stride<LG>();
+  constexpr int LS = plane_stride<LG>();
   cplx<T>* P = reinterpret_cast<cplx<T>*>(smem);  // P[i1 * LS + i2]
   cplx<T>* tw = P + N * LS;
   for (int k = threadIdx.x; k < (N >> 1); k += NT) tw[k] = d.tw[k];
   for (int e = threadIdx.x; e < NN; e += NT) P[(e >> LG) * LS + (e & (N - 1))] = src[e];
   __syncthreads();
-  line_fwd<T, LG, false, NT>(P, N, LS, 1, tw);  // along i2 (rows)
+  line_fwd<T, LG, true, NT>(P, N, LS, 1, tw);  // along i2 (rows)
   line_fwd<T, LG, true, NT>(P, N, 1, LS, tw);   // along i1 (columns)
   const int qz = lap_freq(kz, N);
   const T k0 = d.two_pi_over_L;
@@ -679,7 +685,7 @@ __device__ __forceinline__ void plane_body(const SimDev<T>& d, int lb, unsigned 
   }
   __syncthreads();
   line_inv<T, LG, true, NT>(P, N, 1, LS, tw);
-  line_inv<T, LG, false, NT>(P, N, LS, 1, tw);
+  line_inv<T, LG, true, NT>(P, N, LS, 1, tw);
   for (int e = threadIdx.x; e < NN; e += NT) dst[e] = P[(e >> LG) * LS + (e & (N - 1))];
 }
 
@@ -789,7 +795,7 @@ size_t fft_lds_bytes(int kind, int lg) {
     case K_YINV: return Bl * LZ * c + tw;
     case K_XPASS: return Bx * LS * c + tw;
     case K_ZINV: return (2 * B + B / 2) * LZ * c + tw;
-    case K_PLANE: return (size_t)N * LS * c + tw;
+    case K_PLANE: return (size_t)N * (N + 2) * c + tw;  // plane_stride
     default: return 0;
   }
 }
