@@ -282,11 +282,10 @@ __global__ void __launch_bounds__(kThreads) k_particles(Batch<T> bt, int src_set
   const int s = find_sim(bt, K_PART, lb);
   const SimDev<T>& d = bt.sims[s];
   const int nchunks = (int)d.coff[d.ntiles];
+  const uint4 ci = d.cinfo[lb];  // lb < max_chunks; both loads in flight together
   if (lb >= nchunks) return;
-  const int tile = (int)d.ctile[lb];
-  const uint32_t start = d.toff[tile] + (uint32_t)(lb - (int)d.coff[tile]) * kChunk;
-  const uint32_t tend = d.toff[tile + 1];
-  const uint32_t end = start + kChunk < tend ? start + kChunk : tend;
+  const uint32_t start = ci.x, end = ci.y;
+  const int tile = (int)ci.z;
   const int N = d.N;
   const int nt = d.ntile1;
   Region rg;
@@ -523,11 +522,10 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
   const int s = find_sim(bt, K_PART, lb);
   const SimDev<T>& d = bt.sims[s];
   const int nchunks = (int)d.coff[d.ntiles];
+  const uint4 ci = d.cinfo[lb];  // lb < max_chunks; both loads in flight together
   if (lb >= nchunks) return;
-  const int tile = (int)d.ctile[lb];
-  const uint32_t start = d.toff[tile] + (uint32_t)(lb - (int)d.coff[tile]) * kChunk;
-  const uint32_t tend = d.toff[tile + 1];
-  const uint32_t end = start + kChunk < tend ? start + kChunk : tend;
+  const uint32_t start = ci.x, end = ci.y;
+  const int tile = (int)ci.z;
   const int N = d.N;
   const int nt = d.ntile1;
   Region rg;
@@ -760,7 +758,11 @@ __global__ void __launch_bounds__(kThreads) k_bin_scan(Batch<T> bt) {
     const uint32_t nch = (c + kChunk - 1) / kChunk;
     d.toff[t] = rp;
     d.coff[t] = rc;
-    for (uint32_t k = 0; k < nch; ++k) d.ctile[rc + k] = (uint32_t)t;
+    for (uint32_t k = 0; k < nch; ++k) {
+      d.ctile[rc + k] = (uint32_t)t;
+      const uint32_t cs = rp + k * kChunk;
+      d.cinfo[rc + k] = uint4{cs, cs + kChunk < rp + c ? cs + kChunk : rp + c, (uint32_t)t, 0u};
+    }
     rp += c;
     rc += nch;
     d.tcount[t] = 0;
@@ -769,6 +771,7 @@ __global__ void __launch_bounds__(kThreads) k_bin_scan(Batch<T> bt) {
     d.toff[nt] = pp[kThreads - 1];
     d.coff[nt] = pc[kThreads - 1];
   }
+
 }
 
 template <typename T, int DIM>

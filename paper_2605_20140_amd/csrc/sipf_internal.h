@@ -109,6 +109,8 @@ struct SimDev {
   uint32_t* toff;     // ntiles + 1: first sorted index of each tile
   uint32_t* coff;     // ntiles + 1: first chunk of each tile
   uint32_t* ctile;    // max_chunks: tile of each chunk
+  uint4* cinfo;       // max_chunks: (first particle, end, tile, -) of each chunk (set at
+                      // binning, so a particle-pass block needs one lookup)
   int max_chunks;     // bound on the number of chunks: ceil(P / kChunk) + ntiles
   uint32_t* key;      // 2P: (tile, rank within tile) per particle
   // grid (real, N^3 row-major)
@@ -140,7 +142,7 @@ __device__ __forceinline__ int find_sim(const Batch<T>& b, int kind, int& local_
     const int mid = (lo + hi) >> 1;
     if (off[mid] <= bid) lo = mid; else hi = mid;
   }
-  local_block = bid - off[lo];
+  local_block = bid - (lo ? off[lo] : 0);  // off[0] is always 0
   return lo;
 }
 
