@@ -25,7 +25,7 @@ constexpr int kFinThreads = kStripes * kStripeWords;
 
 template <typename T>
 __global__ void __launch_bounds__(kFinThreads) k_diag_finalize(Batch<T> bt, int mode) {
-  const SimDev<T>& d = bt.sims[blockIdx.x];
+  SimC<T>& d = sim_view(bt, (int)blockIdx.x);
   __shared__ unsigned long long w[kFinThreads];
   const int t = threadIdx.x;
   const int sl = t % kStripeWords;
@@ -56,7 +56,7 @@ __global__ void __launch_bounds__(kFinThreads) k_diag_finalize(Batch<T> bt, int 
 // Clear every word of the diagnostics area.
 template <typename T>
 __global__ void k_diag_clear(Batch<T> bt) {
-  const SimDev<T>& d = bt.sims[blockIdx.x];
+  SimC<T>& d = sim_view(bt, (int)blockIdx.x);
   for (int e = threadIdx.x; e < kDiagWords; e += blockDim.x)
     d.diag[e] = slot_identity(e % kStripeWords);
 }
@@ -67,7 +67,7 @@ template <typename T>
 __global__ void __launch_bounds__(kThreads) k_diag_full(Batch<T> bt, int state, int u) {
   int lb;
   const int s = find_sim(bt, K_DIAG, lb);
-  const SimDev<T>& d = bt.sims[s];
+  SimC<T>& d = sim_view(bt, s);
   const int* off = bt.blk + K_DIAG * (bt.nsims + 1);
   const int nb = off[s + 1] - off[s];
   Acc a;

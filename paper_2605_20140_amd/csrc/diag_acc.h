@@ -77,7 +77,7 @@ __device__ __forceinline__ void acc_flush(Acc& a, unsigned long long* g) {
 
 // accumulator copy of this block
 template <typename T>
-__device__ __forceinline__ unsigned long long* diag_stripe(const SimDev<T>& d) {
+__device__ __forceinline__ unsigned long long* diag_stripe(SimC<T>& d) {
   return d.diag + (blockIdx.x & (kStripes - 1)) * kStripeWords;
 }
 

@@ -40,6 +40,9 @@
 
 namespace sipf {
 
+// elements per thread whose global loads the z passes issue before any of their stores
+constexpr int kLoadBatch = 4;
+
 template <> int elems_per_block<double>() { return 1024; }
 template <> int elems_per_block<float>() { return 2048; }
 
@@ -275,7 +278,7 @@ __device__ __forceinline__ void line_inv(cplx<T>* buf, int nlines, int ls, int e
 }
 
 template <typename T>
-__device__ __forceinline__ void load_twiddles(cplx<T>* tw, const SimDev<T>& d) {
+__device__ __forceinline__ void load_twiddles(cplx<T>* tw, SimC<T>& d) {
   for (int k = threadIdx.x; k < (d.N >> 1); k += kThreads) tw[k] = d.tw[k];
 }
 
@@ -288,7 +291,7 @@ __device__ __forceinline__ int lap_freq(int k, int N) { return k < (N >> 1) ? k 
 
 // ---- zfwd ---------------------------------------------------------------------------------
 template <typename T, int LG>
-__device__ __forceinline__ void zfwd_body(const SimDev<T>& d, int lb, unsigned char* smem) {
+__device__ __forceinline__ void zfwd_body(SimC<T>& d, int lb, unsigned char* smem) {
   constexpr int N = 1 << LG;
   const int B = d.rows_per_blk;
   const int64_t N2 = d.nrows;  // rows per k3 plane of the spectra (N^2; N in 2D)
@@ -303,23 +306,42 @@ __device__ __forceinline__ void zfwd_body(const SimDev<T>& d, int lb, unsigned c
   const bool impl_v = d.flags & SIPF_FLAG_IMPLICIT_V;
   Acc acc;
   acc_init(acc);
-  for (int e = threadIdx.x; e < B * N; e += kThreads) {
-    const int rr = e >> LG, iz = e & (N - 1);
-    const int64_t g = (r0 + rr) * N + iz;
-    const T u = d.ubar[g], mm = d.m[g], vv = d.v[g], ww = d.w[g];
-    const T ms = mm + dt * u;
-    const T eta = (T)2 * u / ((T)1 + u);
-    const T wsr = ww + dt * (gam * vv - eta * ww);
-    T vn = vv;
-    if (!freeze_v) {
-      vn = impl_v ? vv / ((T)1 + adt * mm) : vv * exp(-adt * mm);
-      d.v[g] = vn;
+  // kLoadBatch elements per thread have their loads in flight together (the stores to v and
+  // ubar would otherwise order each element's loads after the previous element's stores)
+  const int nel = B * N;
+  const int64_t g0 = r0 * N;  // first node of the block's rows
+  for (int e0 = threadIdx.x; e0 < nel; e0 += kLoadBatch * kThreads) {
+    T u[kLoadBatch], mm[kLoadBatch], vv[kLoadBatch], ww[kLoadBatch];
+#pragma unroll
+    for (int k = 0; k < kLoadBatch; ++k) {
+      const int e = e0 + k * kThreads;
+      if (e < nel) {
+        u[k] = d.ubar[g0 + e];
+        mm[k] = d.m[g0 + e];
+        vv[k] = d.v[g0 + e];
+        ww[k] = d.w[g0 + e];
+      }
     }
-    if (isfinite((double)vn)) acc_min(acc, D_MIN_V, (double)vn); else acc.cnt[0] += 1;
-    d.ubar[g] = (T)0;
-    A[rr * LS + iz] = cplx<T>{ms, wsr};
-    T* vp = reinterpret_cast<T*>(&Vp[(rr >> 1) * LS + iz]);
-    vp[rr & 1] = vv;
+#pragma unroll
+    for (int k = 0; k < kLoadBatch; ++k) {
+      const int e = e0 + k * kThreads;
+      if (e < nel) {
+        const int rr = e >> LG, iz = e & (N - 1);
+        const T ms = mm[k] + dt * u[k];
+        const T eta = (T)2 * u[k] / ((T)1 + u[k]);
+        const T wsr = ww[k] + dt * (gam * vv[k] - eta * ww[k]);
+        T vn = vv[k];
+        if (!freeze_v) {
+          vn = impl_v ? vv[k] / ((T)1 + adt * mm[k]) : vv[k] * exp(-adt * mm[k]);
+          d.v[g0 + e] = vn;
+        }
+        if (isfinite((double)vn)) acc_min(acc, D_MIN_V, (double)vn); else acc.cnt[0] += 1;
+        d.ubar[g0 + e] = (T)0;
+        A[rr * LS + iz] = cplx<T>{ms, wsr};
+        T* vp = reinterpret_cast<T*>(&Vp[(rr >> 1) * LS + iz]);
+        vp[rr & 1] = vv[k];
+      }
+    }
   }
   __syncthreads();
   line_fwd<T, LG, true>(A, B + (B >> 1), LS, 1, tw);
@@ -351,13 +373,13 @@ __global__ void __launch_bounds__(kThreads) k_zfwd(Batch<T> bt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
   const int s = find_sim(bt, K_ZFWD, lb);
-  zfwd_body<T, LG>(bt.sims[s], lb, smem_raw);
+  zfwd_body<T, LG>(sim_view(bt, s), lb, smem_raw);
 }
 
 // ---- y passes -------------------------------------------------------------------------------
 // Along y the spectra stay in fpos order between yfwd and yinv.
 template <typename T, int LG>
-__device__ __forceinline__ void yfwd_body(const SimDev<T>& d, int lb, unsigned char* smem) {
+__device__ __forceinline__ void yfwd_body(SimC<T>& d, int lb, unsigned char* smem) {
   constexpr int N = 1 << LG;
   const int Bl = d.lines_per_blk;
   const int64_t lines = (int64_t)((N >> 1) + 1) * N;
@@ -381,11 +403,11 @@ __global__ void __launch_bounds__(kThreads) k_yfwd(Batch<T> bt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
   const int s = find_sim(bt, K_YFWD, lb);
-  yfwd_body<T, LG>(bt.sims[s], lb, smem_raw);
+  yfwd_body<T, LG>(sim_view(bt, s), lb, smem_raw);
 }
 
 template <typename T, int LG>
-__device__ __forceinline__ void yinv_body(const SimDev<T>& d, int lb, unsigned char* smem) {
+__device__ __forceinline__ void yinv_body(SimC<T>& d, int lb, unsigned char* smem) {
   constexpr int N = 1 << LG;
   const int Bl = d.lines_per_blk;
   const int64_t lines = (int64_t)((N >> 1) + 1) * N;
@@ -437,12 +459,12 @@ __global__ void __launch_bounds__(kThreads) k_yinv(Batch<T> bt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
   const int s = find_sim(bt, K_YINV, lb);
-  yinv_body<T, LG>(bt.sims[s], lb, smem_raw);
+  yinv_body<T, LG>(sim_view(bt, s), lb, smem_raw);
 }
 
 // ---- x pass: forward x transform, multipliers, inverse x transform ------------------------
 template <typename T, int LG>
-__device__ __forceinline__ void xpass_body(const SimDev<T>& d, int lb, unsigned char* smem) {
+__device__ __forceinline__ void xpass_body(SimC<T>& d, int lb, unsigned char* smem) {
   constexpr int N = 1 << LG;
   const int Bx = d.cols_per_blk;
   constexpr int H = (N >> 1) + 1;
@@ -519,7 +541,7 @@ __device__ __forceinline__ void xpass_body(const SimDev<T>& d, int lb, unsigned 
 // low-pass filter the filtered V (1/N undoes this round trip) into SVg; inverse transform.
 // The d2 derivative is formed by the inverse row pass from SVg, as d3 is in 3D.
 template <typename T, int LG>
-__device__ __forceinline__ void col2d_body(const SimDev<T>& d, int lb, unsigned char* smem) {
+__device__ __forceinline__ void col2d_body(SimC<T>& d, int lb, unsigned char* smem) {
   constexpr int N = 1 << LG;
   constexpr int H = (N >> 1) + 1;
   const int Bl = d.cols_per_blk;
@@ -578,10 +600,11 @@ __global__ void __launch_bounds__(kThreads) k_xpass(Batch<T> bt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
   const int s = find_sim(bt, K_XPASS, lb);
-  if (bt.sims[s].dim == 2)
-    col2d_body<T, LG>(bt.sims[s], lb, smem_raw);
+  SimC<T>& d = sim_view(bt, s);
+  if (d.dim == 2)
+    col2d_body<T, LG>(d, lb, smem_raw);
   else
-    xpass_body<T, LG>(bt.sims[s], lb, smem_raw);
+    xpass_body<T, LG>(d, lb, smem_raw);
 }
 
 // ---- plane pass: y, x, multipliers, x^-1, y^-1 on one k3 plane in LDS --------------------
@@ -595,7 +618,7 @@ __global__ void __launch_bounds__(kThreads) k_xpass(Batch<T> bt) {
 // d2 V with full 2D transforms, and a fifth writes the filtered V plane (x, y round trip
 // undone) into SVg, from which zinv then forms the z derivative.
 template <typename T, int LG>
-__device__ __forceinline__ void plane_body(const SimDev<T>& d, int lb, unsigned char* smem) {
+__device__ __forceinline__ void plane_body(SimC<T>& d, int lb, unsigned char* smem) {
   constexpr int N = 1 << LG;
   constexpr int NN = N * N;
   constexpr int NT = kPlaneThreads;
@@ -694,12 +717,12 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane(Batch<T> bt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
   const int s = find_sim(bt, K_PLANE, lb);
-  plane_body<T, LG>(bt.sims[s], lb, smem_raw);
+  plane_body<T, LG>(sim_view(bt, s), lb, smem_raw);
 }
 
 // ---- zinv ---------------------------------------------------------------------------------
 template <typename T, int LG>
-__device__ __forceinline__ void zinv_body(const SimDev<T>& d, int lb, unsigned char* smem) {
+__device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* smem) {
   constexpr int N = 1 << LG;
   const int B = d.rows_per_blk;
   const int64_t N2 = d.nrows;  // rows per k3 plane of the spectra (N^2; N in 2D)
@@ -741,28 +764,44 @@ __device__ __forceinline__ void zinv_body(const SimDev<T>& d, int lb, unsigned c
   const bool freeze_w = d.flags & SIPF_FLAG_FREEZE_W;
   Acc acc;
   acc_init(acc);
-  for (int e = threadIdx.x; e < B * N; e += kThreads) {
-    const int rr = e >> LG, iz = e & (N - 1);
-    const int64_t g = (r0 + rr) * N + iz;
-    const cplx<T> mw = MW[rr * LS + iz];
-    const cplx<T> gg = GG[rr * LS + iz];
-    const cplx<T> gzp = GZ[(rr >> 1) * LS + iz];
-    const T wold = d.w[g];
-    d.g4[g] = vec4<T>{gg.x, gg.y, (rr & 1) ? gzp.y : gzp.x, wold};
-    T mn = mw.x, wn = mw.y;
-    if (!freeze_m) d.m[g] = mn; else mn = d.m[g];
-    if (!freeze_w) d.w[g] = wn; else wn = wold;
-    const double md = mn, wd = wn;
-    if (isfinite(md) && isfinite(wd)) {
-      acc.sum[2] += md;
-      acc_min(acc, D_MIN_M, md);
-      acc_min(acc, D_MAX_M, md);
-      acc_min(acc, D_MIN_W, wd);
-      acc_min(acc, D_MAX_W, wd);
-      acc.cnt[1] += md < 0.0;
-      acc.cnt[2] += wd < 0.0;
-    } else {
-      acc.cnt[0] += 1;
+  // the old w (and, with m frozen, m) of kLoadBatch elements per thread loaded together
+  const int nel = B * N;
+  const int64_t g0 = r0 * N;
+  for (int e0 = threadIdx.x; e0 < nel; e0 += kLoadBatch * kThreads) {
+    T wold[kLoadBatch], mold[kLoadBatch];
+#pragma unroll
+    for (int k = 0; k < kLoadBatch; ++k) {
+      const int e = e0 + k * kThreads;
+      if (e < nel) {
+        wold[k] = d.w[g0 + e];
+        if (freeze_m) mold[k] = d.m[g0 + e];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kLoadBatch; ++k) {
+      const int e = e0 + k * kThreads;
+      if (e >= nel) continue;
+      const int rr = e >> LG, iz = e & (N - 1);
+      const int64_t g = g0 + e;
+      const cplx<T> mw = MW[rr * LS + iz];
+      const cplx<T> gg = GG[rr * LS + iz];
+      const cplx<T> gzp = GZ[(rr >> 1) * LS + iz];
+      d.g4[g] = vec4<T>{gg.x, gg.y, (rr & 1) ? gzp.y : gzp.x, wold[k]};
+      T mn = mw.x, wn = mw.y;
+      if (!freeze_m) d.m[g] = mn; else mn = mold[k];
+      if (!freeze_w) d.w[g] = wn; else wn = wold[k];
+      const double md = mn, wd = wn;
+      if (isfinite(md) && isfinite(wd)) {
+        acc.sum[2] += md;
+        acc_min(acc, D_MIN_M, md);
+        acc_min(acc, D_MAX_M, md);
+        acc_min(acc, D_MIN_W, wd);
+        acc_min(acc, D_MAX_W, wd);
+        acc.cnt[1] += md < 0.0;
+        acc.cnt[2] += wd < 0.0;
+      } else {
+        acc.cnt[0] += 1;
+      }
     }
   }
   acc_flush(acc, diag_stripe(d));
@@ -773,7 +812,7 @@ __global__ void __launch_bounds__(kThreads) k_zinv(Batch<T> bt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
   const int s = find_sim(bt, K_ZINV, lb);
-  zinv_body<T, LG>(bt.sims[s], lb, smem_raw);
+  zinv_body<T, LG>(sim_view(bt, s), lb, smem_raw);
 }
 
 // ---- LDS sizes and launchers ----------------------------------------------------------------

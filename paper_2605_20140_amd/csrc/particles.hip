@@ -40,8 +40,10 @@ __device__ __forceinline__ Stencil<T> make_stencil(T x, T y, T z, T inv_h, int N
   return st;
 }
 
-__device__ __forceinline__ int64_t node(int a, int b, int c, int N) {
-  return ((int64_t)a * N + b) * N + c;
+// flat index of node (a, b, c) on the N^3 grid; 32-bit arithmetic, since N <= 512 in 3D keeps
+// every index below 2^27
+__device__ __forceinline__ uint32_t node(int a, int b, int c, int N) {
+  return ((uint32_t)a * (uint32_t)N + (uint32_t)b) * (uint32_t)N + (uint32_t)c;
 }
 
 // Box-Muller normals from one Philox block.  float64: exact uniforms (r + 1/2) 2^-32 and
@@ -164,9 +166,13 @@ __device__ __forceinline__ void deposit_global(T* ubar, const Stencil<T>& st, T 
 // far cheaper than float32 ones under the same-address contention of dense cells, and the
 // wider sum loses nothing when the block's total is rounded into the global density.
 constexpr int kPer = kChunk / kThreads;  // particles per thread
+// s_waitcnt operand for vmcnt(0) alone (expcnt and lgkmcnt at their no-wait maxima)
+constexpr int kWaitVmcnt0 = 0x0F70;
 // particles whose loads are issued together (float64 ones need twice the registers)
 template <typename T> struct LoadBatch { static constexpr int n = 8; };
 template <> struct LoadBatch<double> { static constexpr int n = 4; };
+// gather-region nodes per thread whose loads are in flight together (24 VGPRs of data)
+template <typename T> struct kStageGroup { static constexpr int n = 24 / (int)sizeof(T); };
 
 template <int R, typename T>
 __device__ __forceinline__ void deposit_lds(double* acc, const Stencil<T>& st, const int l[3],
@@ -280,7 +286,7 @@ __global__ void __launch_bounds__(kThreads) k_particles(Batch<T> bt, int src_set
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
   const int s = find_sim(bt, K_PART, lb);
-  const SimDev<T>& d = bt.sims[s];
+  SimC<T>& d = sim_view(bt, s);
   const int nchunks = (int)d.coff[d.ntiles];
   const uint4 ci = d.cinfo[lb];  // lb < max_chunks; both loads in flight together
   if (lb >= nchunks) return;
@@ -293,6 +299,7 @@ __global__ void __launch_bounds__(kThreads) k_particles(Batch<T> bt, int src_set
   rg.o[1] = ((tile / nt) % nt) * kTile - Reg<ORDER>::M;
   rg.o[2] = (tile % nt) * kTile - Reg<ORDER>::M;
   const bool use_region = d.use_region;
+  T* const ubar = d.ubar;
 
   const T* xi = d.xs[src_set];
   const T* yi = d.ys[src_set];
@@ -322,12 +329,35 @@ __global__ void __launch_bounds__(kThreads) k_particles(Batch<T> bt, int src_set
   vec4<T>* gl = reinterpret_cast<vec4<T>*>(smem_raw);  // gather array of the region
   double* acc = reinterpret_cast<double*>(gl + R3);  // deposit accumulator
   if (use_region) {
-    for (int e = threadIdx.x; e < R3; e += kThreads) {
-      const int rz = e % R, ry = (e / R) % R, rx = e / (R * R);
-      if (!deposit_only)
-        gl[e] = d.g4[node((rg.o[0] + rx) & (N - 1), (rg.o[1] + ry) & (N - 1),
-                          (rg.o[2] + rz) & (N - 1), N)];
-      acc[e] = 0.0;
+    // groups of kStageGroup nodes per thread: all loads of a group in flight together
+    constexpr int kS = (R3 + kThreads - 1) / kThreads;
+    constexpr int kG = kStageGroup<T>::n;
+#pragma unroll
+    for (int k0 = 0; k0 < kS; k0 += kG) {
+      T s0[kG], s1[kG], s2[kG], s3[kG];  // components, so that they stay in registers
+      if (!deposit_only) {
+#pragma unroll
+        for (int k = 0; k < kG; ++k) {
+          const int e = threadIdx.x + (k0 + k) * kThreads;
+          if (k0 + k < kS && e < R3) {
+            const int rz = e % R, ry = (e / R) % R, rx = e / (R * R);
+            const vec4<T> q = d.g4[node((rg.o[0] + rx) & (N - 1), (rg.o[1] + ry) & (N - 1),
+                                        (rg.o[2] + rz) & (N - 1), N)];
+            s0[k] = q.x;
+            s1[k] = q.y;
+            s2[k] = q.z;
+            s3[k] = q.w;
+          }
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < kG; ++k) {
+        const int e = threadIdx.x + (k0 + k) * kThreads;
+        if (k0 + k < kS && e < R3) {
+          if (!deposit_only) gl[e] = vec4<T>{s0[k], s1[k], s2[k], s3[k]};
+          acc[e] = 0.0;
+        }
+      }
     }
     __syncthreads();
   }
@@ -343,17 +373,17 @@ __global__ void __launch_bounds__(kThreads) k_particles(Batch<T> bt, int src_set
   acc_init(dg);
 
   for (int j0 = 0; j0 < kPer; j0 += kB) {
-    if (j0 > 0) load_batch(j0);
 #pragma unroll
     for (int j = 0; j < kB; ++j) {
       const uint32_t i = start + threadIdx.x + (j0 + j) * kThreads;
       if (i >= end) continue;
+      __builtin_amdgcn_sched_barrier(0);
       const T x = px[j], y = py[j], z = pz[j];
       const double a = pa[j];
       int l[3];
       if (deposit_only) {
         const Stencil<T> s0 = make_stencil(x, y, z, d.inv_h, N);
-        deposit_one<ORDER, R>(d.ubar, acc, s0, rg, use_region, N, (T)a * d.inv_h3);
+        deposit_one<ORDER, R>(ubar, acc, s0, rg, use_region, N, (T)a * d.inv_h3);
         continue;
       }
       // gather (d1 v, d2 v, d3 v, w) at the old position
@@ -376,22 +406,19 @@ __global__ void __launch_bounds__(kThreads) k_particles(Batch<T> bt, int src_set
               gw += wgt * q.w;
             }
       } else {
-        const int ix[2] = {st.c[0], (st.c[0] + 1) & (N - 1)};
-        const int iy[2] = {st.c[1], (st.c[1] + 1) & (N - 1)};
-        const int iz[2] = {st.c[2], (st.c[2] + 1) & (N - 1)};
-#pragma unroll
-        for (int aa = 0; aa < 2; ++aa)
-#pragma unroll
-          for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-            for (int cc = 0; cc < 2; ++cc) {
-              const vec4<T> q = d.g4[node(ix[aa], iy[bb], iz[cc], N)];
-              const T wgt = wx[aa] * wy[bb] * wz[cc];
-              g0 += wgt * q.x;
-              g1 += wgt * q.y;
-              g2 += wgt * q.z;
-              gw += wgt * q.w;
-            }
+        // the stencil leaves the staged region (or there is none): one corner at a time, so
+        // that this rare path does not raise the register count of the whole kernel
+#pragma unroll 1
+        for (int k = 0; k < 8; ++k) {
+          const int aa = k >> 2, bb = (k >> 1) & 1, cc = k & 1;
+          const vec4<T> q = d.g4[node((st.c[0] + aa) & (N - 1), (st.c[1] + bb) & (N - 1),
+                                      (st.c[2] + cc) & (N - 1), N)];
+          const T wgt = (aa ? wx[1] : wx[0]) * (bb ? wy[1] : wy[0]) * (cc ? wz[1] : wz[0]);
+          g0 += wgt * q.x;
+          g1 += wgt * q.y;
+          g2 += wgt * q.z;
+          gw += wgt * q.w;
+        }
       }
 
       // Wiener increment: Philox counter (particle index, step, simulation)
@@ -424,8 +451,15 @@ __global__ void __launch_bounds__(kThreads) k_particles(Batch<T> bt, int src_set
 
       // deposit of the new state: ubar^{n+1}
       const Stencil<T> sn = make_stencil(xn, yn, zz, d.inv_h, N);
-      deposit_one<ORDER, R>(d.ubar, acc, sn, rg, use_region, N, (T)an * d.inv_h3);
+      deposit_one<ORDER, R>(ubar, acc, sn, rg, use_region, N, (T)an * d.inv_h3);
     }
+    // Next batch, if the chunk has one.  Its loads are issued here, after an explicit wait
+    // for this batch's stores: the compiler cannot tell that the exec-masked loads of the
+    // previous batch were all consumed, and would otherwise wait for every outstanding
+    // access before each particle's loads, so that a batch cost one round trip per particle.
+    if (j0 + kB >= kPer || start + (uint32_t)((j0 + kB) * kThreads) >= end) break;
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
+    load_batch(j0 + kB);
   }
 
   if (use_region) {
@@ -520,7 +554,7 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
   const int s = find_sim(bt, K_PART, lb);
-  const SimDev<T>& d = bt.sims[s];
+  SimC<T>& d = sim_view(bt, s);
   const int nchunks = (int)d.coff[d.ntiles];
   const uint4 ci = d.cinfo[lb];  // lb < max_chunks; both loads in flight together
   if (lb >= nchunks) return;
@@ -533,6 +567,7 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
   rg.o[1] = (tile % nt) * kTile2 - 1;
   rg.o[2] = 0;
   const bool use_region = d.use_region;
+  T* const ubar = d.ubar;
   const T* xi = d.xs[src_set];
   const T* yi = d.ys[src_set];
   const double* ai = d.as[src_set];
@@ -558,7 +593,7 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
     const T x = xi[i], y = yi[i];
     const double a = ai[i];
     if (deposit_only) {
-      deposit2(d.ubar, acc, make_stencil2(x, y, d.inv_h, N), rg, use_region, N,
+      deposit2(ubar, acc, make_stencil2(x, y, d.inv_h, N), rg, use_region, N,
                (T)a * d.inv_h3);
       continue;
     }
@@ -569,18 +604,32 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
     T g0 = 0, g1 = 0, gw = 0;
     int l[2];
     const bool inside = use_region && in_region2(st, rg, N, l);
+    // separate LDS and global branches: a load through a pointer selected between the two
+    // would be a flat access
+    if (inside) {
 #pragma unroll
-    for (int aa = 0; aa < 2; ++aa)
+      for (int aa = 0; aa < 2; ++aa)
 #pragma unroll
-      for (int bb = 0; bb < 2; ++bb) {
-        const vec4<T> q =
-            inside ? gl[(l[0] + aa) * kR2 + l[1] + bb]
-                   : d.g4[(int64_t)((st.c[0] + aa) & (N - 1)) * N + ((st.c[1] + bb) & (N - 1))];
-        const T wgt = wx[aa] * wy[bb];
-        g0 += wgt * q.x;
-        g1 += wgt * q.z;
-        gw += wgt * q.w;
-      }
+        for (int bb = 0; bb < 2; ++bb) {
+          const vec4<T> q = gl[(l[0] + aa) * kR2 + l[1] + bb];
+          const T wgt = wx[aa] * wy[bb];
+          g0 += wgt * q.x;
+          g1 += wgt * q.z;
+          gw += wgt * q.w;
+        }
+    } else {
+#pragma unroll
+      for (int aa = 0; aa < 2; ++aa)
+#pragma unroll
+        for (int bb = 0; bb < 2; ++bb) {
+          const vec4<T> q =
+              d.g4[(int64_t)((st.c[0] + aa) & (N - 1)) * N + ((st.c[1] + bb) & (N - 1))];
+          const T wgt = wx[aa] * wy[bb];
+          g0 += wgt * q.x;
+          g1 += wgt * q.z;
+          gw += wgt * q.w;
+        }
+    }
     T zn[2] = {0, 0};
     if (noise) {
       uint32_t c0 = pid, c1 = n, c2 = d.sim_lo, c3 = d.sim_hi;
@@ -603,7 +652,7 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
     } else {
       dg.cnt[0] += 1;
     }
-    deposit2(d.ubar, acc, make_stencil2(xn, yn, d.inv_h, N), rg, use_region, N,
+    deposit2(ubar, acc, make_stencil2(xn, yn, d.inv_h, N), rg, use_region, N,
              (T)an * d.inv_h3);
   }
   if (use_region) {
@@ -639,7 +688,7 @@ template <typename T, int DIM>
 __global__ void __launch_bounds__(kThreads) k_bin_count(Batch<T> bt) {
   int lb;
   const int s = find_sim(bt, K_SCOUNT, lb);
-  const SimDev<T>& d = bt.sims[s];
+  SimC<T>& d = sim_view(bt, s);
   __shared__ uint32_t hkey[kHash], hcnt[kHash], hbase[kHash];
   for (int e = threadIdx.x; e < kHash; e += kThreads) {
     hkey[e] = kEmpty;
@@ -724,7 +773,7 @@ template <typename T>
 __global__ void __launch_bounds__(kThreads) k_bin_scan(Batch<T> bt) {
   int lb;
   const int s = find_sim(bt, K_SSCAN, lb);
-  const SimDev<T>& d = bt.sims[s];
+  SimC<T>& d = sim_view(bt, s);
   const int nt = d.ntiles;
   const int per = (nt + kThreads - 1) / kThreads;
   const int b0 = threadIdx.x * per;
@@ -778,7 +827,7 @@ template <typename T, int DIM>
 __global__ void __launch_bounds__(kThreads) k_bin_scatter(Batch<T> bt) {
   int lb;
   const int s = find_sim(bt, K_SSCATTER, lb);
-  const SimDev<T>& d = bt.sims[s];
+  SimC<T>& d = sim_view(bt, s);
   const int64_t i = (int64_t)lb * kThreads + threadIdx.x;
   if (i >= d.P) return;
   const uint32_t dst = d.toff[d.key[2 * i]] + d.key[2 * i + 1];

@@ -55,7 +55,7 @@ enum KernelKind {
 };
 
 // Diagnostic accumulator slots (uint64 words; sums stored as float64 bit patterns).
-// Layout of SimDev::diag: kStripes accumulator copies of kStripeWords words, then the reduced
+// Layout of SimDesc::diag: kStripes accumulator copies of kStripeWords words, then the reduced
 // diagnostics of the latest state (D_COUNT words), then the read-time reduction of ubar.
 enum DiagSlot {
   D_SUM_A = 0, D_SUM_U, D_SUM_M,
@@ -69,9 +69,22 @@ constexpr int kDiagResult = kStripes * kStripeWords;   // offset of the reduced 
 constexpr int kDiagResultU = kDiagResult + kStripeWords;  // offset of the ubar reduction
 constexpr int kDiagWords = kDiagResultU + kStripeWords;
 
+// Pointer kinds of a descriptor.  The host writes plain pointers.  Kernels read the same
+// bytes as pointers into the global address space: a pointer loaded from memory is generic to
+// the compiler, and generic accesses become flat instructions, which count on the LDS counter
+// as well as the vector-memory one, so every wait for an LDS result would also wait for all
+// global loads in flight.  (The host compilation pass only type-checks kernels; there both
+// kinds are plain pointers.)
+template <typename U> using HostPtr = U*;
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename U> using GlobalPtr = __attribute__((address_space(1))) U*;
+#else
+template <typename U> using GlobalPtr = U*;
+#endif
+
 // Device-visible description of one simulation.  All pointers point into its workspace.
-template <typename T>
-struct SimDev {
+template <typename T, template <typename> class Ptr>
+struct SimDesc {
   int N, log2N;       // grid nodes per axis
   int64_t P;          // particles
   int rows_per_blk;   // z passes: rows (i1, i2) per block
@@ -101,30 +114,33 @@ struct SimDev {
   T inv_nd;           // 1 / N^dim
   int deposit_order;  // 2: trilinear assignment; 4: fourth-order assignment
   // particles, structure of arrays; set 0 is the state, set 1 receives the binned copy
-  T *xs[2], *ys[2], *zs[2];
-  double* as[2];
-  uint32_t* ids[2];   // particle index: keys the noise stream, restores the input order
+  Ptr<T> xs[2], ys[2], zs[2];
+  Ptr<double> as[2];
+  Ptr<uint32_t> ids[2];  // particle index: keys the noise stream, restores the input order
   // binning
-  uint32_t* tcount;   // ntiles: particles per tile (zero between binnings)
-  uint32_t* toff;     // ntiles + 1: first sorted index of each tile
-  uint32_t* coff;     // ntiles + 1: first chunk of each tile
-  uint32_t* ctile;    // max_chunks: tile of each chunk
-  uint4* cinfo;       // max_chunks: (first particle, end, tile, -) of each chunk (set at
-                      // binning, so a particle-pass block needs one lookup)
+  Ptr<uint32_t> tcount;  // ntiles: particles per tile (zero between binnings)
+  Ptr<uint32_t> toff;    // ntiles + 1: first sorted index of each tile
+  Ptr<uint32_t> coff;    // ntiles + 1: first chunk of each tile
+  Ptr<uint32_t> ctile;   // max_chunks: tile of each chunk
+  Ptr<uint4> cinfo;      // max_chunks: (first particle, end, tile, -) of each chunk (set at
+                         // binning, so a particle-pass block needs one lookup)
   int max_chunks;     // bound on the number of chunks: ceil(P / kChunk) + ntiles
-  uint32_t* key;      // 2P: (tile, rank within tile) per particle
+  Ptr<uint32_t> key;     // 2P: (tile, rank within tile) per particle
   // grid (real, N^3 row-major)
-  T *ubar, *v, *m, *w;
-  vec4<T>* g4;        // gather field per node: (d1 v, d2 v, d3 v, w^n)
+  Ptr<T> ubar, v, m, w;
+  Ptr<vec4<T>> g4;       // gather field per node: (d1 v, d2 v, d3 v, w^n)
   // spectra, half-spectrum layout S[k3][i1][i2], k3 in [0, N/2]
-  cplx<T> *SM, *SW, *SV, *SGx, *SGy;
-  cplx<T>* SVg;       // V spectrum the y and z derivatives are formed from: SV, or with the
-                      // low-pass filter its filtered copy (a sixth spectrum buffer)
-  cplx<T>* tw;        // exp(-2 pi i k / N), k < N/2
-  T* mtab;            // separable multiplier tables: [field m | field w | lowpass] x N each
-  uint64_t* step;     // absolute step index n (device-resident, advanced once per step)
-  unsigned long long* diag;  // kDiagWords words, see DiagSlot
+  Ptr<cplx<T>> SM, SW, SV, SGx, SGy;
+  Ptr<cplx<T>> SVg;      // V spectrum the y and z derivatives are formed from: SV, or with the
+                         // low-pass filter its filtered copy (a sixth spectrum buffer)
+  Ptr<cplx<T>> tw;       // exp(-2 pi i k / N), k < N/2
+  Ptr<T> mtab;           // separable multiplier tables: [field m | field w | lowpass] x N each
+  Ptr<uint64_t> step;    // absolute step index n (device-resident, advanced once per step)
+  Ptr<unsigned long long> diag;  // kDiagWords words, see DiagSlot
 };
+
+template <typename T> using SimDev = SimDesc<T, HostPtr>;    // host side
+template <typename T> using SimK = SimDesc<T, GlobalPtr>;     // kernel side
 
 template <typename T>
 struct Batch {
@@ -144,6 +160,23 @@ __device__ __forceinline__ int find_sim(const Batch<T>& b, int kind, int& local_
   }
   local_block = bid - (lo ? off[lo] : 0);  // off[0] is always 0
   return lo;
+}
+
+// Descriptor of simulation s as kernels read it: through the constant address space.  The
+// descriptor is never written while a kernel runs.  Read through a plain reference, its
+// fields would be reloaded after every float or double store of the kernel (type-based alias
+// analysis cannot separate those stores from the descriptor's own fields), and each reload
+// would be followed by a wait for all outstanding memory accesses.  Constant-space loads are
+// invariant: each field is loaded once, into scalar registers.
+#if defined(__HIP_DEVICE_COMPILE__)
+template <typename T> using SimC = __attribute__((address_space(4))) const SimK<T>;
+#else
+template <typename T> using SimC = const SimK<T>;
+#endif
+
+template <typename T>
+__device__ __forceinline__ SimC<T>& sim_view(const Batch<T>& b, int s) {
+  return *(SimC<T>*)(b.sims + s);
 }
 
 // ---- complex arithmetic -------------------------------------------------------------------
