@@ -373,6 +373,11 @@ __global__ void __launch_bounds__(kThreads) k_particles(Batch<T> bt, int src_set
   acc_init(dg);
 
   for (int j0 = 0; j0 < kPer; j0 += kB) {
+    // The batch's loads were issued together, so waiting for all of them costs about what
+    // waiting for the first does; afterwards no particle of the batch waits for memory (the
+    // compiler would otherwise wait for every outstanding access, including the previous
+    // particle's stores, before each use of a loaded value).
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
 #pragma unroll
     for (int j = 0; j < kB; ++j) {
       const uint32_t i = start + threadIdx.x + (j0 + j) * kThreads;
@@ -572,15 +577,52 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
   const T* yi = d.ys[src_set];
   const double* ai = d.as[src_set];
   const uint32_t* idi = d.ids[src_set];
+  constexpr int kB = LoadBatch<T>::n;
+  T px[kB], py[kB];
+  double pa[kB];
+  uint32_t pid[kB];
+  // the loads of kB particles are issued before any arithmetic on them
+  auto load_batch = [&](int j0) {
+#pragma unroll
+    for (int j = 0; j < kB; ++j) {
+      const uint32_t i = start + threadIdx.x + (j0 + j) * kThreads;
+      if (i < end) {
+        px[j] = xi[i];
+        py[j] = yi[i];
+        pa[j] = ai[i];
+        pid[j] = deposit_only ? 0u : idi[i];
+      }
+    }
+  };
+  load_batch(0);  // in flight while the region is staged
 
   vec4<T>* gl = reinterpret_cast<vec4<T>*>(smem_raw);
   double* acc = reinterpret_cast<double*>(gl + kR2sq);
   if (use_region) {
-    for (int e = threadIdx.x; e < kR2sq; e += kThreads) {
-      const int ry = e % kR2, rx = e / kR2;
-      if (!deposit_only)
-        gl[e] = d.g4[(int64_t)((rg.o[0] + rx) & (N - 1)) * N + ((rg.o[1] + ry) & (N - 1))];
-      acc[e] = 0.0;
+    constexpr int kS = (kR2sq + kThreads - 1) / kThreads;
+    T s0[kS], s1[kS], s2[kS], s3[kS];
+    if (!deposit_only) {
+#pragma unroll
+      for (int k = 0; k < kS; ++k) {
+        const int e = threadIdx.x + k * kThreads;
+        if (e < kR2sq) {
+          const int ry = e % kR2, rx = e / kR2;
+          const vec4<T> q =
+              d.g4[(int64_t)((rg.o[0] + rx) & (N - 1)) * N + ((rg.o[1] + ry) & (N - 1))];
+          s0[k] = q.x;
+          s1[k] = q.y;
+          s2[k] = q.z;
+          s3[k] = q.w;
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < kS; ++k) {
+      const int e = threadIdx.x + k * kThreads;
+      if (e < kR2sq) {
+        if (!deposit_only) gl[e] = vec4<T>{s0[k], s1[k], s2[k], s3[k]};
+        acc[e] = 0.0;
+      }
     }
     __syncthreads();
   }
@@ -589,71 +631,80 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
   const bool noise = !(d.flags & SIPF_FLAG_NO_NOISE);
   Acc dg;
   acc_init(dg);
-  for (uint32_t i = start + threadIdx.x; i < end; i += kThreads) {
-    const T x = xi[i], y = yi[i];
-    const double a = ai[i];
-    if (deposit_only) {
-      deposit2(ubar, acc, make_stencil2(x, y, d.inv_h, N), rg, use_region, N,
-               (T)a * d.inv_h3);
-      continue;
-    }
-    const uint32_t pid = idi[i];
-    const Stencil<T> st = make_stencil2(x, y, d.inv_h, N);
-    const T wx[2] = {(T)1 - st.f[0], st.f[0]};
-    const T wy[2] = {(T)1 - st.f[1], st.f[1]};
-    T g0 = 0, g1 = 0, gw = 0;
-    int l[2];
-    const bool inside = use_region && in_region2(st, rg, N, l);
-    // separate LDS and global branches: a load through a pointer selected between the two
-    // would be a flat access
-    if (inside) {
+  for (int j0 = 0; j0 < kPer; j0 += kB) {
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);  // the batch's loads, as in the 3D pass
 #pragma unroll
-      for (int aa = 0; aa < 2; ++aa)
+    for (int j = 0; j < kB; ++j) {
+      const uint32_t i = start + threadIdx.x + (j0 + j) * kThreads;
+      if (i >= end) continue;
+      __builtin_amdgcn_sched_barrier(0);
+      const T x = px[j], y = py[j];
+      const double a = pa[j];
+      if (deposit_only) {
+        deposit2(ubar, acc, make_stencil2(x, y, d.inv_h, N), rg, use_region, N,
+                 (T)a * d.inv_h3);
+        continue;
+      }
+      const Stencil<T> st = make_stencil2(x, y, d.inv_h, N);
+      const T wx[2] = {(T)1 - st.f[0], st.f[0]};
+      const T wy[2] = {(T)1 - st.f[1], st.f[1]};
+      T g0 = 0, g1 = 0, gw = 0;
+      int l[2];
+      const bool inside = use_region && in_region2(st, rg, N, l);
+      // separate LDS and global branches: a load through a pointer selected between the two
+      // would be a flat access
+      if (inside) {
 #pragma unroll
-        for (int bb = 0; bb < 2; ++bb) {
-          const vec4<T> q = gl[(l[0] + aa) * kR2 + l[1] + bb];
-          const T wgt = wx[aa] * wy[bb];
-          g0 += wgt * q.x;
-          g1 += wgt * q.z;
-          gw += wgt * q.w;
-        }
-    } else {
+        for (int aa = 0; aa < 2; ++aa)
 #pragma unroll
-      for (int aa = 0; aa < 2; ++aa)
-#pragma unroll
-        for (int bb = 0; bb < 2; ++bb) {
+          for (int bb = 0; bb < 2; ++bb) {
+            const vec4<T> q = gl[(l[0] + aa) * kR2 + l[1] + bb];
+            const T wgt = wx[aa] * wy[bb];
+            g0 += wgt * q.x;
+            g1 += wgt * q.z;
+            gw += wgt * q.w;
+          }
+      } else {
+        // outside the staged region (or none): one node at a time, as in the 3D pass
+#pragma unroll 1
+        for (int k = 0; k < 4; ++k) {
+          const int aa = k >> 1, bb = k & 1;
           const vec4<T> q =
               d.g4[(int64_t)((st.c[0] + aa) & (N - 1)) * N + ((st.c[1] + bb) & (N - 1))];
-          const T wgt = wx[aa] * wy[bb];
+          const T wgt = (aa ? wx[1] : wx[0]) * (bb ? wy[1] : wy[0]);
           g0 += wgt * q.x;
           g1 += wgt * q.z;
           gw += wgt * q.w;
         }
+      }
+      T zn[2] = {0, 0};
+      if (noise) {
+        uint32_t c0 = pid[j], c1 = n, c2 = d.sim_lo, c3 = d.sim_hi;
+        philox4x32_10(c0, c1, c2, c3, d.seed_lo, d.seed_hi);
+        box_muller2(c0, c1, zn);
+      }
+      const T xn = wrap_periodic(x + d.drift * g0 + d.noise_amp * zn[0], d.L);
+      const T yn = wrap_periodic(y + d.drift * g1 + d.noise_amp * zn[1], d.L);
+      const T rho = (T)2 * gw / ((T)1 + gw);
+      const double an = linear_mass ? a * (1.0 + d.dt * (double)rho - d.dt)
+                                    : a * exp(d.dt * ((double)rho - 1.0));
+      d.xs[0][i] = xn;
+      d.ys[0][i] = yn;
+      d.as[0][i] = an;
+      if (src_set) d.ids[0][i] = pid[j];
+      if (isfinite(an) && isfinite((double)xn) && isfinite((double)yn)) {
+        dg.sum[0] += an;
+        acc_min(dg, D_MIN_A, an);
+        acc_min(dg, D_MAX_A, an);
+      } else {
+        dg.cnt[0] += 1;
+      }
+      deposit2(ubar, acc, make_stencil2(xn, yn, d.inv_h, N), rg, use_region, N,
+               (T)an * d.inv_h3);
     }
-    T zn[2] = {0, 0};
-    if (noise) {
-      uint32_t c0 = pid, c1 = n, c2 = d.sim_lo, c3 = d.sim_hi;
-      philox4x32_10(c0, c1, c2, c3, d.seed_lo, d.seed_hi);
-      box_muller2(c0, c1, zn);
-    }
-    const T xn = wrap_periodic(x + d.drift * g0 + d.noise_amp * zn[0], d.L);
-    const T yn = wrap_periodic(y + d.drift * g1 + d.noise_amp * zn[1], d.L);
-    const T rho = (T)2 * gw / ((T)1 + gw);
-    const double an = linear_mass ? a * (1.0 + d.dt * (double)rho - d.dt)
-                                  : a * exp(d.dt * ((double)rho - 1.0));
-    d.xs[0][i] = xn;
-    d.ys[0][i] = yn;
-    d.as[0][i] = an;
-    if (src_set) d.ids[0][i] = pid;
-    if (isfinite(an) && isfinite((double)xn) && isfinite((double)yn)) {
-      dg.sum[0] += an;
-      acc_min(dg, D_MIN_A, an);
-      acc_min(dg, D_MAX_A, an);
-    } else {
-      dg.cnt[0] += 1;
-    }
-    deposit2(ubar, acc, make_stencil2(xn, yn, d.inv_h, N), rg, use_region, N,
-             (T)an * d.inv_h3);
+    if (j0 + kB >= kPer || start + (uint32_t)((j0 + kB) * kThreads) >= end) break;
+    __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);  // see the 3D pass
+    load_batch(j0 + kB);
   }
   if (use_region) {
     __syncthreads();
