@@ -282,6 +282,53 @@ __device__ __forceinline__ void load_twiddles(cplx<T>* tw, SimC<T>& d) {
   for (int k = threadIdx.x; k < (d.N >> 1); k += kThreads) tw[k] = d.tw[k];
 }
 
+// values per thread whose global loads a copy into LDS keeps in flight together
+template <typename T> struct CopyBatch { static constexpr int n = 32 / (int)sizeof(T); };
+
+// n consecutive complex values from global memory into LDS rows of N values at stride LS,
+// and (unless twg is null) the N/2 twiddles into twl.  The loads of CopyBatch values per thread (and of the
+// twiddles) are in flight together: a plain loop waits for each load before its LDS store,
+// one memory round trip per value.  Component arrays keep the batch in registers.
+template <typename T, int LG, int NT>
+__device__ __forceinline__ void rows_in(cplx<T>* buf, int LS, const cplx<T>* src, int n,
+                                        cplx<T>* twl, const cplx<T>* twg) {
+  constexpr int N = 1 << LG;
+  constexpr int B = CopyBatch<T>::n;
+  constexpr int TW = ((N >> 1) + NT - 1) / NT;
+  T tx[TW], ty[TW];
+#pragma unroll
+  for (int k = 0; k < TW; ++k) {
+    const int t = threadIdx.x + k * NT;
+    if (twg && t < (N >> 1)) {
+      const cplx<T> v = twg[t];
+      tx[k] = v.x;
+      ty[k] = v.y;
+    }
+  }
+  for (int e0 = threadIdx.x; e0 < n; e0 += B * NT) {
+    T vx[B], vy[B];
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      const int e = e0 + k * NT;
+      if (e < n) {
+        const cplx<T> v = src[e];
+        vx[k] = v.x;
+        vy[k] = v.y;
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < B; ++k) {
+      const int e = e0 + k * NT;
+      if (e < n) buf[(e >> LG) * LS + (e & (N - 1))] = cplx<T>{vx[k], vy[k]};
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < TW; ++k) {
+    const int t = threadIdx.x + k * NT;
+    if (twg && t < (N >> 1)) twl[t] = cplx<T>{tx[k], ty[k]};
+  }
+}
+
 // signed derivative frequency for index k of an N-point axis (Nyquist -> 0)
 __device__ __forceinline__ int deriv_freq(int k, int N) {
   return k < (N >> 1) ? k : (k == (N >> 1) ? 0 : k - N);
@@ -391,8 +438,7 @@ __device__ __forceinline__ void yfwd_body(SimC<T>& d, int lb, unsigned char* sme
   constexpr int LS = zy_stride<LG>();
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* tw = buf + Bl * LS;
-  load_twiddles(tw, d);
-  for (int e = threadIdx.x; e < nl * N; e += kThreads) buf[(e >> LG) * LS + (e & (N - 1))] = S[e];
+  rows_in<T, LG, kThreads>(buf, LS, S, nl * N, tw, d.tw);
   __syncthreads();
   line_fwd<T, LG, true>(buf, nl, LS, 1, tw);
   for (int e = threadIdx.x; e < nl * N; e += kThreads) S[e] = buf[(e >> LG) * LS + (e & (N - 1))];
@@ -415,14 +461,12 @@ __device__ __forceinline__ void yinv_body(SimC<T>& d, int lb, unsigned char* sme
   constexpr int LS = zy_stride<LG>();
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* tw = buf + Bl * LS;
-  load_twiddles(tw, d);
   if (lb < 3 * nb1) {
     const int f = lb / nb1;
     const int64_t l0 = (int64_t)(lb - f * nb1) * Bl;
     const int nl = (int)((lines - l0) < Bl ? (lines - l0) : Bl);
     cplx<T>* S = (f == 0 ? d.SM : (f == 1 ? d.SW : d.SGx)) + l0 * N;
-    for (int e = threadIdx.x; e < nl * N; e += kThreads)
-      buf[(e >> LG) * LS + (e & (N - 1))] = S[e];
+    rows_in<T, LG, kThreads>(buf, LS, S, nl * N, tw, d.tw);
     __syncthreads();
     line_inv<T, LG, true>(buf, nl, LS, 1, tw);
     for (int e = threadIdx.x; e < nl * N; e += kThreads)
@@ -435,6 +479,7 @@ __device__ __forceinline__ void yinv_body(SimC<T>& d, int lb, unsigned char* sme
     const int nl = (int)((lines - l0) < Bh ? (lines - l0) : Bh);
     const cplx<T>* SV = d.SVg + l0 * N;
     const T c = d.two_pi_over_L * d.inv_n2;
+    load_twiddles(tw, d);
     for (int e = threadIdx.x; e < nl * N; e += kThreads) {
       const int line = e >> LG, p = e & (N - 1);
       const cplx<T> V = SV[e];
@@ -481,9 +526,27 @@ __device__ __forceinline__ void xpass_body(SimC<T>& d, int lb, unsigned char* sm
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);  // Bx lines of N along i1
   cplx<T>* tw = buf + Bx * LS;
   load_twiddles(tw, d);
-  for (int e = threadIdx.x; e < Bx * N; e += kThreads) {
-    const int c = e % Bx, ix = e / Bx;
-    buf[c * LS + ix] = src[(int64_t)ix * N + y0 + c];
+  {  // columns of the plane into LDS lines, CopyBatch loads per thread in flight together
+    constexpr int CB = CopyBatch<T>::n;
+    const int n = Bx * N;
+    for (int e0 = threadIdx.x; e0 < n; e0 += CB * kThreads) {
+      T vx[CB], vy[CB];
+#pragma unroll
+      for (int k = 0; k < CB; ++k) {
+        const int e = e0 + k * kThreads;
+        if (e < n) {
+          const int c = e % Bx, ix = e / Bx;
+          const cplx<T> v = src[(int64_t)ix * N + y0 + c];
+          vx[k] = v.x;
+          vy[k] = v.y;
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < CB; ++k) {
+        const int e = e0 + k * kThreads;
+        if (e < n) buf[(e % Bx) * LS + e / Bx] = cplx<T>{vx[k], vy[k]};
+      }
+    }
   }
   __syncthreads();
   line_fwd<T, LG>(buf, Bx, LS, 1, tw);
@@ -554,9 +617,7 @@ __device__ __forceinline__ void col2d_body(SimC<T>& d, int lb, unsigned char* sm
   constexpr int LS = row_stride<LG>();
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* tw = buf + Bl * LS;
-  load_twiddles(tw, d);
-  for (int e = threadIdx.x; e < nl * N; e += kThreads)
-    buf[(e >> LG) * LS + (e & (N - 1))] = src[e];
+  rows_in<T, LG, kThreads>(buf, LS, src, nl * N, tw, d.tw);
   __syncthreads();
   line_fwd<T, LG>(buf, nl, LS, 1, tw);
   const T k0 = d.two_pi_over_L;
@@ -632,11 +693,10 @@ __device__ __forceinline__ void plane_body(SimC<T>& d, int lb, unsigned char* sm
     constexpr int LSv = plane_stride<LG>();
     cplx<T>* Q = reinterpret_cast<cplx<T>*>(smem);
     cplx<T>* twv = Q + N * LSv;
-    for (int k = threadIdx.x; k < (N >> 1); k += NT) twv[k] = d.tw[k];
     const T c = d.two_pi_over_L * d.inv_n2;
     for (int pass = 0; pass < 2; ++pass) {
-      const cplx<T>* src = d.SV + off;
-      for (int e = threadIdx.x; e < NN; e += NT) Q[(e >> LG) * LSv + (e & (N - 1))] = src[e];
+      const cplx<T>* twg = pass == 0 ? (const cplx<T>*)d.tw : nullptr;  // loaded once
+      rows_in<T, LG, NT>(Q, LSv, d.SV + off, NN, twv, twg);
       __syncthreads();
       if (pass == 0)
         line_fwd<T, LG, true, NT>(Q, N, 1, LSv, twv);  // along i1
@@ -668,8 +728,7 @@ __device__ __forceinline__ void plane_body(SimC<T>& d, int lb, unsigned char* sm
   constexpr int LS = plane_stride<LG>();
   cplx<T>* P = reinterpret_cast<cplx<T>*>(smem);  // P[i1 * LS + i2]
   cplx<T>* tw = P + N * LS;
-  for (int k = threadIdx.x; k < (N >> 1); k += NT) tw[k] = d.tw[k];
-  for (int e = threadIdx.x; e < NN; e += NT) P[(e >> LG) * LS + (e & (N - 1))] = src[e];
+  rows_in<T, LG, NT>(P, LS, src, NN, tw, d.tw);
   __syncthreads();
   line_fwd<T, LG, true, NT>(P, N, LS, 1, tw);  // along i2 (rows)
   line_fwd<T, LG, true, NT>(P, N, 1, LS, tw);   // along i1 (columns)

@@ -750,6 +750,18 @@ __global__ void __launch_bounds__(kThreads) k_bin_count(Batch<T> bt) {
   const int lane = threadIdx.x & 63;
   const int64_t i0 = (int64_t)lb * kBinChunk + threadIdx.x;
   uint32_t tiles[kBinPer], slot[kBinPer], lrank[kBinPer];
+  // positions of all kBinPer particles loaded before the first tile is aggregated (the
+  // aggregation loop would otherwise put one memory round trip between consecutive loads)
+  T px[kBinPer], py[kBinPer], pz[kBinPer];
+#pragma unroll
+  for (int j = 0; j < kBinPer; ++j) {
+    const int64_t i = i0 + (int64_t)j * kThreads;
+    if (i < d.P) {
+      px[j] = d.xs[0][i];
+      py[j] = d.ys[0][i];
+      if (DIM == 3) pz[j] = d.zs[0][i];
+    }
+  }
 #pragma unroll
   for (int j = 0; j < kBinPer; ++j) {
     const int64_t i = i0 + (int64_t)j * kThreads;
@@ -757,11 +769,11 @@ __global__ void __launch_bounds__(kThreads) k_bin_count(Batch<T> bt) {
     uint32_t tile = 0;
     if (valid) {
       if (DIM == 2) {
-        const Stencil<T> st = make_stencil2(d.xs[0][i], d.ys[0][i], d.inv_h, N);
+        const Stencil<T> st = make_stencil2(px[j], py[j], d.inv_h, N);
         const int tx = st.c[0] / kTile2, ty = st.c[1] / kTile2;
         tile = (uint32_t)((tx < nt ? tx : nt - 1) * nt + (ty < nt ? ty : nt - 1));
       } else {
-        const Stencil<T> st = make_stencil(d.xs[0][i], d.ys[0][i], d.zs[0][i], d.inv_h, N);
+        const Stencil<T> st = make_stencil(px[j], py[j], pz[j], d.inv_h, N);
         const int tx = st.c[0] / kTile, ty = st.c[1] / kTile, tz = st.c[2] / kTile;
         tile = (uint32_t)(((tx < nt ? tx : nt - 1) * nt + (ty < nt ? ty : nt - 1)) * nt +
                           (tz < nt ? tz : nt - 1));
