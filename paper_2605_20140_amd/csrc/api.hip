@@ -164,7 +164,7 @@ struct sipf_sim {
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph_bin = nullptr;   // binning + one step
   hipGraphExec_t exec_bin = nullptr;
-  int resort_every = 8;             // steps between binnings
+  int resort_every = kResortDefault;  // steps between binnings
   int since_bin = 0;                // steps since the last binning
   unsigned char host_desc[std::max(sizeof(SimDev<double>), sizeof(SimDev<float>))];
 };
@@ -429,7 +429,7 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
     HIPCHK(hipMemcpyAsync(d.ids[0], d.ids[1], P * sizeof(uint32_t), hipMemcpyDeviceToDevice,
                           st));
   }
-  sim->resort_every = p.resort_every > 0 ? p.resort_every : 8;
+  sim->resort_every = p.resort_every > 0 ? p.resort_every : kResortDefault;
   sim->since_bin = 0;
   launch_particles<T>(b, sim->counts[K_PART], 0, 1, p.deposit_order, dim, st);  // ubar^0
   launch_diag_clear<T>(b, 1, st);
