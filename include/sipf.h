@@ -86,7 +86,11 @@ typedef struct {
   int32_t precision;     /* SIPF_FP64 or SIPF_FP32                                         */
   int32_t deposit_order; /* 2: trilinear assignment; 4: fourth-order assignment R_h^(4)    */
   uint32_t flags;        /* SIPF_FLAG_*                                                    */
-  int32_t resort_every;  /* particle tile re-binning period in steps (0: library default, 12) */
+  int32_t resort_every;  /* particle tile re-binning period in steps; 0: the library's    *
+                          * default, the largest k (at most 64) with sqrt(k 2 D_u dt) <=    *
+                          * 0.45 h in 3D, 2.4 h in 2D (diffusive drift within the tiles'    *
+                          * LDS margins of one and four cells); the period changes only   *
+                          * the summation order of the deposit                             */
   double H0;             /* low-pass filter exp(-2 pi^2 |q|^2 / H0^2) (Alg. p2g text), >= 0: *
                           * multiplies the m and w solves and the spectrum of v before its  *
                           * gradient; 0 = off (> 0 adds one half-spectrum to the workspace) */

@@ -97,6 +97,16 @@ int validate_params(const sipf_params* p) {
   return SIPF_OK;
 }
 
+// steps between binnings when the caller leaves it to the library (kBinDrift3, kBinDrift2)
+int default_resort(const sipf_params& p) {
+  const double h = p.L / p.N;
+  const double s = (p.flags & SIPF_FLAG_NO_NOISE) ? 0.0 : std::sqrt(2.0 * p.D_u * p.dt) / h;
+  const double reach = dim_of(p) == 2 ? kBinDrift2 : kBinDrift3;
+  if (!(s > 0.0)) return kResortMax;
+  const double k = std::floor((reach / s) * (reach / s));
+  return k < 1.0 ? 1 : (k > kResortMax ? kResortMax : (int)k);
+}
+
 Layout make_layout(const sipf_params& p) {
   const size_t s = p.precision == SIPF_FP32 ? 4 : 8;
   const int dim = dim_of(p);
@@ -164,7 +174,7 @@ struct sipf_sim {
   hipGraphExec_t exec = nullptr;
   hipGraph_t graph_bin = nullptr;   // binning + one step
   hipGraphExec_t exec_bin = nullptr;
-  int resort_every = kResortDefault;  // steps between binnings
+  int resort_every = 1;             // steps between binnings (set at initialisation)
   int since_bin = 0;                // steps since the last binning
   unsigned char host_desc[std::max(sizeof(SimDev<double>), sizeof(SimDev<float>))];
 };
@@ -429,7 +439,7 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
     HIPCHK(hipMemcpyAsync(d.ids[0], d.ids[1], P * sizeof(uint32_t), hipMemcpyDeviceToDevice,
                           st));
   }
-  sim->resort_every = p.resort_every > 0 ? p.resort_every : kResortDefault;
+  sim->resort_every = p.resort_every > 0 ? p.resort_every : default_resort(p);
   sim->since_bin = 0;
   launch_particles<T>(b, sim->counts[K_PART], 0, 1, p.deposit_order, dim, st);  // ubar^0
   launch_diag_clear<T>(b, 1, st);

@@ -40,8 +40,9 @@
 
 namespace sipf {
 
-// elements per thread whose global loads the z passes issue before any of their stores
-constexpr int kLoadBatch = 4;
+// elements per thread whose global loads the z passes issue before any of their stores:
+// all of a block's elements (B N = elems_per_block, over kThreads threads) in one batch
+template <typename T> struct ZBatch { static constexpr int n = sizeof(T) == 4 ? 8 : 4; };
 
 template <> int elems_per_block<double>() { return 1024; }
 template <> int elems_per_block<float>() { return 2048; }
@@ -282,6 +283,32 @@ __device__ __forceinline__ void load_twiddles(cplx<T>* tw, SimC<T>& d) {
   for (int k = threadIdx.x; k < (d.N >> 1); k += kThreads) tw[k] = d.tw[k];
 }
 
+// The N/2 twiddles in two steps, so that their loads join a batch of other loads: issue them
+// into registers, then (after the batch) write them to LDS.
+template <typename T, int LG, int NT>
+struct TwiddleRegs {
+  static constexpr int K = (((1 << LG) >> 1) + NT - 1) / NT;
+  T x[K], y[K];
+  __device__ __forceinline__ void load(const cplx<T>* twg) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int t = threadIdx.x + k * NT;
+      if (t < ((1 << LG) >> 1)) {
+        const cplx<T> v = twg[t];
+        x[k] = v.x;
+        y[k] = v.y;
+      }
+    }
+  }
+  __device__ __forceinline__ void store(cplx<T>* twl) const {
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const int t = threadIdx.x + k * NT;
+      if (t < ((1 << LG) >> 1)) twl[t] = cplx<T>{x[k], y[k]};
+    }
+  }
+};
+
 // values per thread whose global loads a copy into LDS keeps in flight together
 template <typename T> struct CopyBatch { static constexpr int n = 32 / (int)sizeof(T); };
 
@@ -294,17 +321,8 @@ __device__ __forceinline__ void rows_in(cplx<T>* buf, int LS, const cplx<T>* src
                                         cplx<T>* twl, const cplx<T>* twg) {
   constexpr int N = 1 << LG;
   constexpr int B = CopyBatch<T>::n;
-  constexpr int TW = ((N >> 1) + NT - 1) / NT;
-  T tx[TW], ty[TW];
-#pragma unroll
-  for (int k = 0; k < TW; ++k) {
-    const int t = threadIdx.x + k * NT;
-    if (twg && t < (N >> 1)) {
-      const cplx<T> v = twg[t];
-      tx[k] = v.x;
-      ty[k] = v.y;
-    }
-  }
+  TwiddleRegs<T, LG, NT> tr;
+  if (twg) tr.load(twg);
   for (int e0 = threadIdx.x; e0 < n; e0 += B * NT) {
     T vx[B], vy[B];
 #pragma unroll
@@ -322,11 +340,7 @@ __device__ __forceinline__ void rows_in(cplx<T>* buf, int LS, const cplx<T>* src
       if (e < n) buf[(e >> LG) * LS + (e & (N - 1))] = cplx<T>{vx[k], vy[k]};
     }
   }
-#pragma unroll
-  for (int k = 0; k < TW; ++k) {
-    const int t = threadIdx.x + k * NT;
-    if (twg && t < (N >> 1)) twl[t] = cplx<T>{tx[k], ty[k]};
-  }
+  if (twg) tr.store(twl);
 }
 
 // signed derivative frequency for index k of an N-point axis (Nyquist -> 0)
@@ -347,20 +361,22 @@ __device__ __forceinline__ void zfwd_body(SimC<T>& d, int lb, unsigned char* sme
   cplx<T>* A = reinterpret_cast<cplx<T>*>(smem);  // B lines: m* + i w*
   cplx<T>* Vp = A + B * LS;                       // B/2 lines: v(row 2q) + i v(row 2q+1)
   cplx<T>* tw = Vp + (B >> 1) * LS;
-  load_twiddles(tw, d);
+  TwiddleRegs<T, LG, kThreads> tr;
+  tr.load(d.tw);  // in flight with the first batch of field loads
   const T dt = (T)d.dt, gam = (T)d.gamma, adt = (T)(d.alpha * d.dt);
   const bool freeze_v = d.flags & SIPF_FLAG_FREEZE_V;
   const bool impl_v = d.flags & SIPF_FLAG_IMPLICIT_V;
   Acc acc;
   acc_init(acc);
-  // kLoadBatch elements per thread have their loads in flight together (the stores to v and
-  // ubar would otherwise order each element's loads after the previous element's stores)
+  // ZBatch elements per thread have their loads in flight together (the stores to v and ubar
+  // would otherwise order each element's loads after the previous element's stores)
+  constexpr int ZB = ZBatch<T>::n;
   const int nel = B * N;
   const int64_t g0 = r0 * N;  // first node of the block's rows
-  for (int e0 = threadIdx.x; e0 < nel; e0 += kLoadBatch * kThreads) {
-    T u[kLoadBatch], mm[kLoadBatch], vv[kLoadBatch], ww[kLoadBatch];
+  for (int e0 = threadIdx.x; e0 < nel; e0 += ZB * kThreads) {
+    T u[ZB], mm[ZB], vv[ZB], ww[ZB];
 #pragma unroll
-    for (int k = 0; k < kLoadBatch; ++k) {
+    for (int k = 0; k < ZB; ++k) {
       const int e = e0 + k * kThreads;
       if (e < nel) {
         u[k] = d.ubar[g0 + e];
@@ -370,7 +386,7 @@ __device__ __forceinline__ void zfwd_body(SimC<T>& d, int lb, unsigned char* sme
       }
     }
 #pragma unroll
-    for (int k = 0; k < kLoadBatch; ++k) {
+    for (int k = 0; k < ZB; ++k) {
       const int e = e0 + k * kThreads;
       if (e < nel) {
         const int rr = e >> LG, iz = e & (N - 1);
@@ -390,6 +406,7 @@ __device__ __forceinline__ void zfwd_body(SimC<T>& d, int lb, unsigned char* sme
       }
     }
   }
+  tr.store(tw);
   __syncthreads();
   line_fwd<T, LG, true>(A, B + (B >> 1), LS, 1, tw);
   constexpr int H = (N >> 1) + 1;
@@ -792,52 +809,98 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
   cplx<T>* GG = MW + B * LS;                      // B lines: d1 v + i d2 v
   cplx<T>* GZ = GG + B * LS;                      // B/2 lines: d3 v rows 2q + i 2q+1
   cplx<T>* tw = GZ + Bh * LS;
-  load_twiddles(tw, d);
-  constexpr int H = (N >> 1) + 1;
-  const T cz = d.gz_scale;  // 2 pi / L over the transforms SV went through (N or N^2)
-  for (int e = threadIdx.x; e < H * Bh; e += kThreads) {
-    const int kz = e / Bh, q = e - kz * Bh;
-    const bool mirror = kz > 0 && kz < (N >> 1);
-    const int pk = fpos<LG>(kz), pc = fpos<LG>((N - kz) & (N - 1));
-    const T kk = cz * (T)deriv_freq(kz, N);
-    cplx<T> gz[2];
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int rr = 2 * q + h;
-      const int64_t o = (int64_t)kz * N2 + r0 + rr;
-      const cplx<T> M = d.SM[o], W = d.SW[o], Gx = d.SGx[o], Gy = d.SGy[o], V = d.SVg[o];
-      MW[rr * LS + pk] = cplx<T>{M.x - W.y, M.y + W.x};
-      GG[rr * LS + pk] = cplx<T>{Gx.x - Gy.y, Gx.y + Gy.x};
-      if (mirror) {
-        MW[rr * LS + pc] = cplx<T>{M.x + W.y, W.x - M.y};
-        GG[rr * LS + pc] = cplx<T>{Gx.x + Gy.y, Gy.x - Gx.y};
-      }
-      gz[h] = cplx<T>{-kk * V.y, kk * V.x};
-    }
-    GZ[q * LS + pk] = cplx<T>{gz[0].x - gz[1].y, gz[0].y + gz[1].x};
-    if (mirror) GZ[q * LS + pc] = cplx<T>{gz[0].x + gz[1].y, gz[1].x - gz[0].y};
-  }
-  __syncthreads();
-  line_inv<T, LG, true>(MW, 2 * B + Bh, LS, 1, tw);
   const bool freeze_m = d.flags & SIPF_FLAG_FREEZE_M;
   const bool freeze_w = d.flags & SIPF_FLAG_FREEZE_W;
-  Acc acc;
-  acc_init(acc);
-  // the old w (and, with m frozen, m) of kLoadBatch elements per thread loaded together
+  constexpr int ZB = ZBatch<T>::n;
   const int nel = B * N;
   const int64_t g0 = r0 * N;
-  for (int e0 = threadIdx.x; e0 < nel; e0 += kLoadBatch * kThreads) {
-    T wold[kLoadBatch], mold[kLoadBatch];
+  // The old w (and, with m frozen, m) of the first ZB elements per thread - all of them,
+  // unless a block has more than ZB kThreads elements - are loaded first: they are needed
+  // only after the transforms, so their loads overlap everything before.
+  T wold[ZB], mold[ZB];
 #pragma unroll
-    for (int k = 0; k < kLoadBatch; ++k) {
-      const int e = e0 + k * kThreads;
-      if (e < nel) {
-        wold[k] = d.w[g0 + e];
-        if (freeze_m) mold[k] = d.m[g0 + e];
+  for (int k = 0; k < ZB; ++k) {
+    const int e = threadIdx.x + k * kThreads;
+    if (e < nel) {
+      wold[k] = d.w[g0 + e];
+      if (freeze_m) mold[k] = d.m[g0 + e];
+    }
+  }
+  TwiddleRegs<T, LG, kThreads> tr;
+  tr.load(d.tw);
+  constexpr int H = (N >> 1) + 1;
+  const T cz = d.gz_scale;  // 2 pi / L over the transforms SV went through (N or N^2)
+  // spectra of IB (k3, row pair) items per thread loaded together: 5 spectra x 2 rows each
+  constexpr int IB = sizeof(T) == 4 ? 2 : 1;
+  const int n1 = H * Bh;
+  for (int e0 = threadIdx.x; e0 < n1; e0 += IB * kThreads) {
+    T sv[IB][2][10];  // (M, W, Gx, Gy, V) x (re, im) of rows 2q and 2q + 1
+#pragma unroll
+    for (int ib = 0; ib < IB; ++ib) {
+      const int e = e0 + ib * kThreads;
+      if (e < n1) {
+        const int kz = e / Bh, q = e - kz * Bh;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int64_t o = (int64_t)kz * N2 + r0 + 2 * q + h;
+          const cplx<T> M = d.SM[o], W = d.SW[o], Gx = d.SGx[o], Gy = d.SGy[o], V = d.SVg[o];
+          sv[ib][h][0] = M.x;
+          sv[ib][h][1] = M.y;
+          sv[ib][h][2] = W.x;
+          sv[ib][h][3] = W.y;
+          sv[ib][h][4] = Gx.x;
+          sv[ib][h][5] = Gx.y;
+          sv[ib][h][6] = Gy.x;
+          sv[ib][h][7] = Gy.y;
+          sv[ib][h][8] = V.x;
+          sv[ib][h][9] = V.y;
+        }
       }
     }
 #pragma unroll
-    for (int k = 0; k < kLoadBatch; ++k) {
+    for (int ib = 0; ib < IB; ++ib) {
+      const int e = e0 + ib * kThreads;
+      if (e < n1) {
+        const int kz = e / Bh, q = e - kz * Bh;
+        const bool mirror = kz > 0 && kz < (N >> 1);
+        const int pk = fpos<LG>(kz), pc = fpos<LG>((N - kz) & (N - 1));
+        const T kk = cz * (T)deriv_freq(kz, N);
+        cplx<T> gz[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int rr = 2 * q + h;
+          const T* a = sv[ib][h];
+          MW[rr * LS + pk] = cplx<T>{a[0] - a[3], a[1] + a[2]};
+          GG[rr * LS + pk] = cplx<T>{a[4] - a[7], a[5] + a[6]};
+          if (mirror) {
+            MW[rr * LS + pc] = cplx<T>{a[0] + a[3], a[2] - a[1]};
+            GG[rr * LS + pc] = cplx<T>{a[4] + a[7], a[6] - a[5]};
+          }
+          gz[h] = cplx<T>{-kk * a[9], kk * a[8]};
+        }
+        GZ[q * LS + pk] = cplx<T>{gz[0].x - gz[1].y, gz[0].y + gz[1].x};
+        if (mirror) GZ[q * LS + pc] = cplx<T>{gz[0].x + gz[1].y, gz[1].x - gz[0].y};
+      }
+    }
+  }
+  tr.store(tw);
+  __syncthreads();
+  line_inv<T, LG, true>(MW, 2 * B + Bh, LS, 1, tw);
+  Acc acc;
+  acc_init(acc);
+  for (int e0 = threadIdx.x; e0 < nel; e0 += ZB * kThreads) {
+    if (e0 != (int)threadIdx.x) {  // elements beyond the first ZB per thread
+#pragma unroll
+      for (int k = 0; k < ZB; ++k) {
+        const int e = e0 + k * kThreads;
+        if (e < nel) {
+          wold[k] = d.w[g0 + e];
+          if (freeze_m) mold[k] = d.m[g0 + e];
+        }
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < ZB; ++k) {
       const int e = e0 + k * kThreads;
       if (e >= nel) continue;
       const int rr = e >> LG, iz = e & (N - 1);

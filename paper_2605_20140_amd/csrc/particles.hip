@@ -487,7 +487,7 @@ __global__ void __launch_bounds__(kThreads) k_particles(Batch<T> bt, int src_set
 // square tiles of kTile2^2 cells with a (kTile2 + 3)^2-node LDS region, two Wiener
 // components (the first two normals of the Philox block).  The gather array holds
 // (d1 v, -, d2 v, w) per node.
-constexpr int kR2 = kTile2 + 3;  // nodes per axis of a 2D region (one-cell margin each side)
+constexpr int kR2 = kTile2 + 2 * kM2 + 1;  // nodes per axis of a 2D region
 constexpr int kR2sq = kR2 * kR2;
 
 template <typename T>
@@ -568,8 +568,8 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
   const int N = d.N;
   const int nt = d.ntile1;
   Region rg;
-  rg.o[0] = (tile / nt) * kTile2 - 1;
-  rg.o[1] = (tile % nt) * kTile2 - 1;
+  rg.o[0] = (tile / nt) * kTile2 - kM2;
+  rg.o[1] = (tile % nt) * kTile2 - kM2;
   rg.o[2] = 0;
   const bool use_region = d.use_region;
   T* const ubar = d.ubar;

@@ -23,11 +23,19 @@ constexpr int kTile = 8;
 constexpr int kTile2 = 16;  // square tiles of the two-dimensional form
 constexpr int kChunk = 4096;
 constexpr int kBinBlock = 2048;  // particles per block of the binning count kernel
-// Steps between binnings when the caller leaves it to the library.  At 128^3 / 2^23, dt 5e-4:
-// every 8 steps the binning costs 29 us per step, every 12 steps 21.5 us while the particle
-// pass grows by 1 us (more particles past the drift margin), every 16 and 24 steps the
-// particle pass grows by 5 and 15 us.
-constexpr int kResortDefault = 12;
+// Drift margin of a tile's LDS region, in cells on each side: 3D one cell (11^3 nodes for
+// the trilinear stencil; more would cost blocks per CU), 2D four cells (25^2 nodes).
+constexpr int kM2 = 4;
+// Steps between binnings when the caller leaves it to the library: the largest k for which
+// the expected diffusive displacement since the last binning, sqrt(k) s cells with
+// s = sqrt(2 D_u dt) / h per step, stays within kBinDrift cells (at most kResortMax).
+// Calibrated on the bench workloads.  128^3 / 2^23, s = 0.128: every 8, 12, 16, 24 steps
+// 284, 277.5, 277, 283 us per step (binning cost against particles past the margin).  The
+// 2D example at 1024^2 / 2^22, s = 0.76: with a one-cell margin 228 us at best (every 2 to 4
+// steps), with four cells every 6, 8, 12, 16 steps 191, 188, 187, 192 us.
+constexpr double kBinDrift3 = 0.45;
+constexpr double kBinDrift2 = 2.4;
+constexpr int kResortMax = 64;
 
 // Plane pass: one block of kPlaneThreads per k3 plane and job when a plane fits in LDS.
 constexpr int kPlaneThreads = 1024;
