@@ -157,6 +157,26 @@ Layout make_layout(const sipf_params& p) {
   return L;
 }
 
+// second stream and events of a captured step's fork (binning) and join (particle pass)
+struct StepFork {
+  hipStream_t aux = nullptr;
+  hipEvent_t fork = nullptr, join = nullptr;
+};
+
+hipError_t create_fork(StepFork& f) {
+  hipError_t e = hipStreamCreateWithFlags(&f.aux, hipStreamNonBlocking);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&f.fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&f.join, hipEventDisableTiming);
+  return e;
+}
+
+void destroy_fork(StepFork& f) {
+  if (f.join) (void)hipEventDestroy(f.join);
+  if (f.fork) (void)hipEventDestroy(f.fork);
+  if (f.aux) (void)hipStreamDestroy(f.aux);
+  f = StepFork{};
+}
+
 }  // namespace
 
 struct sipf_sim {
@@ -166,6 +186,7 @@ struct sipf_sim {
   Layout lay;
   hipStream_t stream = nullptr;
   hipStream_t cap = nullptr;
+  StepFork fork;                      // second stream of the captured binning step
   hipStream_t last_stream = nullptr;  // stream of the last batched step, if any
   hipEvent_t ev = nullptr;            // orders this simulation's streams for batches
   int device = 0;
@@ -213,9 +234,20 @@ void enqueue_fft(const std::vector<FftGroup<T>>& groups, hipStream_t st) {
 template <typename T>
 void enqueue_step(const Batch<T>& b, const int* tot, int nsims,
                   const std::vector<FftGroup<T>>& groups, int bin, int order, int dim,
-                  hipStream_t st) {
-  if (bin) launch_binning<T>(b, tot, nsims, dim, st);
+                  hipStream_t st, const StepFork* fk) {
+  // The binning kernels touch only the particles and their tables, the field passes only
+  // grids and spectra: on binning steps the binning runs on a second stream beside the field
+  // passes (filling the CUs they leave idle), and the particle pass waits for both.
+  if (bin && fk) {
+    (void)hipEventRecord(fk->fork, st);
+    (void)hipStreamWaitEvent(fk->aux, fk->fork, 0);
+    launch_binning<T>(b, tot, nsims, dim, fk->aux);
+    (void)hipEventRecord(fk->join, fk->aux);
+  } else if (bin) {
+    launch_binning<T>(b, tot, nsims, dim, st);
+  }
   enqueue_fft<T>(groups, st);
+  if (bin && fk) (void)hipStreamWaitEvent(st, fk->join, 0);
   launch_particles<T>(b, tot[K_PART], bin ? 1 : 0, 0, order, dim, st);
   launch_finalize<T>(b, nsims, st);
 }
@@ -449,14 +481,15 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
 
   // capture one step as a graph on a private stream; replays go to the caller's stream
   HIPCHK(hipStreamCreateWithFlags(&sim->cap, hipStreamNonBlocking));
+  HIPCHK(create_fork(sim->fork));
   const auto groups = single_groups<T>(sim, b);
   HIPCHK(hipStreamBeginCapture(sim->cap, hipStreamCaptureModeThreadLocal));
-  enqueue_step<T>(b, sim->counts, 1, groups, 0, p.deposit_order, dim, sim->cap);
+  enqueue_step<T>(b, sim->counts, 1, groups, 0, p.deposit_order, dim, sim->cap, nullptr);
   HIPCHK(hipStreamEndCapture(sim->cap, &sim->graph));
   HIPCHK(hipGetLastError());
   HIPCHK(hipGraphInstantiate(&sim->exec, sim->graph, nullptr, nullptr, 0));
   HIPCHK(hipStreamBeginCapture(sim->cap, hipStreamCaptureModeThreadLocal));
-  enqueue_step<T>(b, sim->counts, 1, groups, 1, p.deposit_order, dim, sim->cap);
+  enqueue_step<T>(b, sim->counts, 1, groups, 1, p.deposit_order, dim, sim->cap, &sim->fork);
   HIPCHK(hipStreamEndCapture(sim->cap, &sim->graph_bin));
   HIPCHK(hipGetLastError());
   HIPCHK(hipGraphInstantiate(&sim->exec_bin, sim->graph_bin, nullptr, nullptr, 0));
@@ -621,6 +654,7 @@ std::mutex g_batch_mu;
 std::vector<BatchGraph*> g_graphs;
 uint64_t g_use_clock = 0;
 hipStream_t g_cap_stream[64] = {};
+StepFork g_cap_fork[64];  // per device, like the capture stream (kept until the process ends)
 
 void free_batch_graph(BatchGraph* e) {
   if (e->done) (void)hipEventSynchronize(e->done);
@@ -719,6 +753,7 @@ int build_batch_graph(sipf_sim* const* sims, int nsims, int dev, BatchGraph** ou
   if (rc == SIPF_OK) chk(hipEventCreateWithFlags(&e->done, hipEventDisableTiming), "hipEventCreate");
   if (rc == SIPF_OK && !g_cap_stream[dev])
     chk(hipStreamCreateWithFlags(&g_cap_stream[dev], hipStreamNonBlocking), "hipStreamCreate");
+  if (rc == SIPF_OK && !g_cap_fork[dev].aux) chk(create_fork(g_cap_fork[dev]), "step fork");
   unsigned char* base = static_cast<unsigned char*>(e->table);
   const Batch<T> b = table_batch<T>(base, nsims);
   for (size_t g = 0; g < sub.size(); ++g)
@@ -727,7 +762,7 @@ int build_batch_graph(sipf_sim* const* sims, int nsims, int dev, BatchGraph** ou
     chk(hipStreamBeginCapture(g_cap_stream[dev], hipStreamCaptureModeThreadLocal), "capture");
     if (rc != SIPF_OK) break;
     enqueue_step<T>(b, tot.data(), nsims, groups, bin, sims[0]->prm.deposit_order, 3,
-                    g_cap_stream[dev]);
+                    g_cap_stream[dev], &g_cap_fork[dev]);
     chk(hipStreamEndCapture(g_cap_stream[dev], &e->graph[bin]), "hipStreamEndCapture");
     if (rc == SIPF_OK) chk(hipGetLastError(), "batched launch");
     if (rc == SIPF_OK)
@@ -1069,6 +1104,7 @@ void sipf_destroy(sipf_sim* sim) {
   if (sim->exec_bin) (void)hipGraphExecDestroy(sim->exec_bin);
   if (sim->graph_bin) (void)hipGraphDestroy(sim->graph_bin);
   if (sim->cap) (void)hipStreamDestroy(sim->cap);
+  destroy_fork(sim->fork);
   delete sim;
 }
 
