@@ -32,24 +32,29 @@ __global__ void __launch_bounds__(kFinThreads) k_diag_finalize(Batch<T> bt, int 
   w[t] = d.diag[t];
   d.diag[t] = slot_identity(sl);
   __syncthreads();
-  if (t < D_COUNT) {
-    unsigned long long r = slot_identity(t);
-    double x = 0.0;
-    for (int c = 0; c < kStripes; ++c) {
-      const unsigned long long v = w[c * kStripeWords + t];
-      if (t < D_MIN_V) {
-        double y;
-        __builtin_memcpy(&y, &v, 8);
-        x += y;
-      } else if (t <= D_MIN_U) {
-        r = slot_is_max(t) ? (v > r ? v : r) : (v < r ? v : r);
-      } else {
-        r += v;
+  // one wavefront per slot, lane c holding stripe c's word, reduced across the lanes
+  static_assert(kStripes == 64 && D_COUNT <= kFinThreads / 64, "one stripe per lane");
+  const int slot = t >> 6, lane = t & 63;
+  if (slot < D_COUNT) {
+    unsigned long long r = w[lane * kStripeWords + slot];
+    if (slot < D_MIN_V) {
+      double x;
+      __builtin_memcpy(&x, &r, 8);
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+      __builtin_memcpy(&r, &x, 8);
+    } else {
+      const bool mx = slot_is_max(slot), cnt = slot > D_MIN_U;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long v = (unsigned long long)__shfl_xor((long long)r, o, 64);
+        r = cnt ? r + v : (mx ? (v > r ? v : r) : (v < r ? v : r));
       }
     }
-    if (t < D_MIN_V) __builtin_memcpy(&r, &x, 8);
-    d.diag[(mode == 2 ? kDiagResultU : kDiagResult) + t] = r;
-    if (t == 0 && mode == 0) *d.step += 1;
+    if (lane == 0) {
+      d.diag[(mode == 2 ? kDiagResultU : kDiagResult) + slot] = r;
+      if (slot == 0 && mode == 0) *d.step += 1;
+    }
   }
 }
 
