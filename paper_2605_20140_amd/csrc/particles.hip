@@ -169,13 +169,18 @@ constexpr int kPer = kChunk / kThreads;  // particles per thread
 // s_waitcnt operand for vmcnt(0) alone (expcnt and lgkmcnt at their no-wait maxima)
 constexpr int kWaitVmcnt0 = 0x0F70;
 // particles whose loads are issued together (float64 ones need twice the registers)
+// type of the LDS deposit accumulator (float64 in both forms: a tile's sums mix up to
+// thousands of contributions per node)
+template <typename T> struct LdsAccT { using type = double; };
+template <typename T> using LdsAcc = typename LdsAccT<T>::type;
+
 template <typename T> struct LoadBatch { static constexpr int n = 8; };
 template <> struct LoadBatch<double> { static constexpr int n = 4; };
 // gather-region nodes per thread whose loads are in flight together (24 VGPRs of data)
 template <typename T> struct kStageGroup { static constexpr int n = 24 / (int)sizeof(T); };
 
 template <int R, typename T>
-__device__ __forceinline__ void deposit_lds(double* acc, const Stencil<T>& st, const int l[3],
+__device__ __forceinline__ void deposit_lds(LdsAcc<T>* acc, const Stencil<T>& st, const int l[3],
                                             T q) {
   T wx[2], wy[2], wz[2];
   weights(st, wx, wy, wz);
@@ -186,7 +191,7 @@ __device__ __forceinline__ void deposit_lds(double* acc, const Stencil<T>& st, c
 #pragma unroll
       for (int cc = 0; cc < 2; ++cc)
         atomicAdd(&acc[rindex<R>(l[0] + aa, l[1] + bb, l[2] + cc)],
-                  (double)(q * wx[aa] * wy[bb] * wz[cc]));
+                  (LdsAcc<T>)(q * wx[aa] * wy[bb] * wz[cc]));
 }
 
 // Fourth-order assignment R_h^(4) (Sec. 2.2.1) in factored form.  With f the fractional
@@ -242,11 +247,11 @@ __device__ __forceinline__ void for_r4(const W4<T>& w, F&& fn) {
 }
 
 template <int R, typename T>
-__device__ __forceinline__ void deposit4_lds(double* acc, const Stencil<T>& st, const int l[3],
+__device__ __forceinline__ void deposit4_lds(LdsAcc<T>* acc, const Stencil<T>& st, const int l[3],
                                              T q) {
   const W4<T> w = weights4(st);
   for_r4(w, [&](int a, int b, int c, T wt) {
-    atomicAdd(&acc[rindex<R>(l[0] + a, l[1] + b, l[2] + c)], (double)(q * wt));
+    atomicAdd(&acc[rindex<R>(l[0] + a, l[1] + b, l[2] + c)], (LdsAcc<T>)(q * wt));
   });
 }
 
@@ -262,7 +267,7 @@ __device__ __forceinline__ void deposit4_global(T* ubar, const Stencil<T>& st, T
 
 // deposit of one particle with the assignment of order ORDER
 template <int ORDER, int R, typename T>
-__device__ __forceinline__ void deposit_one(T* ubar, double* acc, const Stencil<T>& st,
+__device__ __forceinline__ void deposit_one(T* ubar, LdsAcc<T>* acc, const Stencil<T>& st,
                                             const Region& rg, bool use_region, int N, T q) {
   int l[3];
   if (ORDER == 4) {
@@ -327,7 +332,7 @@ __global__ void __launch_bounds__(kThreads) k_particles(Batch<T> bt, int src_set
   load_batch(0);  // in flight while the region is staged
 
   vec4<T>* gl = reinterpret_cast<vec4<T>*>(smem_raw);  // gather array of the region
-  double* acc = reinterpret_cast<double*>(gl + R3);  // deposit accumulator
+  LdsAcc<T>* acc = reinterpret_cast<LdsAcc<T>*>(gl + R3);  // deposit accumulator
   if (use_region) {
     // groups of kStageGroup nodes per thread: all loads of a group in flight together
     constexpr int kS = (R3 + kThreads - 1) / kThreads;
@@ -355,7 +360,7 @@ __global__ void __launch_bounds__(kThreads) k_particles(Batch<T> bt, int src_set
         const int e = threadIdx.x + (k0 + k) * kThreads;
         if (k0 + k < kS && e < R3) {
           if (!deposit_only) gl[e] = vec4<T>{s0[k], s1[k], s2[k], s3[k]};
-          acc[e] = 0.0;
+          acc[e] = (LdsAcc<T>)0;
         }
       }
     }
@@ -470,8 +475,8 @@ __global__ void __launch_bounds__(kThreads) k_particles(Batch<T> bt, int src_set
   if (use_region) {
     __syncthreads();
     for (int e = threadIdx.x; e < R3; e += kThreads) {
-      const double v = acc[e];
-      if (v != 0.0) {
+      const LdsAcc<T> v = acc[e];
+      if (v != (LdsAcc<T>)0) {
         const int rz = e % R, ry = (e / R) % R, rx = e / (R * R);
         unsafeAtomicAdd(&d.ubar[node((rg.o[0] + rx) & (N - 1), (rg.o[1] + ry) & (N - 1),
                                      (rg.o[2] + rz) & (N - 1), N)],
@@ -532,7 +537,7 @@ __device__ __forceinline__ void box_muller2(uint32_t r0, uint32_t r1, float z[2]
 }
 
 template <typename T>
-__device__ __forceinline__ void deposit2(T* ubar, double* acc, const Stencil<T>& st,
+__device__ __forceinline__ void deposit2(T* ubar, LdsAcc<T>* acc, const Stencil<T>& st,
                                          const Region& rg, bool use_region, int N, T q) {
   const T wx[2] = {(T)1 - st.f[0], st.f[0]};
   const T wy[2] = {(T)1 - st.f[1], st.f[1]};
@@ -542,7 +547,7 @@ __device__ __forceinline__ void deposit2(T* ubar, double* acc, const Stencil<T>&
     for (int a = 0; a < 2; ++a)
 #pragma unroll
       for (int b = 0; b < 2; ++b)
-        atomicAdd(&acc[(l[0] + a) * kR2 + l[1] + b], (double)(q * wx[a] * wy[b]));
+        atomicAdd(&acc[(l[0] + a) * kR2 + l[1] + b], (LdsAcc<T>)(q * wx[a] * wy[b]));
   } else {
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -597,7 +602,7 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
   load_batch(0);  // in flight while the region is staged
 
   vec4<T>* gl = reinterpret_cast<vec4<T>*>(smem_raw);
-  double* acc = reinterpret_cast<double*>(gl + kR2sq);
+  LdsAcc<T>* acc = reinterpret_cast<LdsAcc<T>*>(gl + kR2sq);
   if (use_region) {
     constexpr int kS = (kR2sq + kThreads - 1) / kThreads;
     T s0[kS], s1[kS], s2[kS], s3[kS];
@@ -621,7 +626,7 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
       const int e = threadIdx.x + k * kThreads;
       if (e < kR2sq) {
         if (!deposit_only) gl[e] = vec4<T>{s0[k], s1[k], s2[k], s3[k]};
-        acc[e] = 0.0;
+        acc[e] = (LdsAcc<T>)0;
       }
     }
     __syncthreads();
@@ -709,8 +714,8 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
   if (use_region) {
     __syncthreads();
     for (int e = threadIdx.x; e < kR2sq; e += kThreads) {
-      const double v = acc[e];
-      if (v != 0.0) {
+      const LdsAcc<T> v = acc[e];
+      if (v != (LdsAcc<T>)0) {
         const int ry = e % kR2, rx = e / kR2;
         unsafeAtomicAdd(&d.ubar[(int64_t)((rg.o[0] + rx) & (N - 1)) * N +
                                 ((rg.o[1] + ry) & (N - 1))],
@@ -903,7 +908,7 @@ __global__ void __launch_bounds__(kThreads) k_bin_scatter(Batch<T> bt) {
 
 template <typename T, int ORDER>
 size_t particle_lds_bytes() {
-  return Reg<ORDER>::R3 * (sizeof(vec4<T>) + sizeof(double));
+  return Reg<ORDER>::R3 * (sizeof(vec4<T>) + sizeof(LdsAcc<T>));
 }
 
 template <typename T>
@@ -912,7 +917,7 @@ void launch_particles(const Batch<T>& b, int nblk, int src_set, int deposit_only
   if (nblk <= 0) return;
   if (dim == 2) {
     hipLaunchKernelGGL(k_particles2<T>, dim3(nblk), dim3(kThreads),
-                       kR2sq * (sizeof(vec4<T>) + sizeof(double)), st, b, src_set, deposit_only);
+                       kR2sq * (sizeof(vec4<T>) + sizeof(LdsAcc<T>)), st, b, src_set, deposit_only);
     return;
   }
   auto kern = order == 4 ? k_particles<T, 4> : k_particles<T, 2>;
