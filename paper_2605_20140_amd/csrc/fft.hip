@@ -215,9 +215,13 @@ struct TaskMap {
   }
 };
 
-// forward transforms: natural order -> fpos order
-template <typename T, int LG, bool LINE_FAST = false, int NT = kThreads>
-__device__ __forceinline__ void line_fwd(cplx<T>* buf, int nlines, int ls, int es, const cplx<T>* tw) {
+// Four-step line transforms (N = N1 N2).  Forward, first stage: N2-point transforms of the
+// N1 strided subsequences, times the twiddles; second stage: N1-point transforms of
+// contiguous groups, leaving frequency k at position fpos(k).  The inverse takes that order
+// and runs the stages the other way round.  Each stage ends at a barrier.
+template <typename T, int LG, bool LINE_FAST, int NT>
+__device__ __forceinline__ void fwd_stage1(cplx<T>* buf, int nlines, int ls, int es,
+                                           const cplx<T>* tw) {
   using S = Split<LG>;
   for (int t = threadIdx.x; t < nlines * S::N1; t += NT) {
     int line, n1;
@@ -233,6 +237,10 @@ __device__ __forceinline__ void line_fwd(cplx<T>* buf, int nlines, int ls, int e
       Lp[(k2 << S::L1) * es] = cmul(a[k2], twid<T, LG, 1>(tw, n1 * k2));
   }
   __syncthreads();
+}
+template <typename T, int LG, bool LINE_FAST, int NT>
+__device__ __forceinline__ void fwd_stage2(cplx<T>* buf, int nlines, int ls, int es) {
+  using S = Split<LG>;
   for (int t = threadIdx.x; t < nlines * S::N2; t += NT) {
     int line, k2;
     TaskMap<LG, LINE_FAST>::template map<S::L2>(t, nlines, line, k2);
@@ -246,10 +254,9 @@ __device__ __forceinline__ void line_fwd(cplx<T>* buf, int nlines, int ls, int e
   }
   __syncthreads();
 }
-
-// inverse (unnormalised) transforms: fpos order -> natural order
-template <typename T, int LG, bool LINE_FAST = false, int NT = kThreads>
-__device__ __forceinline__ void line_inv(cplx<T>* buf, int nlines, int ls, int es, const cplx<T>* tw) {
+template <typename T, int LG, bool LINE_FAST, int NT>
+__device__ __forceinline__ void inv_stage1(cplx<T>* buf, int nlines, int ls, int es,
+                                           const cplx<T>* tw) {
   using S = Split<LG>;
   for (int t = threadIdx.x; t < nlines * S::N2; t += NT) {
     int line, a2;
@@ -264,6 +271,10 @@ __device__ __forceinline__ void line_inv(cplx<T>* buf, int nlines, int ls, int e
     for (int c = 1; c < S::N1; ++c) Lp[c * es] = cmul(v[c], twid<T, LG, -1>(tw, c * a2));
   }
   __syncthreads();
+}
+template <typename T, int LG, bool LINE_FAST, int NT>
+__device__ __forceinline__ void inv_stage2(cplx<T>* buf, int nlines, int ls, int es) {
+  using S = Split<LG>;
   for (int t = threadIdx.x; t < nlines * S::N1; t += NT) {
     int line, c;
     TaskMap<LG, LINE_FAST>::template map<S::L1>(t, nlines, line, c);
@@ -276,6 +287,62 @@ __device__ __forceinline__ void line_inv(cplx<T>* buf, int nlines, int ls, int e
     for (int dd = 0; dd < S::N2; ++dd) Lp[(dd << S::L1) * es] = v[dd];
   }
   __syncthreads();
+}
+
+// forward transforms: natural order -> fpos order
+template <typename T, int LG, bool LINE_FAST = false, int NT = kThreads>
+__device__ __forceinline__ void line_fwd(cplx<T>* buf, int nlines, int ls, int es, const cplx<T>* tw) {
+  fwd_stage1<T, LG, LINE_FAST, NT>(buf, nlines, ls, es, tw);
+  fwd_stage2<T, LG, LINE_FAST, NT>(buf, nlines, ls, es);
+}
+// inverse transforms (unnormalised): fpos order -> natural order
+template <typename T, int LG, bool LINE_FAST = false, int NT = kThreads>
+__device__ __forceinline__ void line_inv(cplx<T>* buf, int nlines, int ls, int es, const cplx<T>* tw) {
+  inv_stage1<T, LG, LINE_FAST, NT>(buf, nlines, ls, es, tw);
+  inv_stage2<T, LG, LINE_FAST, NT>(buf, nlines, ls, es);
+}
+
+// Forward transform, pointwise multiplier and inverse transform of nlines lines.  The
+// forward second stage and the inverse first stage work on the same groups of N1 elements
+// with the same thread mapping, so the multiplier is applied in registers between them: one
+// LDS pass and one barrier less than the transforms alone, and no pass for the multiplier.
+// mul(line, p, v) returns v times the multiplier of position p (frequency ufpos(p)).
+// (Above 128 points the two transforms and the multiplier in registers cost more registers
+// than the pass saves - the x pass at 256 points went from 7 to 3 waves per SIMD in float32
+// - so there the multiplier is a pass of its own.)
+template <typename T, int LG, bool LINE_FAST, int NT, typename Mul>
+__device__ __forceinline__ void line_round_trip(cplx<T>* buf, int nlines, int ls, int es,
+                                                const cplx<T>* tw, const Mul& mul) {
+  using S = Split<LG>;
+  fwd_stage1<T, LG, LINE_FAST, NT>(buf, nlines, ls, es, tw);
+  if (LG > 7) {
+    fwd_stage2<T, LG, LINE_FAST, NT>(buf, nlines, ls, es);
+    for (int e = threadIdx.x; e < (nlines << LG); e += NT) {
+      const int line = e >> LG, p = e & ((1 << LG) - 1);
+      cplx<T>* q = buf + line * ls + p * es;
+      *q = mul(line, p, *q);
+    }
+    __syncthreads();
+    line_inv<T, LG, LINE_FAST, NT>(buf, nlines, ls, es, tw);
+    return;
+  }
+  for (int t = threadIdx.x; t < nlines * S::N2; t += NT) {
+    int line, k2;
+    TaskMap<LG, LINE_FAST>::template map<S::L2>(t, nlines, line, k2);
+    cplx<T>* Lp = buf + line * ls + (k2 << S::L1) * es;
+    cplx<T> a[S::N1];
+#pragma unroll
+    for (int n1 = 0; n1 < S::N1; ++n1) a[n1] = Lp[n1 * es];
+    reg_dft<T, S::N1, 1>(a);
+#pragma unroll
+    for (int k1 = 0; k1 < S::N1; ++k1) a[k1] = mul(line, (k2 << S::L1) + k1, a[k1]);
+    reg_dft<T, S::N1, -1>(a);
+    Lp[0] = a[0];
+#pragma unroll
+    for (int c = 1; c < S::N1; ++c) Lp[c * es] = cmul(a[c], twid<T, LG, -1>(tw, c * k2));
+  }
+  __syncthreads();
+  inv_stage2<T, LG, LINE_FAST, NT>(buf, nlines, ls, es);
 }
 
 template <typename T>
@@ -566,48 +633,40 @@ __device__ __forceinline__ void xpass_body(SimC<T>& d, int lb, unsigned char* sm
     }
   }
   __syncthreads();
-  line_fwd<T, LG>(buf, Bx, LS, 1, tw);
   const int qz = lap_freq(kz, N);
   const T k0 = d.two_pi_over_L;
-  for (int e = threadIdx.x; e < Bx * N; e += kThreads) {
-    const int c = e >> LG, p = e & (N - 1);
+  const T D = (T)(f == 0 ? d.D_m : d.D_w);
+  const T decay = (T)(f == 0 ? d.beta : 1.0);
+  const T dt = (T)d.dt, inv_n3 = d.inv_n3;
+  const bool use_lp = d.use_lowpass, implicit = d.mult_kind == 0;
+  const T* lpt = d.mtab + 2 * N;
+  const T* tab = d.mtab + (f < 2 ? f : 0) * N;
+  const T e_dec = implicit ? (T)0 : (T)exp(-dt * decay);
+  // multiplier at position p (frequency along x) of the line c (y = y0 + c, plane kz)
+  const auto mul = [=](int c, int p, cplx<T> val) {
     const int kx = ufpos<LG>(p);
     const int ky = ufpos<LG>(y0 + c);
-    cplx<T> val = buf[c * LS + p];
     if (f < 2) {
-      const T D = (T)(f == 0 ? d.D_m : d.D_w);
-      const T decay = (T)(f == 0 ? d.beta : 1.0);
       T mult;
-      if (d.mult_kind == 0) {
+      if (implicit) {
         const int qx = lap_freq(kx, N), qy = lap_freq(ky, N);
         const T k2 = k0 * k0 * (T)(qx * qx + qy * qy + qz * qz);
-        mult = (T)1 / ((T)1 + (T)d.dt * (decay + D * k2));
+        mult = (T)1 / ((T)1 + dt * (decay + D * k2));
       } else {
-        const T* tab = d.mtab + f * N;
-        mult = (T)exp(-(T)d.dt * decay) * tab[kx] * tab[ky] * tab[kz];
+        mult = e_dec * tab[kx] * tab[ky] * tab[kz];
       }
-      mult *= d.inv_n3;
-      if (d.use_lowpass) {
-        const T* lp = d.mtab + 2 * N;
-        mult *= lp[kx] * lp[ky] * lp[kz];
-      }
-      val = cscale(val, mult);
+      mult *= inv_n3;
+      if (use_lp) mult *= lpt[kx] * lpt[ky] * lpt[kz];
+      return cscale(val, mult);
     } else if (f == 2) {
-      T kk = k0 * (T)deriv_freq(kx, N) * d.inv_n3;
-      if (d.use_lowpass) {
-        const T* lp = d.mtab + 2 * N;
-        kk *= lp[kx] * lp[ky] * lp[kz];
-      }
-      val = cplx<T>{-kk * val.y, kk * val.x};
-    } else {
-      // low-pass filtered V for the y and z derivatives; 1/N undoes this x round trip
-      const T* lp = d.mtab + 2 * N;
-      val = cscale(val, lp[kx] * lp[ky] * lp[kz] / (T)N);
+      T kk = k0 * (T)deriv_freq(kx, N) * inv_n3;
+      if (use_lp) kk *= lpt[kx] * lpt[ky] * lpt[kz];
+      return cplx<T>{-kk * val.y, kk * val.x};
     }
-    buf[c * LS + p] = val;
-  }
-  __syncthreads();
-  line_inv<T, LG>(buf, Bx, LS, 1, tw);
+    // low-pass filtered V for the y and z derivatives; 1/N undoes this x round trip
+    return cscale(val, lpt[kx] * lpt[ky] * lpt[kz] / (T)N);
+  };
+  line_round_trip<T, LG, false, kThreads>(buf, Bx, LS, 1, tw, mul);
   for (int e = threadIdx.x; e < Bx * N; e += kThreads) {
     const int c = e % Bx, ix = e / Bx;
     dst[(int64_t)ix * N + y0 + c] = buf[c * LS + ix];
@@ -636,39 +695,34 @@ __device__ __forceinline__ void col2d_body(SimC<T>& d, int lb, unsigned char* sm
   cplx<T>* tw = buf + Bl * LS;
   rows_in<T, LG, kThreads>(buf, LS, src, nl * N, tw, d.tw);
   __syncthreads();
-  line_fwd<T, LG>(buf, nl, LS, 1, tw);
   const T k0 = d.two_pi_over_L;
   const T D = (T)(f == 0 ? d.D_m : d.D_w);
   const T decay = (T)(f == 0 ? d.beta : 1.0);
-  for (int e = threadIdx.x; e < nl * N; e += kThreads) {
-    const int line = e >> LG, p = e & (N - 1);
+  const T dt = (T)d.dt, inv_nd = d.inv_nd;
+  const bool use_lp = d.use_lowpass, implicit = d.mult_kind == 0;
+  const T* lpt = d.mtab + 2 * N;
+  const T* tab = d.mtab + (f < 2 ? f : 0) * N;
+  const T e_dec = implicit ? (T)0 : (T)exp(-dt * decay);
+  // multiplier at position p (frequency along i1) of the line k2 = kl0 + line
+  const auto mul = [=](int line, int p, cplx<T> val) {
     const int k1 = ufpos<LG>(p), k2 = kl0 + line;
-    cplx<T> val = buf[line * LS + p];
-    T lp = (T)1;
-    if (d.use_lowpass) {
-      const T* t = d.mtab + 2 * N;
-      lp = t[k1] * t[k2];
-    }
+    const T lp = use_lp ? lpt[k1] * lpt[k2] : (T)1;
     if (f < 2) {
       T mult;
-      if (d.mult_kind == 0) {
+      if (implicit) {
         const int q1 = lap_freq(k1, N), q2 = lap_freq(k2, N);
-        mult = (T)1 / ((T)1 + (T)d.dt * (decay + D * k0 * k0 * (T)(q1 * q1 + q2 * q2)));
+        mult = (T)1 / ((T)1 + dt * (decay + D * k0 * k0 * (T)(q1 * q1 + q2 * q2)));
       } else {
-        const T* tab = d.mtab + f * N;
-        mult = (T)exp(-(T)d.dt * decay) * tab[k1] * tab[k2];
+        mult = e_dec * tab[k1] * tab[k2];
       }
-      val = cscale(val, mult * d.inv_nd * lp);
+      return cscale(val, mult * inv_nd * lp);
     } else if (f == 2) {
-      const T kk = k0 * (T)deriv_freq(k1, N) * d.inv_nd * lp;
-      val = cplx<T>{-kk * val.y, kk * val.x};
-    } else {
-      val = cscale(val, lp / (T)N);
+      const T kk = k0 * (T)deriv_freq(k1, N) * inv_nd * lp;
+      return cplx<T>{-kk * val.y, kk * val.x};
     }
-    buf[line * LS + p] = val;
-  }
-  __syncthreads();
-  line_inv<T, LG>(buf, nl, LS, 1, tw);
+    return cscale(val, lp / (T)N);
+  };
+  line_round_trip<T, LG, false, kThreads>(buf, nl, LS, 1, tw, mul);
   for (int e = threadIdx.x; e < nl * N; e += kThreads)
     dst[e] = buf[(e >> LG) * LS + (e & (N - 1))];
 }
@@ -715,23 +769,15 @@ __device__ __forceinline__ void plane_body(SimC<T>& d, int lb, unsigned char* sm
       const cplx<T>* twg = pass == 0 ? (const cplx<T>*)d.tw : nullptr;  // loaded once
       rows_in<T, LG, NT>(Q, LSv, d.SV + off, NN, twv, twg);
       __syncthreads();
+      // i (2 pi / L) q v along the pass's axis (position p on a line of that axis)
+      const auto deriv = [c](int, int p, cplx<T> v) {
+        const T kk = c * (T)deriv_freq(ufpos<LG>(p), N);
+        return cplx<T>{-kk * v.y, kk * v.x};
+      };
       if (pass == 0)
-        line_fwd<T, LG, true, NT>(Q, N, 1, LSv, twv);  // along i1
+        line_round_trip<T, LG, true, NT>(Q, N, 1, LSv, twv, deriv);  // along i1
       else
-        line_fwd<T, LG, true, NT>(Q, N, LSv, 1, twv);  // along i2
-      for (int e = threadIdx.x; e < NN; e += NT) {
-        const int i1 = e >> LG, i2 = e & (N - 1);
-        const int q = deriv_freq(ufpos<LG>(pass == 0 ? i1 : i2), N);
-        const int pe = i1 * LSv + i2;
-        const cplx<T> val = Q[pe];
-        const T kk = c * (T)q;
-        Q[pe] = cplx<T>{-kk * val.y, kk * val.x};
-      }
-      __syncthreads();
-      if (pass == 0)
-        line_inv<T, LG, true, NT>(Q, N, 1, LSv, twv);
-      else
-        line_inv<T, LG, true, NT>(Q, N, LSv, 1, twv);
+        line_round_trip<T, LG, true, NT>(Q, N, LSv, 1, twv, deriv);  // along i2
       cplx<T>* dst = (pass == 0 ? d.SGx : d.SGy) + off;
       for (int e = threadIdx.x; e < NN; e += NT) dst[e] = Q[(e >> LG) * LSv + (e & (N - 1))];
       __syncthreads();
@@ -748,42 +794,39 @@ __device__ __forceinline__ void plane_body(SimC<T>& d, int lb, unsigned char* sm
   rows_in<T, LG, NT>(P, LS, src, NN, tw, d.tw);
   __syncthreads();
   line_fwd<T, LG, true, NT>(P, N, LS, 1, tw);  // along i2 (rows)
-  line_fwd<T, LG, true, NT>(P, N, 1, LS, tw);   // along i1 (columns)
   const int qz = lap_freq(kz, N);
   const T k0 = d.two_pi_over_L;
   const T D = (T)(job == 0 ? d.D_m : d.D_w);
   const T decay = (T)(job == 0 ? d.beta : 1.0);
-  for (int e = threadIdx.x; e < NN; e += NT) {
-    const int kx = ufpos<LG>(e >> LG), ky = ufpos<LG>(e & (N - 1));
-    const int pe = (e >> LG) * LS + (e & (N - 1));
-    cplx<T> val = P[pe];
-    T lp = (T)1;
-    if (d.use_lowpass) {
-      const T* t = d.mtab + 2 * N;
-      lp = t[kx] * t[ky] * t[kz];
-    }
+  const T dt = (T)d.dt, inv_n3 = d.inv_n3, inv_n2 = d.inv_n2;
+  const bool use_lp = d.use_lowpass, implicit = d.mult_kind == 0;
+  const T* lpt = d.mtab + 2 * N;
+  const T* tab = d.mtab + (job < 2 ? job : 0) * N;
+  const T lpz = use_lp ? lpt[kz] : (T)1;
+  const T sep_z = implicit ? (T)0 : (T)exp(-dt * decay) * tab[kz];
+  // multiplier at column position p (frequency along i1) of the line i2 (frequency along
+  // i2 from the row transforms)
+  const auto mul = [=](int i2, int p, cplx<T> val) {
+    const int kx = ufpos<LG>(p), ky = ufpos<LG>(i2);
+    const T lp = use_lp ? lpt[kx] * lpt[ky] * lpz : (T)1;
     if (job < 2) {
       T mult;
-      if (d.mult_kind == 0) {
+      if (implicit) {
         const int qx = lap_freq(kx, N), qy = lap_freq(ky, N);
         const T k2 = k0 * k0 * (T)(qx * qx + qy * qy + qz * qz);
-        mult = (T)1 / ((T)1 + (T)d.dt * (decay + D * k2));
+        mult = (T)1 / ((T)1 + dt * (decay + D * k2));
       } else {
-        const T* tab = d.mtab + job * N;
-        mult = (T)exp(-(T)d.dt * decay) * tab[kx] * tab[ky] * tab[kz];
+        mult = sep_z * tab[kx] * tab[ky];
       }
-      val = cscale(val, mult * d.inv_n3 * lp);
+      return cscale(val, mult * inv_n3 * lp);
     } else if (job < 4) {
-      const T kk = k0 * (T)deriv_freq(job == 2 ? kx : ky, N) * d.inv_n3 * lp;
-      val = cplx<T>{-kk * val.y, kk * val.x};
-    } else {
-      // low-pass filtered V for the z derivative; 1/N^2 undoes this x, y round trip
-      val = cscale(val, lp * d.inv_n2);
+      const T kk = k0 * (T)deriv_freq(job == 2 ? kx : ky, N) * inv_n3 * lp;
+      return cplx<T>{-kk * val.y, kk * val.x};
     }
-    P[pe] = val;
-  }
-  __syncthreads();
-  line_inv<T, LG, true, NT>(P, N, 1, LS, tw);
+    // low-pass filtered V for the z derivative; 1/N^2 undoes this x, y round trip
+    return cscale(val, lp * inv_n2);
+  };
+  line_round_trip<T, LG, true, NT>(P, N, 1, LS, tw, mul);  // along i1 (columns)
   line_inv<T, LG, true, NT>(P, N, LS, 1, tw);
   for (int e = threadIdx.x; e < NN; e += NT) dst[e] = P[(e >> LG) * LS + (e & (N - 1))];
 }
