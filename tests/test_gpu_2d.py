@@ -57,6 +57,18 @@ def test_2d_steps_fp64(N, P, steps):
     assert out["diag"]["step"] == steps and out["diag"]["n_nan"] == 0
 
 
+@pytest.mark.parametrize("resort_every", [1, 0])
+def test_2d_rebinning_period(resort_every):
+    """Every step, and the library's default period (four-cell tile margins in 2D)."""
+    ic = W.blob2d_initial_state(N=64, P=20000)
+    sim = gpu_sim(ic, resort_every=resort_every)
+    sim.step(12)
+    out = sim.fields()
+    sim.close()
+    ref = S.run(oracle_state(ic), oracle_params(ic["params"]), 12)
+    compare_state(out, ref, TOL64)
+
+
 def test_2d_fp32():
     ic = W.blob2d_initial_state(N=64, P=20000)
     out, _, _, ref, _ = _run(ic, 30, precision=1)

@@ -81,6 +81,20 @@ def test_sizes_and_ragged_tails_fp64(N, P, steps):
     compare_state(out, ref, TOL64)
 
 
+@pytest.mark.parametrize("resort_every", [1, 3, 7, 0])
+def test_rebinning_period_changes_only_summation_order(resort_every):
+    """Any tile re-binning period (0: the library's default from the diffusive step size)
+    gives the oracle's state: the period reorders the particles in memory and the deposit's
+    sums, nothing else."""
+    ic = W.make_initial_state("blob16", N=32, P=4096 * 3 + 77)
+    sim = gpu_sim(ic, resort_every=resort_every)
+    sim.step(25)
+    out = sim.fields()
+    sim.close()
+    ref = S.run(oracle_state(ic), oracle_params(ic["params"]), 25)
+    compare_state(out, ref, TOL64)
+
+
 def test_empty_particle_set_fp64():
     ic = W.make_initial_state("blob16", P=0)
     out, ref, _ = _run_both(ic, 10)
