@@ -36,7 +36,7 @@ struct Layout {
   size_t total = 0;
   size_t desc, blk, step, diag;
   size_t x[2], y[2], z[2], a[2], id[2];
-  size_t tcount, toff, coff, ctile, cinfo, key;
+  size_t tcount, toff, coff, cinfo, key;
   size_t ubar, v, m, w, g4;
   size_t SM, SW, SV, SGx, SGy, SVf;
   size_t tw, mtab;
@@ -135,7 +135,6 @@ Layout make_layout(const sipf_params& p) {
   L.tcount = take(ntiles * 4);
   L.toff = take((ntiles + 1) * 4);
   L.coff = take((ntiles + 1) * 4);
-  L.ctile = take(((P + kChunk - 1) / kChunk + ntiles) * 4);
   L.cinfo = take(((P + kChunk - 1) / kChunk + ntiles) * 16);
   L.key = take(P * 8);
   L.ubar = take(G * s);
@@ -360,7 +359,6 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   d.tcount = reinterpret_cast<uint32_t*>(ws + L.tcount);
   d.toff = reinterpret_cast<uint32_t*>(ws + L.toff);
   d.coff = reinterpret_cast<uint32_t*>(ws + L.coff);
-  d.ctile = reinterpret_cast<uint32_t*>(ws + L.ctile);
   d.cinfo = reinterpret_cast<uint4*>(ws + L.cinfo);
   d.max_chunks = (int)((P + kChunk - 1) / kChunk + d.ntiles);
   d.key = reinterpret_cast<uint32_t*>(ws + L.key);

@@ -168,7 +168,6 @@ __device__ __forceinline__ void deposit_global(T* ubar, const Stencil<T>& st, T 
 constexpr int kPer = kChunk / kThreads;  // particles per thread
 // s_waitcnt operand for vmcnt(0) alone (expcnt and lgkmcnt at their no-wait maxima)
 constexpr int kWaitVmcnt0 = 0x0F70;
-// particles whose loads are issued together (float64 ones need twice the registers)
 // type of the LDS deposit accumulator (float64 in both forms: a tile's sums mix up to
 // thousands of contributions per node)
 template <typename T> struct LdsAccT { using type = double; };
@@ -849,52 +848,72 @@ __global__ void __launch_bounds__(kThreads) k_bin_scan(Batch<T> bt) {
   const int s = find_sim(bt, K_SSCAN, lb);
   SimC<T>& d = sim_view(bt, s);
   const int nt = d.ntiles;
-  const int per = (nt + kThreads - 1) / kThreads;
-  const int b0 = threadIdx.x * per;
-  const int b1 = b0 + per < nt ? b0 + per : nt;
-  uint32_t sp = 0, sc = 0;
-  for (int t = b0; t < b1; ++t) {
-    const uint32_t c = d.tcount[t];
-    sp += c;
-    sc += (c + kChunk - 1) / kChunk;
-  }
+  // Segments of kScanSeg tiles per thread: the counts are loaded coalesced, all of a
+  // segment's loads in flight together, into LDS; each thread then scans kScanSeg
+  // consecutive tiles from there (a running carry links the segments).
+  constexpr int kScanSeg = 16;
+  constexpr int kSegTiles = kScanSeg * kThreads;
+  __shared__ uint32_t cnt[kSegTiles];
   __shared__ uint32_t pp[kThreads], pc[kThreads];
-  pp[threadIdx.x] = sp;
-  pc[threadIdx.x] = sc;
-  __syncthreads();
-  // inclusive Hillis-Steele scan of the per-thread sums
-  for (int off = 1; off < kThreads; off <<= 1) {
-    uint32_t ap = 0, ac = 0;
-    if ((int)threadIdx.x >= off) {
-      ap = pp[threadIdx.x - off];
-      ac = pc[threadIdx.x - off];
+  uint32_t carry_p = 0, carry_c = 0;  // tiles and chunks before the segment (uniform)
+  for (int s0 = 0; s0 < nt; s0 += kSegTiles) {
+    uint32_t v[kScanSeg];
+#pragma unroll
+    for (int j = 0; j < kScanSeg; ++j) {
+      const int t = s0 + (int)threadIdx.x + j * kThreads;
+      v[j] = t < nt ? d.tcount[t] : 0u;
     }
+#pragma unroll
+    for (int j = 0; j < kScanSeg; ++j) cnt[threadIdx.x + j * kThreads] = v[j];
     __syncthreads();
-    pp[threadIdx.x] += ap;
-    pc[threadIdx.x] += ac;
-    __syncthreads();
-  }
-  uint32_t rp = threadIdx.x ? pp[threadIdx.x - 1] : 0;
-  uint32_t rc = threadIdx.x ? pc[threadIdx.x - 1] : 0;
-  for (int t = b0; t < b1; ++t) {
-    const uint32_t c = d.tcount[t];
-    const uint32_t nch = (c + kChunk - 1) / kChunk;
-    d.toff[t] = rp;
-    d.coff[t] = rc;
-    for (uint32_t k = 0; k < nch; ++k) {
-      d.ctile[rc + k] = (uint32_t)t;
-      const uint32_t cs = rp + k * kChunk;
-      d.cinfo[rc + k] = uint4{cs, cs + kChunk < rp + c ? cs + kChunk : rp + c, (uint32_t)t, 0u};
+    const int b0 = (int)threadIdx.x * kScanSeg;
+    uint32_t sp = 0, sc = 0;
+#pragma unroll
+    for (int j = 0; j < kScanSeg; ++j) {
+      const uint32_t c = cnt[b0 + j];
+      sp += c;
+      sc += (c + kChunk - 1) / kChunk;
     }
-    rp += c;
-    rc += nch;
-    d.tcount[t] = 0;
+    pp[threadIdx.x] = sp;
+    pc[threadIdx.x] = sc;
+    __syncthreads();
+    // inclusive Hillis-Steele scan of the per-thread sums
+    for (int off = 1; off < kThreads; off <<= 1) {
+      uint32_t ap = 0, ac = 0;
+      if ((int)threadIdx.x >= off) {
+        ap = pp[threadIdx.x - off];
+        ac = pc[threadIdx.x - off];
+      }
+      __syncthreads();
+      pp[threadIdx.x] += ap;
+      pc[threadIdx.x] += ac;
+      __syncthreads();
+    }
+    uint32_t rp = carry_p + (threadIdx.x ? pp[threadIdx.x - 1] : 0u);
+    uint32_t rc = carry_c + (threadIdx.x ? pc[threadIdx.x - 1] : 0u);
+    for (int j = 0; j < kScanSeg; ++j) {
+      const int t = s0 + b0 + j;
+      if (t >= nt) break;
+      const uint32_t c = cnt[b0 + j];
+      const uint32_t nch = (c + kChunk - 1) / kChunk;
+      d.toff[t] = rp;
+      d.coff[t] = rc;
+      for (uint32_t k = 0; k < nch; ++k) {
+        const uint32_t cs = rp + k * kChunk;
+        d.cinfo[rc + k] = uint4{cs, cs + kChunk < rp + c ? cs + kChunk : rp + c, (uint32_t)t, 0u};
+      }
+      rp += c;
+      rc += nch;
+      d.tcount[t] = 0;
+    }
+    carry_p += pp[kThreads - 1];
+    carry_c += pc[kThreads - 1];
+    __syncthreads();  // pp, pc and cnt are rewritten by the next segment
   }
-  if (threadIdx.x == kThreads - 1) {
-    d.toff[nt] = pp[kThreads - 1];
-    d.coff[nt] = pc[kThreads - 1];
+  if (threadIdx.x == 0) {
+    d.toff[nt] = carry_p;
+    d.coff[nt] = carry_c;
   }
-
 }
 
 template <typename T, int DIM>

@@ -134,7 +134,6 @@ struct SimDesc {
   Ptr<uint32_t> tcount;  // ntiles: particles per tile (zero between binnings)
   Ptr<uint32_t> toff;    // ntiles + 1: first sorted index of each tile
   Ptr<uint32_t> coff;    // ntiles + 1: first chunk of each tile
-  Ptr<uint32_t> ctile;   // max_chunks: tile of each chunk
   Ptr<uint4> cinfo;      // max_chunks: (first particle, end, tile, -) of each chunk (set at
                          // binning, so a particle-pass block needs one lookup)
   int max_chunks;     // bound on the number of chunks: ceil(P / kChunk) + ntiles
