@@ -78,6 +78,13 @@ __device__ __forceinline__ void box_muller(uint32_t r0, uint32_t r1, uint32_t r2
   z[2] = rb * __builtin_amdgcn_cosf(u3);
 }
 
+// rho(w) = 2w / (1 + w) of the mass update: float64 exactly rounded; float32 with the
+// hardware reciprocal (about 1 ulp), since rho enters only through exp(dt (rho - 1))
+__device__ __forceinline__ double rho_of(double w) { return 2.0 * w / (1.0 + w); }
+__device__ __forceinline__ float rho_of(float w) {
+  return 2.0f * w * __builtin_amdgcn_rcpf(1.0f + w);
+}
+
 template <typename T>
 __device__ __forceinline__ T wrap_periodic(T x, T L) {
   if (x < (T)0) x += L;
@@ -448,7 +455,7 @@ __global__ void __launch_bounds__(kThreads)
       const T xn = wrap_periodic(x + d.drift * g0 + d.noise_amp * zn[0], d.L);
       const T yn = wrap_periodic(y + d.drift * g1 + d.noise_amp * zn[1], d.L);
       const T zz = wrap_periodic(z + d.drift * g2 + d.noise_amp * zn[2], d.L);
-      const T rho = (T)2 * gw / ((T)1 + gw);
+      const T rho = rho_of(gw);
       const double an = linear_mass ? a * (1.0 + d.dt * (double)rho - d.dt)
                                     : a * exp(d.dt * ((double)rho - 1.0));
       xo[i] = xn;
@@ -695,7 +702,7 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
       }
       const T xn = wrap_periodic(x + d.drift * g0 + d.noise_amp * zn[0], d.L);
       const T yn = wrap_periodic(y + d.drift * g1 + d.noise_amp * zn[1], d.L);
-      const T rho = (T)2 * gw / ((T)1 + gw);
+      const T rho = rho_of(gw);
       const double an = linear_mass ? a * (1.0 + d.dt * (double)rho - d.dt)
                                     : a * exp(d.dt * ((double)rho - 1.0));
       d.xs[0][i] = xn;
