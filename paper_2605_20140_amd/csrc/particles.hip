@@ -307,8 +307,11 @@ __global__ void __launch_bounds__(kThreads)
   const int nchunks = (int)d.coff[d.ntiles];
   const uint4 ci = d.cinfo[lb];  // lb < max_chunks; both loads in flight together
   if (lb >= nchunks) return;
-  const uint32_t start = ci.x, end = ci.y;
-  const int tile = (int)ci.z;
+  // uniform: every array below is based at the chunk's first particle, so that accesses
+  // take a scalar base and a small per-thread offset (no 64-bit address arithmetic)
+  const uint32_t start = __builtin_amdgcn_readfirstlane(ci.x);
+  const uint32_t cnt = __builtin_amdgcn_readfirstlane(ci.y) - start;
+  const int tile = (int)__builtin_amdgcn_readfirstlane(ci.z);
   const int N = d.N;
   const int nt = d.ntile1;
   Region rg;
@@ -318,11 +321,11 @@ __global__ void __launch_bounds__(kThreads)
   const bool use_region = d.use_region;
   T* const ubar = d.ubar;
 
-  const T* xi = d.xs[src_set];
-  const T* yi = d.ys[src_set];
-  const T* zi = d.zs[src_set];
-  const double* ai = d.as[src_set];
-  const uint32_t* idi = d.ids[src_set];
+  const T* xi = d.xs[src_set] + start;
+  const T* yi = d.ys[src_set] + start;
+  const T* zi = d.zs[src_set] + start;
+  const double* ai = d.as[src_set] + start;
+  const uint32_t* idi = d.ids[src_set] + start;
   constexpr int kB = LoadBatch<T>::n;
   T px[kB], py[kB], pz[kB];
   double pa[kB];
@@ -331,8 +334,8 @@ __global__ void __launch_bounds__(kThreads)
   auto load_batch = [&](int j0) {
 #pragma unroll
     for (int j = 0; j < kB; ++j) {
-      const uint32_t i = start + threadIdx.x + (j0 + j) * kThreads;
-      if (i < end) {
+      const uint32_t i = threadIdx.x + (j0 + j) * kThreads;  // within the chunk
+      if (i < cnt) {
         px[j] = xi[i];
         py[j] = yi[i];
         pz[j] = zi[i];
@@ -380,10 +383,11 @@ __global__ void __launch_bounds__(kThreads)
   }
 
   const uint32_t n = (uint32_t)(*d.step);
-  T* xo = d.xs[0];
-  T* yo = d.ys[0];
-  T* zo = d.zs[0];
-  double* ao = d.as[0];
+  T* xo = d.xs[0] + start;
+  T* yo = d.ys[0] + start;
+  T* zo = d.zs[0] + start;
+  double* ao = d.as[0] + start;
+  uint32_t* ido = d.ids[0] + start;
   const bool linear_mass = d.flags & SIPF_FLAG_LINEAR_MASS;
   const bool noise = !(d.flags & SIPF_FLAG_NO_NOISE);
   Acc dg;
@@ -397,8 +401,8 @@ __global__ void __launch_bounds__(kThreads)
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
 #pragma unroll
     for (int j = 0; j < kB; ++j) {
-      const uint32_t i = start + threadIdx.x + (j0 + j) * kThreads;
-      if (i >= end) continue;
+      const uint32_t i = threadIdx.x + (j0 + j) * kThreads;  // within the chunk
+      if (i >= cnt) continue;
       __builtin_amdgcn_sched_barrier(0);
       const T x = px[j], y = py[j], z = pz[j];
       const double a = pa[j];
@@ -462,7 +466,7 @@ __global__ void __launch_bounds__(kThreads)
       yo[i] = yn;
       zo[i] = zz;
       ao[i] = an;
-      if (src_set) d.ids[0][i] = pid[j];
+      if (src_set) ido[i] = pid[j];
       if (isfinite(an) && isfinite((double)xn) && isfinite((double)yn) && isfinite((double)zz)) {
         dg.sum[0] += an;
         acc_min(dg, D_MIN_A, an);
@@ -479,7 +483,7 @@ __global__ void __launch_bounds__(kThreads)
     // for this batch's stores: the compiler cannot tell that the exec-masked loads of the
     // previous batch were all consumed, and would otherwise wait for every outstanding
     // access before each particle's loads, so that a batch cost one round trip per particle.
-    if (j0 + kB >= kPer || start + (uint32_t)((j0 + kB) * kThreads) >= end) break;
+    if (j0 + kB >= kPer || (uint32_t)((j0 + kB) * kThreads) >= cnt) break;
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);
     load_batch(j0 + kB);
   }
@@ -580,8 +584,11 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
   const int nchunks = (int)d.coff[d.ntiles];
   const uint4 ci = d.cinfo[lb];  // lb < max_chunks; both loads in flight together
   if (lb >= nchunks) return;
-  const uint32_t start = ci.x, end = ci.y;
-  const int tile = (int)ci.z;
+  // uniform: every array below is based at the chunk's first particle, so that accesses
+  // take a scalar base and a small per-thread offset (no 64-bit address arithmetic)
+  const uint32_t start = __builtin_amdgcn_readfirstlane(ci.x);
+  const uint32_t cnt = __builtin_amdgcn_readfirstlane(ci.y) - start;
+  const int tile = (int)__builtin_amdgcn_readfirstlane(ci.z);
   const int N = d.N;
   const int nt = d.ntile1;
   Region rg;
@@ -590,10 +597,14 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
   rg.o[2] = 0;
   const bool use_region = d.use_region;
   T* const ubar = d.ubar;
-  const T* xi = d.xs[src_set];
-  const T* yi = d.ys[src_set];
-  const double* ai = d.as[src_set];
-  const uint32_t* idi = d.ids[src_set];
+  const T* xi = d.xs[src_set] + start;
+  const T* yi = d.ys[src_set] + start;
+  const double* ai = d.as[src_set] + start;
+  const uint32_t* idi = d.ids[src_set] + start;
+  T* xo = d.xs[0] + start;
+  T* yo = d.ys[0] + start;
+  double* ao = d.as[0] + start;
+  uint32_t* ido = d.ids[0] + start;
   constexpr int kB = LoadBatch2<T>::n;
   T px[kB], py[kB];
   double pa[kB];
@@ -602,8 +613,8 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
   auto load_batch = [&](int j0) {
 #pragma unroll
     for (int j = 0; j < kB; ++j) {
-      const uint32_t i = start + threadIdx.x + (j0 + j) * kThreads;
-      if (i < end) {
+      const uint32_t i = threadIdx.x + (j0 + j) * kThreads;  // within the chunk
+      if (i < cnt) {
         px[j] = xi[i];
         py[j] = yi[i];
         pa[j] = ai[i];
@@ -652,8 +663,8 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);  // the batch's loads, as in the 3D pass
 #pragma unroll
     for (int j = 0; j < kB; ++j) {
-      const uint32_t i = start + threadIdx.x + (j0 + j) * kThreads;
-      if (i >= end) continue;
+      const uint32_t i = threadIdx.x + (j0 + j) * kThreads;  // within the chunk
+      if (i >= cnt) continue;
       __builtin_amdgcn_sched_barrier(0);
       const T x = px[j], y = py[j];
       const double a = pa[j];
@@ -705,10 +716,10 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
       const T rho = rho_of(gw);
       const double an = linear_mass ? a * (1.0 + d.dt * (double)rho - d.dt)
                                     : a * exp(d.dt * ((double)rho - 1.0));
-      d.xs[0][i] = xn;
-      d.ys[0][i] = yn;
-      d.as[0][i] = an;
-      if (src_set) d.ids[0][i] = pid[j];
+      xo[i] = xn;
+      yo[i] = yn;
+      ao[i] = an;
+      if (src_set) ido[i] = pid[j];
       if (isfinite(an) && isfinite((double)xn) && isfinite((double)yn)) {
         dg.sum[0] += an;
         acc_min(dg, D_MIN_A, an);
@@ -719,7 +730,7 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
       deposit2(ubar, acc, make_stencil2(xn, yn, d.inv_h, N), rg, use_region, N,
                (T)an * d.inv_h3);
     }
-    if (j0 + kB >= kPer || start + (uint32_t)((j0 + kB) * kThreads) >= end) break;
+    if (j0 + kB >= kPer || (uint32_t)((j0 + kB) * kThreads) >= cnt) break;
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);  // see the 3D pass
     load_batch(j0 + kB);
   }
