@@ -134,9 +134,10 @@ __device__ __forceinline__ bool in_region4(const Stencil<T>& st, const Region& r
   return ok;
 }
 
+// node (a, b, c) of an R^3 region; 24-bit multiplies (full rate), indices are below R^3
 template <int R>
 __device__ __forceinline__ int rindex(int a, int b, int c) {
-  return (a * R + b) * R + c;
+  return (int)__umul24(__umul24((unsigned)a, R) + (unsigned)b, R) + c;
 }
 
 template <typename T>
@@ -467,7 +468,7 @@ __global__ void __launch_bounds__(kThreads)
       zo[i] = zz;
       ao[i] = an;
       if (src_set) ido[i] = pid[j];
-      if (isfinite(an) && isfinite((double)xn) && isfinite((double)yn) && isfinite((double)zz)) {
+      if (isfinite(an) && isfinite(xn) && isfinite(yn) && isfinite(zz)) {
         dg.sum[0] += an;
         acc_min(dg, D_MIN_A, an);
         acc_min(dg, D_MAX_A, an);
@@ -720,7 +721,7 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
       yo[i] = yn;
       ao[i] = an;
       if (src_set) ido[i] = pid[j];
-      if (isfinite(an) && isfinite((double)xn) && isfinite((double)yn)) {
+      if (isfinite(an) && isfinite(xn) && isfinite(yn)) {
         dg.sum[0] += an;
         acc_min(dg, D_MIN_A, an);
         acc_min(dg, D_MAX_A, an);
