@@ -94,7 +94,10 @@ __device__ __forceinline__ T wrap_periodic(T x, T L) {
 
 // LDS region of one tile for deposit order ORDER: the tile's kTile^3 cells, the nodes their
 // stencils reach (one more for the trilinear stencil; one before and two after for the
-// fourth-order one) and a one-cell drift margin.
+// fourth-order one) and a one-cell drift margin.  The gather is trilinear at every order, so
+// the gather array always covers the order-2 region (11^3 nodes) and only the deposit
+// accumulator grows to 13^3 at order 4 (38.9 KB of LDS instead of 52.7 KB in float32: four
+// blocks per CU instead of three).
 template <int ORDER>
 struct Reg {
   static constexpr int M = ORDER == 4 ? 2 : 1;  // nodes before the tile's first node
@@ -299,8 +302,10 @@ template <typename T, int ORDER>
 __global__ void __launch_bounds__(kThreads)
     __attribute__((amdgpu_waves_per_eu(ORDER == 2 && sizeof(T) == 4 ? 5 : 1)))
     k_particles(Batch<T> bt, int src_set, int deposit_only) {
-  constexpr int R = Reg<ORDER>::R;
+  constexpr int R = Reg<ORDER>::R;  // deposit accumulator region
   constexpr int R3 = Reg<ORDER>::R3;
+  constexpr int RG = Reg<2>::R;     // gather region: the gather is trilinear at every order
+  constexpr int RG3 = Reg<2>::R3;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
   const int s = find_sim(bt, K_PART, lb);
@@ -319,6 +324,9 @@ __global__ void __launch_bounds__(kThreads)
   rg.o[0] = (tile / (nt * nt)) * kTile - Reg<ORDER>::M;
   rg.o[1] = ((tile / nt) % nt) * kTile - Reg<ORDER>::M;
   rg.o[2] = (tile % nt) * kTile - Reg<ORDER>::M;
+  Region rgg;  // origin of the gather region (rg itself at order 2)
+#pragma unroll
+  for (int j = 0; j < 3; ++j) rgg.o[j] = rg.o[j] + (Reg<ORDER>::M - Reg<2>::M);
   const bool use_region = d.use_region;
   T* const ubar = d.ubar;
 
@@ -347,8 +355,8 @@ __global__ void __launch_bounds__(kThreads)
   };
   load_batch(0);  // in flight while the region is staged
 
-  vec4<T>* gl = reinterpret_cast<vec4<T>*>(smem_raw);  // gather array of the region
-  LdsAcc<T>* acc = reinterpret_cast<LdsAcc<T>*>(gl + R3);  // deposit accumulator
+  vec4<T>* gl = reinterpret_cast<vec4<T>*>(smem_raw);  // gather array (RG^3 nodes)
+  LdsAcc<T>* acc = reinterpret_cast<LdsAcc<T>*>(gl + RG3);  // deposit accumulator (R^3)
   if (use_region) {
     // groups of kStageGroup nodes per thread: all loads of a group in flight together
     constexpr int kS = (R3 + kThreads - 1) / kThreads;
@@ -360,10 +368,10 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
         for (int k = 0; k < kG; ++k) {
           const int e = threadIdx.x + (k0 + k) * kThreads;
-          if (k0 + k < kS && e < R3) {
-            const int rz = e % R, ry = (e / R) % R, rx = e / (R * R);
-            const vec4<T> q = d.g4[node((rg.o[0] + rx) & (N - 1), (rg.o[1] + ry) & (N - 1),
-                                        (rg.o[2] + rz) & (N - 1), N)];
+          if (k0 + k < kS && e < RG3) {
+            const int rz = e % RG, ry = (e / RG) % RG, rx = e / (RG * RG);
+            const vec4<T> q = d.g4[node((rgg.o[0] + rx) & (N - 1), (rgg.o[1] + ry) & (N - 1),
+                                        (rgg.o[2] + rz) & (N - 1), N)];
             s0[k] = q.x;
             s1[k] = q.y;
             s2[k] = q.z;
@@ -374,8 +382,8 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
       for (int k = 0; k < kG; ++k) {
         const int e = threadIdx.x + (k0 + k) * kThreads;
-        if (k0 + k < kS && e < R3) {
-          if (!deposit_only) gl[e] = vec4<T>{s0[k], s1[k], s2[k], s3[k]};
+        if (k0 + k < kS && e < R3) {  // R3 >= RG3
+          if (!deposit_only && e < RG3) gl[e] = vec4<T>{s0[k], s1[k], s2[k], s3[k]};
           acc[e] = (LdsAcc<T>)0;
         }
       }
@@ -418,14 +426,14 @@ __global__ void __launch_bounds__(kThreads)
       T wx[2], wy[2], wz[2];
       weights(st, wx, wy, wz);
       T g0 = 0, g1 = 0, g2 = 0, gw = 0;
-      if (use_region && in_region<R>(st, rg, N, l)) {
+      if (use_region && in_region<RG>(st, rgg, N, l)) {
 #pragma unroll
         for (int aa = 0; aa < 2; ++aa)
 #pragma unroll
           for (int bb = 0; bb < 2; ++bb)
 #pragma unroll
             for (int cc = 0; cc < 2; ++cc) {
-              const vec4<T> q = gl[rindex<R>(l[0] + aa, l[1] + bb, l[2] + cc)];
+              const vec4<T> q = gl[rindex<RG>(l[0] + aa, l[1] + bb, l[2] + cc)];
               const T wgt = wx[aa] * wy[bb] * wz[cc];
               g0 += wgt * q.x;
               g1 += wgt * q.y;
@@ -952,7 +960,7 @@ __global__ void __launch_bounds__(kThreads) k_bin_scatter(Batch<T> bt) {
 
 template <typename T, int ORDER>
 size_t particle_lds_bytes() {
-  return Reg<ORDER>::R3 * (sizeof(vec4<T>) + sizeof(LdsAcc<T>));
+  return Reg<2>::R3 * sizeof(vec4<T>) + Reg<ORDER>::R3 * sizeof(LdsAcc<T>);
 }
 
 template <typename T>
