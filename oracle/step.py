@@ -104,9 +104,49 @@ def wrap(X, L):
     return Y
 
 
+def field_update(ubar, v, m, w, prm):
+    """Steps 4 and 5 on the grid: explicit reaction on the time-n fields, then the diffusion
+    and decay solves.  Returns (v^{n+1}, m^{n+1}, w^{n+1})."""
+    d, dt = v.ndim, prm.dt
+    m_star = m + dt * ubar
+    w_star = w + dt * (prm.gamma * v - eta(ubar) * w)
+    if prm.implicit_v:
+        v_new = v / (1.0 + prm.alpha * dt * m)
+    else:
+        v_new = v * np.exp(-prm.alpha * dt * m)
+    m_new = spectral.apply_multiplier(m_star, diffusion_multiplier(prm, prm.D_m, prm.beta, d))
+    w_new = spectral.apply_multiplier(w_star, diffusion_multiplier(prm, prm.D_w, 1.0, d))
+    if prm.freeze_v:
+        v_new = v.copy()
+    if prm.freeze_m:
+        m_new = m.copy()
+    if prm.freeze_w:
+        w_new = w.copy()
+    return v_new, m_new, w_new
+
+
+def particle_update(X, a, ids, g, n, prm):
+    """Step 6 for the particles with indices ids (rows of X and a, in the same order): g holds
+    their gathered values ((grad v)_p rows, then w_p), n the step index that keys the noise.
+    Returns (X^{n+1}, a^{n+1}) of those particles."""
+    P, d = X.shape[0], X.shape[1]
+    dt = prm.dt
+    if prm.no_noise or P == 0:
+        z = np.zeros((P, d))
+    else:
+        z = philox.step_normals(np.asarray(ids), n, prm.sim_id, prm.seed)[:, :d]
+    X_new = wrap(X + prm.chi * dt * g[:d].T + np.sqrt(2.0 * prm.D_u * dt) * z, prm.L)
+    w_p = g[d]
+    if prm.linear_mass:
+        a_new = a * (1.0 + dt * rho(w_p) - dt)
+    else:
+        a_new = a * np.exp(dt * (rho(w_p) - 1.0))
+    return X_new, a_new, z
+
+
 def step(state, prm, return_aux=False):
     """Advance one step; returns the new State (and a dict of intermediates if asked)."""
-    N, L, dt = prm.N, prm.L, prm.dt
+    N, L = prm.N, prm.L
     X, a, v, m, w = state.X, state.a, state.v, state.m, state.w
     P, d = X.shape[0], v.ndim
 
@@ -116,33 +156,10 @@ def step(state, prm, return_aux=False):
     grad = spectral.gradient(v, L, mult=spectral.lowpass(N, prm.H0, d=d) if prm.H0 > 0 else None)
     # 3. grid-to-particle at the old positions
     g = pic.gather(list(grad) + [w], X, N, L)
-    # 4. explicit reaction on the old fields
-    m_star = m + dt * ubar
-    w_star = w + dt * (prm.gamma * v - eta(ubar) * w)
-    if prm.implicit_v:
-        v_new = v / (1.0 + prm.alpha * dt * m)
-    else:
-        v_new = v * np.exp(-prm.alpha * dt * m)
-    # 5. diffusion + linear decay
-    m_new = spectral.apply_multiplier(m_star, diffusion_multiplier(prm, prm.D_m, prm.beta, d))
-    w_new = spectral.apply_multiplier(w_star, diffusion_multiplier(prm, prm.D_w, 1.0, d))
-    if prm.freeze_v:
-        v_new = v.copy()
-    if prm.freeze_m:
-        m_new = m.copy()
-    if prm.freeze_w:
-        w_new = w.copy()
+    # 4. explicit reaction on the old fields, 5. diffusion + linear decay
+    v_new, m_new, w_new = field_update(ubar, v, m, w, prm)
     # 6. Euler-Maruyama push and mass update
-    if prm.no_noise or P == 0:
-        z = np.zeros((P, d))
-    else:
-        z = philox.step_normals(np.arange(P), state.n, prm.sim_id, prm.seed)[:, :d]
-    X_new = wrap(X + prm.chi * dt * g[:d].T + np.sqrt(2.0 * prm.D_u * dt) * z, L)
-    w_p = g[d]
-    if prm.linear_mass:
-        a_new = a * (1.0 + dt * rho(w_p) - dt)
-    else:
-        a_new = a * np.exp(dt * (rho(w_p) - 1.0))
+    X_new, a_new, z = particle_update(X, a, np.arange(P), g, state.n, prm)
     new = State(X_new, a_new, v_new, m_new, w_new, state.n + 1)
     if return_aux:
         return new, dict(ubar=ubar, grad=grad, g=g, z=z)

@@ -166,3 +166,22 @@ def test_temporal_order_one_without_noise():
         errs.append(max(np.abs(d).max(), np.abs(np.log(finals[k].a / ref.a)).max()))
     slope = np.polyfit(np.log([T / k for k in (10, 20, 40, 80)]), np.log(errs), 1)[0]
     assert 0.85 < slope < 1.2, (slope, errs)
+
+
+def test_particle_subset_update_equals_full_step():
+    # the particle update of a subset (as the full-size GPU checks use it) gives the rows of
+    # the whole step: the noise is keyed by the particle index, not by the row
+    ic = W.make_initial_state("blob16")
+    prm = S.Params(N=16, dt=1e-3, L=1.0, seed=ic["params"]["seed"], sim_id=3)
+    st = S.State(ic["X0"], ic["a0"], ic["v0"], ic["m0"], ic["w0"], 5)
+    full = S.step(st, prm)
+    from oracle import spectral
+    ids = np.array([0, 7, 4095, 1234, 2])
+    grad = spectral.gradient(st.v, prm.L)
+    g = pic.gather(list(grad) + [st.w], st.X[ids], prm.N, prm.L)
+    X1, a1, _ = S.particle_update(st.X[ids], st.a[ids], ids, g, st.n, prm)
+    assert np.array_equal(X1, full.X[ids]) and np.array_equal(a1, full.a[ids])
+    # and the field update is the step's, given the same deposit
+    ubar = pic.deposit(st.X, st.a, prm.N, prm.L)
+    v1, m1, w1 = S.field_update(ubar, st.v, st.m, st.w, prm)
+    assert np.array_equal(v1, full.v) and np.array_equal(m1, full.m) and np.array_equal(w1, full.w)
