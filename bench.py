@@ -13,6 +13,7 @@ Prints one JSON line.  `python bench.py --gpus N --steps K --warmup W`.
 import argparse
 import ctypes
 import hashlib
+import math
 import json
 import os
 import sys
@@ -46,7 +47,18 @@ def stage_bytes(N, P, s):
     }
 
 
-RESORT_EVERY = 8  # library default binning period
+def resort_period(prm):
+    """Re-binning period of a run: resort_every if set, else the library's default as the
+    header documents it (the largest k <= 64 with sqrt(k 2 D_u dt) <= 0.45 h in 3D, 2.4 h in
+    2D; 64 without noise)."""
+    if prm.get("resort_every", 0) > 0:
+        return int(prm["resort_every"])
+    h = prm["L"] / prm["N"]
+    s = math.sqrt(2.0 * prm["D_u"] * prm["dt"]) / h
+    if not s > 0.0:
+        return 64
+    reach = 2.4 if prm.get("dim") == 2 else 0.45
+    return int(min(64, max(1, math.floor((reach / s) ** 2))))
 
 # Kernel behind each stage (the roofline names the dominant one) and the sources it is built
 # from: a byte-counter summary under profiles/ only applies while these are unchanged.
@@ -138,7 +150,7 @@ def run_form(ic, precision, steps, warmup, profile_steps, workload, **over):
     stages = {}
     for k, tot in stage_ms.items():
         avg = tot / profile_steps  # per step (binning: amortised over its period)
-        nbytes = sb[k] / RESORT_EVERY if k == "binning" else sb[k]
+        nbytes = sb[k] / resort_period(prm) if k == "binning" else sb[k]
         stages[k] = dict(ms=round(avg, 5),
                          GBs=round(nbytes / (avg * 1e-3) / 1e9, 1) if avg > 0 and nbytes else None)
     dominant = max(stages, key=lambda k: stages[k]["ms"])
@@ -180,7 +192,8 @@ def cpu_baseline(ic, steps=3):
 def next_rows(ic, steps=50, warmup=5, profile_steps=8):
     """The rows beyond the plain step, each timed on its own: the fourth-order deposit and
     the low-pass filter on the benchmark workload (float32), one residual resampling of its
-    particles with log-normal masses, and the paper's 2D example at 1024^2 / 2^22 (float32)."""
+    particles with log-normal masses, the 256^3 / 2^25 workload (float32; per-kernel split),
+    and the paper's 2D example at 1024^2 / 2^22 (float32)."""
     import numpy as np
     import torch
     from paper_2605_20140_amd import sipf, workloads as W
@@ -206,6 +219,13 @@ def next_rows(ic, steps=50, warmup=5, profile_steps=8):
     out["resample"] = dict(ms=rs_s * 1e3, particles_per_s=prm["P"] / rs_s, n_stoch=info["n_stoch"],
                            a0=info["a0"], note="one synchronous call incl. re-binning and "
                            "deposit, float32 form", check=dict(n_nan=d["n_nan"]))
+    # the largest single-GPU configuration: 256^3 grid, 2^25 particles, float32
+    ic5 = W.make_initial_state("blobs256")
+    r = run_form(ic5, 1, steps, warmup, profile_steps, "blobs256")
+    out["blobs256"] = dict(value=r["value"], unit="particle-steps/s",
+                           ms_per_step=r["ms_per_step"], N=256, P=ic5["params"]["P"],
+                           stages=r["stages"], roofline=r["roofline"], check=r["check"])
+    del ic5
     ic2 = W.paper2d_initial_state(1024)
     r = run_form(ic2, 1, steps, warmup, profile_steps, "")
     out["paper2d"] = dict(value=r["value"], unit="particle-steps/s",
