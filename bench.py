@@ -192,8 +192,9 @@ def cpu_baseline(ic, steps=3):
 def next_rows(ic, steps=50, warmup=5, profile_steps=8):
     """The rows beyond the plain step, each timed on its own: the fourth-order deposit and
     the low-pass filter on the benchmark workload (float32), one residual resampling of its
-    particles with log-normal masses, the 256^3 / 2^25 workload (float32; per-kernel split),
-    and the paper's 2D example at 1024^2 / 2^22 (float32)."""
+    particles with log-normal masses, the small configurations 16^3 / 4096 and 64^3 / 2^20,
+    the 256^3 / 2^25 workload (float32; per-kernel split), and the paper's 2D example at
+    1024^2 / 2^22 (float32)."""
     import numpy as np
     import torch
     from paper_2605_20140_amd import sipf, workloads as W
@@ -219,6 +220,15 @@ def next_rows(ic, steps=50, warmup=5, profile_steps=8):
     out["resample"] = dict(ms=rs_s * 1e3, particles_per_s=prm["P"] / rs_s, n_stoch=info["n_stoch"],
                            a0=info["a0"], note="one synchronous call incl. re-binning and "
                            "deposit, float32 form", check=dict(n_nan=d["n_nan"]))
+    # the small configurations, where a step is bound by launch latency rather than HBM:
+    # 16^3 / 4096 (float64) and 64^3 / 2^20 (float64 and float32), whole runs of graph replays
+    for name, prec, nst in (("blob16", 0, 100), ("modes64", 0, 500), ("modes64", 1, 500)):
+        icn = W.make_initial_state(name)
+        r = run_form(icn, prec, nst, warmup, profile_steps, "")
+        out[f"{name}_{'fp32' if prec else 'fp64'}"] = dict(
+            value=r["value"], unit="particle-steps/s", ms_per_step=r["ms_per_step"],
+            steps=nst, N=icn["params"]["N"], P=icn["params"]["P"],
+            stages_ms={k: v["ms"] for k, v in r["stages"].items()}, check=r["check"])
     # the largest single-GPU configuration: 256^3 grid, 2^25 particles, float32
     ic5 = W.make_initial_state("blobs256")
     r = run_form(ic5, 1, steps, warmup, profile_steps, "blobs256")
