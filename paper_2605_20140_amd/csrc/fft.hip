@@ -503,7 +503,7 @@ template <typename T, int LG>
 __global__ void __launch_bounds__(kThreads) k_zfwd(Batch<T> bt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
-  const int s = find_sim(bt, K_ZFWD, lb);
+  const int s = find_sim<kFieldRun>(bt, K_ZFWD, lb);
   zfwd_body<T, LG>(sim_view(bt, s), lb, smem_raw);
 }
 
@@ -532,7 +532,7 @@ template <typename T, int LG>
 __global__ void __launch_bounds__(kThreads) k_yfwd(Batch<T> bt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
-  const int s = find_sim(bt, K_YFWD, lb);
+  const int s = find_sim<kFieldRun>(bt, K_YFWD, lb);
   yfwd_body<T, LG>(sim_view(bt, s), lb, smem_raw);
 }
 
@@ -587,7 +587,7 @@ template <typename T, int LG>
 __global__ void __launch_bounds__(kThreads) k_yinv(Batch<T> bt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
-  const int s = find_sim(bt, K_YINV, lb);
+  const int s = find_sim<kFieldRun>(bt, K_YINV, lb);
   yinv_body<T, LG>(sim_view(bt, s), lb, smem_raw);
 }
 
@@ -731,7 +731,7 @@ template <typename T, int LG>
 __global__ void __launch_bounds__(kThreads) k_xpass(Batch<T> bt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
-  const int s = find_sim(bt, K_XPASS, lb);
+  const int s = find_sim<kFieldRun>(bt, K_XPASS, lb);
   SimC<T>& d = sim_view(bt, s);
   if (d.dim == 2)
     col2d_body<T, LG>(d, lb, smem_raw);
@@ -976,7 +976,7 @@ template <typename T, int LG>
 __global__ void __launch_bounds__(kThreads) k_zinv(Batch<T> bt) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
-  const int s = find_sim(bt, K_ZINV, lb);
+  const int s = find_sim<kFieldRun>(bt, K_ZINV, lb);
   zinv_body<T, LG>(sim_view(bt, s), lb, smem_raw);
 }
 

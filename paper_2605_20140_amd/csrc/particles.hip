@@ -308,7 +308,7 @@ __global__ void __launch_bounds__(kThreads)
   constexpr int RG3 = Reg<2>::R3;
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
-  const int s = find_sim(bt, K_PART, lb);
+  const int s = find_sim<kPartRun>(bt, K_PART, lb);
   SimC<T>& d = sim_view(bt, s);
   const int nchunks = (int)d.coff[d.ntiles];
   const uint4 ci = d.cinfo[lb];  // lb < max_chunks; both loads in flight together
@@ -588,7 +588,7 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
                                                          int deposit_only) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
-  const int s = find_sim(bt, K_PART, lb);
+  const int s = find_sim<kPartRun>(bt, K_PART, lb);
   SimC<T>& d = sim_view(bt, s);
   const int nchunks = (int)d.coff[d.ntiles];
   const uint4 ci = d.cinfo[lb];  // lb < max_chunks; both loads in flight together
@@ -775,7 +775,7 @@ constexpr uint32_t kGlobalFlag = 0x80000000u;
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kThreads) k_bin_count(Batch<T> bt) {
   int lb;
-  const int s = find_sim(bt, K_SCOUNT, lb);
+  const int s = find_sim<kFieldRun>(bt, K_SCOUNT, lb);
   SimC<T>& d = sim_view(bt, s);
   __shared__ uint32_t hkey[kHash], hcnt[kHash], hbase[kHash];
   for (int e = threadIdx.x; e < kHash; e += kThreads) {
@@ -946,7 +946,7 @@ __global__ void __launch_bounds__(kThreads) k_bin_scan(Batch<T> bt) {
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kThreads) k_bin_scatter(Batch<T> bt) {
   int lb;
-  const int s = find_sim(bt, K_SSCATTER, lb);
+  const int s = find_sim<kFieldRun>(bt, K_SSCATTER, lb);
   SimC<T>& d = sim_view(bt, s);
   const int64_t i = (int64_t)lb * kThreads + threadIdx.x;
   if (i >= d.P) return;
