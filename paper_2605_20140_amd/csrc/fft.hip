@@ -70,7 +70,7 @@ void block_counts(const SimDev<T>& d, int c[K_COUNT]) {
     // plane jobs: M, W and one for both V derivatives; with the filter M, W, d1 V, d2 V, V
     c[K_PLANE] = d.use_plane ? (int)((nlp ? 5 : 3) * H) : 0;
   }
-  c[K_ZINV] = c[K_ZFWD];
+  c[K_ZINV] = (int)(d.nrows / d.rows_zinv);
   const int64_t pb = (d.P + kThreads - 1) / kThreads;
   c[K_PART] = d.max_chunks;  // bound on the number of (tile, chunk) items
   c[K_SCOUNT] = (int)((d.P + kBinBlock - 1) / kBinBlock);
@@ -843,7 +843,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane(Batch<T> bt) {
 template <typename T, int LG>
 __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* smem) {
   constexpr int N = 1 << LG;
-  const int B = d.rows_per_blk;
+  const int B = d.rows_zinv;
   const int64_t N2 = d.nrows;  // rows per k3 plane of the spectra (N^2; N in 2D)
   const int64_t r0 = (int64_t)lb * B;
   const int Bh = B >> 1;
@@ -990,7 +990,8 @@ size_t fft_lds_bytes(int kind, int lg) {
   const size_t LZ = (size_t)zy_stride_rt(lg);     // z and y passes
   const size_t c = sizeof(cplx<T>);
   const size_t tw = (size_t)(N / 2) * c;
-  const size_t B = (size_t)std::min(N * N, std::max(2, E / N));  // rows per block (z passes)
+  const size_t B = (size_t)std::min(N * N, std::max(2, E / N));  // rows per block (z forward)
+  const size_t Bz = (size_t)std::min(N * N, std::max(2, zinv_elems<T>(N) / N));  // z inverse
   const size_t Bl = (size_t)(E / N);                // lines per block (y passes)
   const size_t Bx = (size_t)std::min(N, E / N);     // columns per block (x pass)
   switch (kind) {
@@ -998,7 +999,7 @@ size_t fft_lds_bytes(int kind, int lg) {
     case K_YFWD: return Bl * LZ * c + tw;
     case K_YINV: return Bl * LZ * c + tw;
     case K_XPASS: return Bx * LS * c + tw;
-    case K_ZINV: return (2 * B + B / 2) * LZ * c + tw;
+    case K_ZINV: return (2 * Bz + Bz / 2) * LZ * c + tw;
     case K_PLANE: return (size_t)N * (N + 2) * c + tw;  // plane_stride
     default: return 0;
   }

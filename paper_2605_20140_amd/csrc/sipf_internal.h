@@ -100,7 +100,8 @@ template <typename T, template <typename> class Ptr>
 struct SimDesc {
   int N, log2N;       // grid nodes per axis
   int64_t P;          // particles
-  int rows_per_blk;   // z passes: rows (i1, i2) per block
+  int rows_per_blk;   // z forward pass: rows (i1, i2) per block
+  int rows_zinv;      // z inverse pass: rows per block (zinv_elems)
   int lines_per_blk;  // y passes: lines per block
   int cols_per_blk;   // x pass: i2 columns per block
   int flags;
@@ -265,6 +266,13 @@ __device__ __forceinline__ unsigned long long order_key(double d) {
 
 // ---- launchers (defined in fft.hip, particles.hip, diag.hip) ------------------------------
 template <typename T> int elems_per_block();
+// Elements per block of the z inverse pass.  Its LDS holds 2.5 lines per row, so at
+// N <= 128 float32 blocks of 1024 elements (half the forward pass's) let five blocks share
+// a CU instead of three, which pays while a block's runs along a spectrum row stay a full
+// 64 bytes (8 rows); at N >= 256 they would be shorter, so the pass keeps 2048.
+template <typename T> inline int zinv_elems(int N) {
+  return sizeof(T) == 4 && N <= 128 ? 1024 : elems_per_block<T>();
+}
 template <typename T> void block_counts(const SimDev<T>& d, int counts[K_COUNT]);
 
 template <typename T> void launch_zfwd(const Batch<T>& b, int nblk, int lg, hipStream_t s);
