@@ -993,7 +993,7 @@ size_t fft_lds_bytes(int kind, int lg) {
   const size_t B = (size_t)std::min(N * N, std::max(2, E / N));  // rows per block (z forward)
   const size_t Bz = (size_t)std::min(N * N, std::max(2, zinv_elems<T>(N) / N));  // z inverse
   const size_t Bl = (size_t)(E / N);                // lines per block (y passes)
-  const size_t Bx = (size_t)std::min(N, E / N);     // columns per block (x pass)
+  const size_t Bx = (size_t)std::min(N, kXpassElems / N);  // columns per block (x pass)
   switch (kind) {
     case K_ZFWD: return (B + B / 2) * LZ * c + tw;
     case K_YFWD: return Bl * LZ * c + tw;

@@ -273,6 +273,9 @@ template <typename T> int elems_per_block();
 template <typename T> inline int zinv_elems(int N) {
   return sizeof(T) == 4 && N <= 128 ? 1024 : elems_per_block<T>();
 }
+// Elements per block of the x pass (columns of N points): 2048 in both precisions, so that a
+// float64 block still moves runs of 16 consecutive columns (256 bytes) at N = 128.
+constexpr int kXpassElems = 2048;
 template <typename T> void block_counts(const SimDev<T>& d, int counts[K_COUNT]);
 
 template <typename T> void launch_zfwd(const Batch<T>& b, int nblk, int lg, hipStream_t s);
