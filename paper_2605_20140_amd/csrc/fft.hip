@@ -993,7 +993,7 @@ size_t fft_lds_bytes(int kind, int lg) {
   const size_t B = (size_t)std::min(N * N, std::max(2, E / N));  // rows per block (z forward)
   const size_t Bz = (size_t)std::min(N * N, std::max(2, zinv_elems<T>(N) / N));  // z inverse
   const size_t Bl = (size_t)(E / N);                // lines per block (y passes)
-  const size_t Bx = (size_t)std::min(N, kXpassElems / N);  // columns per block (x pass)
+  const size_t Bx = (size_t)std::min(N, xpass_elems(lg) / N);  // columns per block (x pass)
   switch (kind) {
     case K_ZFWD: return (B + B / 2) * LZ * c + tw;
     case K_YFWD: return Bl * LZ * c + tw;
@@ -1007,8 +1007,9 @@ size_t fft_lds_bytes(int kind, int lg) {
 template size_t fft_lds_bytes<double>(int, int);
 template size_t fft_lds_bytes<float>(int, int);
 
-// Raise the dynamic LDS limit of the row passes where they need more than the default 64 KiB
-// (float64 rows of 1024 nodes, two per block).  Call once, outside capture.
+// Raise the dynamic LDS limit of the passes that can need more than the default 64 KiB at
+// N = 1024 (float64 rows of 1024 nodes, two per block; column blocks of several 1024-point
+// lines).  Call once, outside capture.
 template <typename T>
 void configure_fft(int lg) {
   if (lg != 10) return;
@@ -1018,6 +1019,9 @@ void configure_fft(int lg) {
   (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_zinv<T, 10>),
                             hipFuncAttributeMaxDynamicSharedMemorySize,
                             (int)fft_lds_bytes<T>(K_ZINV, 10));
+  (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_xpass<T, 10>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize,
+                            (int)fft_lds_bytes<T>(K_XPASS, 10));
 }
 template void configure_fft<double>(int);
 template void configure_fft<float>(int);

@@ -274,8 +274,12 @@ template <typename T> inline int zinv_elems(int N) {
   return sizeof(T) == 4 && N <= 128 ? 1024 : elems_per_block<T>();
 }
 // Elements per block of the x pass (columns of N points): 2048 in both precisions, so that a
-// float64 block still moves runs of 16 consecutive columns (256 bytes) at N = 128.
+// float64 block still moves runs of 16 consecutive columns (256 bytes) at N = 128.  The 2D
+// column pass at N = 1024 (log2 N = 10, two-dimensional only) takes kXpassElems1024: with
+// two 1024-point lines per block only 64 threads have a sub-transform to run.
 constexpr int kXpassElems = 2048;
+constexpr int kXpassElems1024 = 4096;
+inline int xpass_elems(int lg) { return lg == 10 ? kXpassElems1024 : kXpassElems; }
 template <typename T> void block_counts(const SimDev<T>& d, int counts[K_COUNT]);
 
 template <typename T> void launch_zfwd(const Batch<T>& b, int nblk, int lg, hipStream_t s);
