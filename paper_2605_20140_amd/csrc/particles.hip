@@ -760,17 +760,28 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
 
 // ---- binning ----------------------------------------------------------------------------
 // Tile of every particle of set 0 and its rank among the particles of that tile.  A block
-// takes kBinChunk consecutive particles: wavefronts aggregate equal tiles (one LDS atomic per
-// distinct tile per wavefront) into a block-local hash table, then the block adds each
-// distinct tile's count to the global counter with one atomic and derives global ranks.
-// Set 0 is tile-ordered after the first binning, so a block sees one or two tiles and the
-// global counters see few atomics.  Tiles that do not fit the table take one global atomic
-// per wavefront instead.
+// takes kBinChunk consecutive particles: wavefronts aggregate their first tile (one LDS
+// atomic), the other lanes count themselves, into a block-local hash table; then the block
+// adds each distinct tile's count to the global counter with one atomic and derives global
+// ranks.  Set 0 is tile-ordered after the first binning, so a block sees one or two tiles
+// and the global counters see few atomics.  Tiles that do not fit the table count on the
+// global counter directly.
 constexpr int kBinChunk = kBinBlock;
 constexpr int kBinPer = kBinChunk / kThreads;
 constexpr int kHash = 512;
 constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 constexpr uint32_t kGlobalFlag = 0x80000000u;
+
+// Slot of tile t in a block's open-addressing hash table (claimed on first use), or kEmpty
+// when 16 probes find no free slot.
+__device__ __forceinline__ uint32_t hash_slot(uint32_t* hkey, uint32_t t) {
+  uint32_t h = (t * 2654435761u) >> 23;  // 9-bit multiplicative hash
+  for (int probe = 0; probe < 16; ++probe, h = (h + 1) & (kHash - 1)) {
+    const uint32_t k = atomicCAS(&hkey[h], kEmpty, t);
+    if (k == kEmpty || k == t) return h;
+  }
+  return kEmpty;
+}
 
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kThreads) k_bin_count(Batch<T> bt) {
@@ -819,21 +830,17 @@ __global__ void __launch_bounds__(kThreads) k_bin_count(Batch<T> bt) {
     tiles[j] = tile;
     slot[j] = kEmpty;
     lrank[j] = 0;
-    unsigned long long pending = __ballot(valid);
-    while (pending) {
+    // The wavefront's first tile (usually shared by most lanes: set 0 is tile-ordered) is
+    // aggregated by one leader lane; the lanes whose particle has moved to another tile then
+    // take their ranks on their own, all in one pass, rather than one pass per tile.
+    const unsigned long long pending = __ballot(valid);
+    if (pending) {
       const int leader = __ffsll((long long)pending) - 1;
       const uint32_t lt = __shfl(tile, leader, 64);
       const unsigned long long same = __ballot(valid && tile == lt) & pending;
       uint32_t sl = kEmpty, base = 0;
       if (lane == leader) {
-        uint32_t h = (lt * 2654435761u) >> 23;  // 9-bit multiplicative hash
-        for (int probe = 0; probe < 16; ++probe, h = (h + 1) & (kHash - 1)) {
-          const uint32_t k = atomicCAS(&hkey[h], kEmpty, lt);
-          if (k == kEmpty || k == lt) {
-            sl = h;
-            break;
-          }
-        }
+        sl = hash_slot(hkey, lt);
         if (sl != kEmpty) {
           base = atomicAdd(&hcnt[sl], (uint32_t)__popcll(same));
         } else {
@@ -846,8 +853,16 @@ __global__ void __launch_bounds__(kThreads) k_bin_count(Batch<T> bt) {
       if ((same >> lane) & 1ull) {
         slot[j] = sl;
         lrank[j] = base + (uint32_t)__popcll(same & ((1ull << lane) - 1ull));
+      } else if (valid) {
+        uint32_t so = hash_slot(hkey, tile);
+        if (so != kEmpty) {
+          lrank[j] = atomicAdd(&hcnt[so], 1u);
+        } else {
+          lrank[j] = atomicAdd(&d.tcount[tile], 1u);
+          so = kGlobalFlag;
+        }
+        slot[j] = so;
       }
-      pending &= ~same;
     }
   }
   __syncthreads();
