@@ -308,7 +308,7 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   d.log2N = lg;
   d.P = P;
   const int E = elems_per_block<T>();
-  d.rows_per_blk = (int)std::min<int64_t>(d.nrows, std::max(2, E / N));
+  d.rows_per_blk = (int)std::min<int64_t>(d.nrows, std::max(zfwd_min_rows<T>(lg), E / N));
   d.rows_zinv = (int)std::min<int64_t>(d.nrows, std::max(2, zinv_elems<T>(N) / N));
   d.lines_per_blk = E / N;
   d.cols_per_blk = std::min(N, xpass_elems(lg) / N);

@@ -990,7 +990,7 @@ size_t fft_lds_bytes(int kind, int lg) {
   const size_t LZ = (size_t)zy_stride_rt(lg);     // z and y passes
   const size_t c = sizeof(cplx<T>);
   const size_t tw = (size_t)(N / 2) * c;
-  const size_t B = (size_t)std::min(N * N, std::max(2, E / N));  // rows per block (z forward)
+  const size_t B = (size_t)std::min(N * N, std::max(zfwd_min_rows<T>(lg), E / N));  // z forward
   const size_t Bz = (size_t)std::min(N * N, std::max(2, zinv_elems<T>(N) / N));  // z inverse
   const size_t Bl = (size_t)(E / N);                // lines per block (y passes)
   const size_t Bx = (size_t)std::min(N, xpass_elems(lg) / N);  // columns per block (x pass)

@@ -273,6 +273,12 @@ template <typename T> int elems_per_block();
 template <typename T> inline int zinv_elems(int N) {
   return sizeof(T) == 4 && N <= 128 ? 1024 : elems_per_block<T>();
 }
+// Fewest rows per block of the z forward pass (rows come in pairs): two, and four for
+// float64 rows of 1024 nodes (the 2D form's largest grid), where two rows left most of a
+// block's threads without a sub-transform (row pass 36.7 -> 27.7 us at 1024^2).
+template <typename T> inline int zfwd_min_rows(int lg) {
+  return lg == 10 && sizeof(T) == 8 ? 4 : 2;
+}
 // Elements per block of the x pass (columns of N points): 2048 in both precisions, so that a
 // float64 block still moves runs of 16 consecutive columns (256 bytes) at N = 128.  The 2D
 // column pass at N = 1024 (log2 N = 10, two-dimensional only) takes kXpassElems1024: with
