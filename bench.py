@@ -261,7 +261,7 @@ def served(nreq, budget_gib, seed=4):
     # solo capacity: the first few requests, one at a time (once untimed, so that first-use
     # costs such as module loading and graph instantiation do not lower the rate)
     probe = reqs[:8]
-    for timed in (False, True):
+    for _ in range(2):
         t = time.perf_counter()
         srv = serve.Server(be, budget_gib << 30, max_slots=1, tick_steps=50)
         srv.run([serve.Request(r.rid, 0.0, r.N, r.P, r.steps, r.params, r.ic) for r in probe])
