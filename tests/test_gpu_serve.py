@@ -1,9 +1,12 @@
 """Served form on the GPU: simulations of mixed grid and particle sizes admitted while others
-run, stepped together in batched launches, give each the result it gets alone."""
+run, stepped together in batched launches, give each the result it gets alone and the
+oracle's (Alg. sipf-pic per request), within the stated tolerances."""
 import numpy as np
 import pytest
 
-from _parity import rel_errors
+from oracle import step as S
+
+from _parity import compare_state, oracle_params, oracle_state, rel_errors
 
 pytestmark = pytest.mark.gpu
 
@@ -13,13 +16,16 @@ def _mix(precision):
     q = W.served_mix(nreq=7, rate=None, steps=23, sizes=(16, 32), logp=(11, 15), seed=11)
     for i, r in enumerate(q):
         r["steps"] = 15 + 4 * i     # different lengths: slots free up while others still run
+    # one 64^3 request, so that a tick holds FFT groups of three grid sizes
+    q[1]["N"], q[1]["P"] = 64, 20000
     return serve.make_requests(q)
 
 
-@pytest.mark.parametrize("precision,tol", [(0, 1e-11), (1, 1e-5)])
-def test_served_results_equal_solo(precision, tol):
+@pytest.mark.parametrize("precision,tol,tol_oracle", [(0, 1e-11, 1e-10), (1, 1e-5, 1e-4)])
+def test_served_results_equal_solo_and_oracle(precision, tol, tol_oracle):
     from paper_2605_20140_amd import serve, sipf
     reqs = _mix(precision)
+    assert sorted({r.N for r in reqs}) == [16, 32, 64]
     be = serve.GpuBackend(precision=precision)
     srv = serve.Server(be, hbm_budget=1 << 30, max_slots=3, tick_steps=5, keep_outputs=True)
     recs, summ = srv.run(reqs)
@@ -41,3 +47,6 @@ def test_served_results_equal_solo(precision, tol):
         assert np.abs(d - np.round(d)).max() < tol, r.rid
         assert np.abs(out["a"] / ref["a"] - 1).max() < tol, r.rid
         assert out["diag"]["step"] == r.steps
+        # the oracle, run on the request's own inputs and parameters (sim_id keys its noise)
+        orc = S.run(oracle_state(r.ic), oracle_params(r.params), r.steps)
+        compare_state(out, orc, tol_oracle)

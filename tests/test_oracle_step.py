@@ -185,3 +185,103 @@ def test_particle_subset_update_equals_full_step():
     ubar = pic.deposit(st.X, st.a, prm.N, prm.L)
     v1, m1, w1 = S.field_update(ubar, st.v, st.m, st.w, prm)
     assert np.array_equal(v1, full.v) and np.array_equal(m1, full.m) and np.array_equal(w1, full.w)
+
+
+# ---- the oxygen-consumption term eta(u) and the period L != 1 -------------------------------
+
+def _uniform_deposit_state(N, L, U, v0, m0, w0):
+    """One particle on every node, all of mass U h^3: the trilinear deposit is then exactly U
+    on every node (each particle puts its whole mass on its own node)."""
+    h = L / N
+    idx = np.stack(np.meshgrid(*(np.arange(N),) * 3, indexing="ij"), -1).reshape(-1, 3)
+    X = idx * h
+    a = np.full(X.shape[0], U * h ** 3)
+    g = np.ones((N, N, N))
+    return S.State(X, a, v0 * g, m0 * g, w0 * g, 0)
+
+
+def _eta_step_closed_form(U, v0, m0, w0, prm):
+    """One step from uniform fields and a uniform deposit U, written out by hand from the
+    model equation (eq. haptotaxis-system: S_w = gamma v - eta(u) w, eta(u) = 2u / (1 + u)),
+    the explicit reaction (eq. g_hat_phy) and the zero mode of the implicit solve
+    (eq. k_q_tilde_update: decay 1 + tau R with R = diag(beta, 1) for (m, w))."""
+    t = prm.dt
+    eta_u = 2.0 * U / (1.0 + U)
+    w1 = (w0 + t * (prm.gamma * v0 - eta_u * w0)) / (1.0 + t)
+    m1 = (m0 + t * U) / (1.0 + t * prm.beta)
+    v1 = v0 * np.exp(-prm.alpha * t * m0)
+    return v1, m1, w1
+
+
+@pytest.mark.parametrize("U", [0.25, 3.0, 17.0])
+def test_eta_pin_uniform_deposit(U):
+    """Uniform deposit U and uniform v, m, w: one step of the whole oracle must reduce to the
+    scalar recursion above.  U = 3 separates 2u/(1+u) = 1.5 from u/(1+u) = 0.75 and from
+    2u/(1+u^2) = 0.6 (at U = 1 the last coincides)."""
+    N, L = 8, 1.0
+    v0, m0, w0 = 0.8, 0.3, 1.7
+    prm = S.Params(N=N, dt=0.05, L=L, chi=0.0, no_noise=True, gamma=0.7, beta=0.4, alpha=2.0)
+    st = _uniform_deposit_state(N, L, U, v0, m0, w0)
+    np.testing.assert_allclose(pic.deposit(st.X, st.a, N, L), U, rtol=1e-14)
+    s = S.step(st, prm)
+    v1, m1, w1 = _eta_step_closed_form(U, v0, m0, w0, prm)
+    np.testing.assert_allclose(s.w, w1, rtol=1e-14)
+    np.testing.assert_allclose(s.m, m1, rtol=1e-14)
+    np.testing.assert_allclose(s.v, v1, rtol=1e-14)
+    # the particles sit still (no drift, no noise) and grow at rate rho(w0) - 1
+    np.testing.assert_array_equal(s.X, st.X)
+    np.testing.assert_allclose(s.a, st.a * np.exp(prm.dt * (2 * w0 / (1 + w0) - 1)), rtol=1e-14)
+
+
+@pytest.mark.parametrize("wrong", [lambda u: u / (1.0 + u), lambda u: 2.0 * u / (1.0 + u * u),
+                                   lambda u: 2.0 * u / (1.0 - u)])
+def test_eta_pin_rejects_planted_mistakes(monkeypatch, wrong):
+    """The pin above fails for plausible slips in eta (planted in the oracle, on the CPU)."""
+    monkeypatch.setattr(S, "eta", wrong)
+    with pytest.raises(AssertionError):
+        test_eta_pin_uniform_deposit(3.0)
+
+
+def test_wrap_at_period_six():
+    """wrap(X, L) maps onto [0, L) with period L (reading A7), at the paper's L = 6."""
+    L = 6.0
+    X = np.array([[-0.5, 6.0, 13.25], [5.999, -6.0, 0.0], [-1e-17, 12.0 - 1e-15, -11.5]])
+    Y = S.wrap(X.copy(), L)
+    expect = np.array([[5.5, 0.0, 1.25], [5.999, 0.0, 0.0], [0.0, 6.0 - 1e-15, 0.5]])
+    np.testing.assert_allclose(Y, expect, rtol=0, atol=2e-15)
+    assert np.all(Y >= 0.0) and np.all(Y < L)
+    # a tiny negative coordinate rounds to L under X - L floor(X / L); it must come back as 0
+    assert Y[2, 0] == 0.0
+
+
+def test_period_six_mode_decay_gradient_and_transfers():
+    """The L-dependent parts of the step at L = 6: the implicit multiplier's |k|^2 =
+    (2 pi / L)^2 |q|^2, the derivative factor 2 pi q / L, and h = L / N in the deposit and
+    the gather."""
+    from oracle import spectral
+    N, L, dt, n = 16, 6.0, 0.02, 5
+    prm = S.Params(N=N, dt=dt, L=L, D_m=0.01, D_w=0.01, beta=0.01)
+    X1, X2, X3 = _nodes(N, L)
+    q = np.array([2, -1, 3])
+    ph = 2 * np.pi * (q[0] * X1 + q[1] * X2 + q[2] * X3) / L
+    s = S.run(_empty_state(N, np.zeros((N, N, N)), np.cos(ph), np.sin(ph)), prm, n)
+    k2 = (2 * np.pi / L) ** 2 * (q ** 2).sum()
+    np.testing.assert_allclose(s.m, np.cos(ph) * (1 + dt * (prm.beta + prm.D_m * k2)) ** -n,
+                               atol=1e-14)
+    np.testing.assert_allclose(s.w, np.sin(ph) * (1 + dt * (1.0 + prm.D_w * k2)) ** -n,
+                               atol=1e-14)
+    g = spectral.gradient(np.cos(ph), L)
+    for j in range(3):
+        np.testing.assert_allclose(g[j], -(2 * np.pi * q[j] / L) * np.sin(ph), atol=1e-12)
+    # a particle at a node deposits a / h^3 there; at a cell centre a / (8 h^3) on 8 nodes
+    h = L / N
+    u = pic.deposit(np.array([[3 * h, 5 * h, 15 * h]]), np.array([2.0]), N, L)
+    assert u[3, 5, 15] == pytest.approx(2.0 / h ** 3, rel=1e-14) and np.count_nonzero(u) == 1
+    u = pic.deposit(np.array([[15.5 * h, 0.5 * h, 7.5 * h]]), np.array([2.0]), N, L)
+    nz = np.argwhere(u)
+    assert len(nz) == 8 and set(nz[:, 0]) == {15, 0} and set(nz[:, 1]) == {0, 1}
+    np.testing.assert_allclose(u[u != 0], 2.0 / (8 * h ** 3), rtol=1e-14)
+    # the gather of a field linear along one axis between two nodes interpolates it
+    f = np.broadcast_to(np.arange(N, dtype=float)[None, :, None], (N, N, N))
+    val = pic.gather([f], np.array([[0.3, 4.25 * h, 1.0]]), N, L)
+    assert val[0, 0] == pytest.approx(4.25, rel=1e-14)
