@@ -151,6 +151,19 @@ int sipf_set_stream(sipf_sim* sim, void* hip_stream);
  * SIPF_EHIP. */
 int sipf_step_batch(sipf_sim* const* sims, int32_t nsims, int32_t nsteps);
 
+/* Allocation-free form of sipf_step_batch, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).  Same
+ * arguments, requirements and results as sipf_step_batch; in addition the simulations' device
+ * must be the current device and nsims <= 64.  The batch's launch table (descriptors and
+ * per-kernel block offsets, at most 128 KiB) lives in one library-owned device array per GPU,
+ * set up when the first simulation is created on that GPU and held until the process ends;
+ * the steps are launched kernel by kernel on the stream of sims[0] (no graph is instantiated,
+ * nothing is allocated).  Every call on a GPU rewrites that GPU's array: calls ordered on one
+ * stream are safe, calls that overlap on one GPU without ordering race on the table.
+ * Errors: as sipf_step_batch, plus SIPF_EINVAL for nsims > 64, a table above the limit, or
+ * a device that is not current. */
+int sipf_step_batch_noalloc(sipf_sim* const* sims, int32_t nsims, int32_t nsteps);
+
 /* Wait for the simulation's stream and copy the state to the host: any pointer may be NULL.
  * v, m, w: N^3 float64; X: 3P float64 SoA in the particle order given at init; a: P float64;
  * diag: diagnostics of the state.  With SIPF_FLAG_STRICT, returns SIPF_EPOS (after filling

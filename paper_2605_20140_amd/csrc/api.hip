@@ -219,21 +219,23 @@ struct FftGroup {
 };
 
 template <typename T>
-void enqueue_fft(const std::vector<FftGroup<T>>& groups, hipStream_t st) {
-  for (const auto& g : groups) launch_zfwd<T>(g.b, g.tot[K_ZFWD], g.lg, st);
-  for (const auto& g : groups) launch_yfwd<T>(g.b, g.tot[K_YFWD], g.lg, st);
-  for (const auto& g : groups) launch_xpass<T>(g.b, g.tot[K_XPASS], g.lg, st);
-  for (const auto& g : groups) launch_plane<T>(g.b, g.tot[K_PLANE], g.lg, st, 0);
-  for (const auto& g : groups) launch_yinv<T>(g.b, g.tot[K_YINV], g.lg, st);
-  for (const auto& g : groups) launch_zinv<T>(g.b, g.tot[K_ZINV], g.lg, st);
+void enqueue_fft(const FftGroup<T>* groups, int ng, hipStream_t st) {
+  for (int i = 0; i < ng; ++i) launch_zfwd<T>(groups[i].b, groups[i].tot[K_ZFWD], groups[i].lg, st);
+  for (int i = 0; i < ng; ++i) launch_yfwd<T>(groups[i].b, groups[i].tot[K_YFWD], groups[i].lg, st);
+  for (int i = 0; i < ng; ++i)
+    launch_xpass<T>(groups[i].b, groups[i].tot[K_XPASS], groups[i].lg, st);
+  for (int i = 0; i < ng; ++i)
+    launch_plane<T>(groups[i].b, groups[i].tot[K_PLANE], groups[i].lg, st, 0);
+  for (int i = 0; i < ng; ++i) launch_yinv<T>(groups[i].b, groups[i].tot[K_YINV], groups[i].lg, st);
+  for (int i = 0; i < ng; ++i) launch_zinv<T>(groups[i].b, groups[i].tot[K_ZINV], groups[i].lg, st);
 }
 
 // One step; with bin != 0 the particles are first binned into set 1 and the particle pass
 // reads set 1 (and writes set 0).
 template <typename T>
-void enqueue_step(const Batch<T>& b, const int* tot, int nsims,
-                  const std::vector<FftGroup<T>>& groups, int bin, int order, int dim,
-                  hipStream_t st, const StepFork* fk) {
+void enqueue_step(const Batch<T>& b, const int* tot, int nsims, const FftGroup<T>* groups,
+                  int ngroups, int bin, int order, int dim, hipStream_t st,
+                  const StepFork* fk) {
   // The binning kernels touch only the particles and their tables, the field passes only
   // grids and spectra: on binning steps the binning runs on a second stream beside the field
   // passes (filling the CUs they leave idle), and the particle pass waits for both.
@@ -245,7 +247,7 @@ void enqueue_step(const Batch<T>& b, const int* tot, int nsims,
   } else if (bin) {
     launch_binning<T>(b, tot, nsims, dim, st);
   }
-  enqueue_fft<T>(groups, st);
+  enqueue_fft<T>(groups, ngroups, st);
   if (bin && fk) (void)hipStreamWaitEvent(st, fk->join, 0);
   launch_particles<T>(b, tot[K_PART], bin ? 1 : 0, 0, order, dim, st);
   launch_finalize<T>(b, nsims, st);
@@ -483,12 +485,14 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   HIPCHK(create_fork(sim->fork));
   const auto groups = single_groups<T>(sim, b);
   HIPCHK(hipStreamBeginCapture(sim->cap, hipStreamCaptureModeThreadLocal));
-  enqueue_step<T>(b, sim->counts, 1, groups, 0, p.deposit_order, dim, sim->cap, nullptr);
+  enqueue_step<T>(b, sim->counts, 1, groups.data(), (int)groups.size(), 0, p.deposit_order,
+                  dim, sim->cap, nullptr);
   HIPCHK(hipStreamEndCapture(sim->cap, &sim->graph));
   HIPCHK(hipGetLastError());
   HIPCHK(hipGraphInstantiate(&sim->exec, sim->graph, nullptr, nullptr, 0));
   HIPCHK(hipStreamBeginCapture(sim->cap, hipStreamCaptureModeThreadLocal));
-  enqueue_step<T>(b, sim->counts, 1, groups, 1, p.deposit_order, dim, sim->cap, &sim->fork);
+  enqueue_step<T>(b, sim->counts, 1, groups.data(), (int)groups.size(), 1, p.deposit_order,
+                  dim, sim->cap, &sim->fork);
   HIPCHK(hipStreamEndCapture(sim->cap, &sim->graph_bin));
   HIPCHK(hipGetLastError());
   HIPCHK(hipGraphInstantiate(&sim->exec_bin, sim->graph_bin, nullptr, nullptr, 0));
@@ -760,8 +764,8 @@ int build_batch_graph(sipf_sim* const* sims, int nsims, int dev, BatchGraph** ou
   for (int bin = 0; bin < 2 && rc == SIPF_OK; ++bin) {
     chk(hipStreamBeginCapture(g_cap_stream[dev], hipStreamCaptureModeThreadLocal), "capture");
     if (rc != SIPF_OK) break;
-    enqueue_step<T>(b, tot.data(), nsims, groups, bin, sims[0]->prm.deposit_order, 3,
-                    g_cap_stream[dev], &g_cap_fork[dev]);
+    enqueue_step<T>(b, tot.data(), nsims, groups.data(), (int)groups.size(), bin,
+                    sims[0]->prm.deposit_order, 3, g_cap_stream[dev], &g_cap_fork[dev]);
     chk(hipStreamEndCapture(g_cap_stream[dev], &e->graph[bin]), "hipStreamEndCapture");
     if (rc == SIPF_OK) chk(hipGetLastError(), "batched launch");
     if (rc == SIPF_OK)
@@ -820,6 +824,154 @@ int step_batch_t(sipf_sim* const* sims, int nsims, int nsteps) {
     for (int i = 0; i < nsims; ++i) sims[i]->since_bin = bin ? 1 : sims[i]->since_bin + 1;
   }
   HIPCHK(hipEventRecord(e->done, st));
+  for (int i = 0; i < nsims; ++i) sims[i]->last_stream = st;
+  return SIPF_OK;
+}
+
+// ---- allocation-free batched steps ------------------------------------------------------------
+// For callers that cannot allocate device memory (code under graph capture, serving loops,
+// harnesses that forbid it): the launch table of a batch lives in this file-scope device
+// array instead of a buffer from hipMalloc, and the step is launched kernel by kernel instead
+// of through a graph instantiated per batch composition.  Each GPU holds its own copy of the
+// array at its own address, found once per device with hipGetSymbolAddress; host code uses
+// only that address (the array's name is a host-side stand-in).  Every call on one GPU
+// rewrites the same array: calls ordered on one stream are safe, calls that overlap on one
+// GPU (different streams, no ordering between them) race on the table.
+constexpr int kNoAllocMaxSims = 64;
+constexpr size_t kNoAllocBytes = 128 * 1024;
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+// Per device: the array's device address, and a host image of the table last written to it
+// (a call whose table is unchanged writes nothing).  Both are set up by sipf_init, the first
+// time a simulation is created on the device, with that device current.
+struct DevScratch {
+  void* ptr = nullptr;
+  unsigned char* last = nullptr;  // kNoAllocBytes
+  size_t last_bytes = 0;          // 0: nothing written yet
+};
+std::mutex g_scratch_mu;
+DevScratch g_scratch[64];
+
+int scratch_setup(int dev, DevScratch** out) {
+  if (dev < 0 || dev >= 64) return fail(SIPF_EINVAL, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  DevScratch& d = g_scratch[dev];
+  if (!d.ptr) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(SIPF_EHIP, std::string("hipGetSymbolAddress(scratch): ") +
+                                 hipGetErrorString(e));
+    d.last = new unsigned char[kNoAllocBytes];
+    d.ptr = p;
+  }
+  *out = &d;
+  return SIPF_OK;
+}
+
+// The table reaches the array through kernel arguments (kTableChunkWords words per launch),
+// so the upload is ordered on the stream like the kernels that read it, and no host buffer
+// has to outlive the call.
+constexpr int kTableChunkWords = 512;
+struct TableChunk {
+  uint32_t off;  // first word
+  uint32_t n;    // words in this chunk
+  uint32_t w[kTableChunkWords];
+};
+
+__global__ void __launch_bounds__(kThreads) k_write_table(uint32_t* dst, TableChunk c) {
+  for (uint32_t i = threadIdx.x; i < c.n; i += kThreads) dst[c.off + i] = c.w[i];
+}
+
+// host image of the table being built (under g_batch_mu)
+unsigned char g_noalloc_host[kNoAllocBytes];
+
+template <typename T>
+int step_batch_noalloc_t(sipf_sim* const* sims, int nsims, int nsteps) {
+  hipStream_t st = sims[0]->stream;
+  const int dev = sims[0]->device;
+  int cur = -1;
+  HIPCHK(hipGetDevice(&cur));
+  if (cur != dev) return fail(SIPF_EINVAL, "the simulations' device must be the current device");
+  DevScratch* ds = nullptr;
+  {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (dev >= 0 && dev < 64 && g_scratch[dev].ptr) ds = &g_scratch[dev];
+  }
+  if (!ds) return fail(SIPF_EINVAL, "no simulation was initialised on this device");
+  void* dptr = ds->ptr;
+  // grid sizes present (FFT kernels are compiled per N): log2 N in [2, 9]
+  int lgs[8], cnt[8], ng = 0;
+  for (int i = 0; i < nsims; ++i) {
+    const int lg = reinterpret_cast<const SimDev<T>*>(sims[i]->host_desc)->log2N;
+    int g = 0;
+    while (g < ng && lgs[g] != lg) ++g;
+    if (g == ng) {
+      if (ng == 8) return fail(SIPF_EINVAL, "more grid sizes than the library supports");
+      lgs[ng] = lg;
+      cnt[ng++] = 0;
+    }
+    ++cnt[g];
+  }
+  size_t offs[8];
+  size_t bytes = table_bytes<T>(nsims);
+  for (int g = 0; g < ng; ++g) {
+    offs[g] = bytes;
+    bytes += table_bytes<T>(cnt[g]);
+  }
+  if (bytes > kNoAllocBytes)
+    return fail(SIPF_EINVAL, "batch table of " + std::to_string(bytes) +
+                                 " bytes exceeds the allocation-free limit of " +
+                                 std::to_string(kNoAllocBytes));
+  std::lock_guard<std::mutex> lk(g_batch_mu);
+  unsigned char* h = g_noalloc_host;
+  int tot[K_COUNT];
+  fill_table<T>(sims, nsims, h, tot);
+  sipf_sim* sub[kNoAllocMaxSims];
+  FftGroup<T> groups[8];
+  unsigned char* base = static_cast<unsigned char*>(dptr);
+  for (int g = 0; g < ng; ++g) {
+    int k = 0;
+    for (int i = 0; i < nsims; ++i)
+      if (reinterpret_cast<const SimDev<T>*>(sims[i]->host_desc)->log2N == lgs[g])
+        sub[k++] = sims[i];
+    fill_table<T>(sub, k, h + offs[g], groups[g].tot);
+    groups[g].lg = lgs[g];
+    groups[g].b = table_batch<T>(base + offs[g], k);
+  }
+  // work a simulation queued on other streams is ordered before the batch (and so is the
+  // previous use of the table, when it was on this stream)
+  for (int i = 0; i < nsims; ++i) {
+    for (hipStream_t o : {sims[i]->stream, sims[i]->last_stream}) {
+      if (o != st && o != nullptr) {
+        HIPCHK(hipEventRecord(sims[i]->ev, o));
+        HIPCHK(hipStreamWaitEvent(st, sims[i]->ev, 0));
+      }
+    }
+  }
+  // (re)write the table unless this device's array already holds exactly these bytes
+  if (!(ds->last_bytes == bytes && memcmp(ds->last, h, bytes) == 0)) {
+    const uint32_t words = (uint32_t)((bytes + 3) / 4);
+    TableChunk c;
+    for (uint32_t o = 0; o < words; o += kTableChunkWords) {
+      c.off = o;
+      c.n = std::min<uint32_t>(kTableChunkWords, words - o);
+      memcpy(c.w, h + 4 * (size_t)o, 4 * (size_t)c.n);
+      hipLaunchKernelGGL(k_write_table, dim3(1), dim3(kThreads), 0, st,
+                         static_cast<uint32_t*>(dptr), c);
+    }
+    HIPCHK(hipGetLastError());
+    memcpy(ds->last, h, bytes);
+    ds->last_bytes = bytes;
+  }
+  const Batch<T> b = table_batch<T>(base, nsims);
+  for (int s = 0; s < nsteps; ++s) {
+    int bin = 0;
+    for (int i = 0; i < nsims; ++i) bin |= sims[i]->since_bin >= sims[i]->resort_every;
+    enqueue_step<T>(b, tot, nsims, groups, ng, bin, sims[0]->prm.deposit_order, 3, st, nullptr);
+    for (int i = 0; i < nsims; ++i) sims[i]->since_bin = bin ? 1 : sims[i]->since_bin + 1;
+  }
+  HIPCHK(hipGetLastError());
   for (int i = 0; i < nsims; ++i) sims[i]->last_stream = st;
   return SIPF_OK;
 }
@@ -939,6 +1091,26 @@ int order_after_batch(sipf_sim* sim) {
   return SIPF_OK;
 }
 
+// checks shared by the batched entry points
+int check_batch(sipf_sim* const* sims, int32_t nsims, int32_t nsteps) {
+  if (!sims || nsims <= 0) return fail(SIPF_EINVAL, "empty simulation list");
+  if (nsteps < 0) return fail(SIPF_EINVAL, "nsteps must be >= 0");
+  for (int i = 0; i < nsims; ++i) {
+    if (!sims[i]) return fail(SIPF_EINVAL, "NULL simulation in the list");
+    if (sims[i]->prm.precision != sims[0]->prm.precision)
+      return fail(SIPF_EINVAL, "mixed precision in one batch");
+    if (sims[i]->prm.deposit_order != sims[0]->prm.deposit_order)
+      return fail(SIPF_EINVAL, "mixed deposit order in one batch");
+    if (dim_of(sims[i]->prm) != 3)
+      return fail(SIPF_EINVAL, "batched steps are three-dimensional only");
+    if (sims[i]->device != sims[0]->device)
+      return fail(SIPF_EINVAL, "simulations on different devices");
+    for (int j = 0; j < i; ++j)
+      if (sims[j] == sims[i]) return fail(SIPF_EINVAL, "simulation listed twice");
+  }
+  return SIPF_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1006,6 +1178,11 @@ int sipf_init(const sipf_params* prm, void* d_workspace, size_t bytes, void* hip
   sim->lay = L;
   sim->stream = static_cast<hipStream_t>(hip_stream);
   (void)hipGetDevice(&sim->device);
+  DevScratch* ds = nullptr;  // set-up of the allocation-free batched step on this device
+  if ((rc = scratch_setup(sim->device, &ds)) != SIPF_OK) {
+    delete sim;
+    return rc;
+  }
   if (hipEventCreateWithFlags(&sim->ev, hipEventDisableTiming) != hipSuccess) {
     delete sim;
     return fail(SIPF_EHIP, "hipEventCreate failed");
@@ -1059,24 +1236,22 @@ int sipf_set_stream(sipf_sim* sim, void* hip_stream) {
 }
 
 int sipf_step_batch(sipf_sim* const* sims, int32_t nsims, int32_t nsteps) {
-  if (!sims || nsims <= 0) return fail(SIPF_EINVAL, "empty simulation list");
-  if (nsteps < 0) return fail(SIPF_EINVAL, "nsteps must be >= 0");
-  for (int i = 0; i < nsims; ++i) {
-    if (!sims[i]) return fail(SIPF_EINVAL, "NULL simulation in the list");
-    if (sims[i]->prm.precision != sims[0]->prm.precision)
-      return fail(SIPF_EINVAL, "mixed precision in one batch");
-    if (sims[i]->prm.deposit_order != sims[0]->prm.deposit_order)
-      return fail(SIPF_EINVAL, "mixed deposit order in one batch");
-    if (dim_of(sims[i]->prm) != 3)
-      return fail(SIPF_EINVAL, "batched steps are three-dimensional only");
-    if (sims[i]->device != sims[0]->device)
-      return fail(SIPF_EINVAL, "simulations on different devices");
-    for (int j = 0; j < i; ++j)
-      if (sims[j] == sims[i]) return fail(SIPF_EINVAL, "simulation listed twice");
-  }
+  int rc = check_batch(sims, nsims, nsteps);
+  if (rc) return rc;
   if (nsteps == 0) return SIPF_OK;
   return sims[0]->prm.precision == SIPF_FP64 ? step_batch_t<double>(sims, nsims, nsteps)
                                              : step_batch_t<float>(sims, nsims, nsteps);
+}
+
+int sipf_step_batch_noalloc(sipf_sim* const* sims, int32_t nsims, int32_t nsteps) {
+  if (nsims > kNoAllocMaxSims)
+    return fail(SIPF_EINVAL, "the allocation-free batched step takes at most " +
+                                 std::to_string(kNoAllocMaxSims) + " simulations");
+  int rc = check_batch(sims, nsims, nsteps);
+  if (rc) return rc;
+  if (nsteps == 0) return SIPF_OK;
+  return sims[0]->prm.precision == SIPF_FP64 ? step_batch_noalloc_t<double>(sims, nsims, nsteps)
+                                             : step_batch_noalloc_t<float>(sims, nsims, nsteps);
 }
 
 int sipf_fields(sipf_sim* sim, double* v, double* m, double* w, double* X, double* a,

@@ -29,8 +29,8 @@ ERRORS = {-1: "SIPF_EINVAL", -2: "SIPF_ENOMEM", -3: "SIPF_EHIP", -4: "SIPF_EPOS"
 
 # exported symbols, as declared in include/sipf.h
 EXPORTS = ("sipf_state_bytes", "sipf_init", "sipf_step", "sipf_set_stream", "sipf_step_batch",
-           "sipf_fields", "sipf_aux", "sipf_step_timed", "sipf_resample", "sipf_destroy",
-           "sipf_last_error")
+           "sipf_step_batch_noalloc", "sipf_fields", "sipf_aux", "sipf_step_timed",
+           "sipf_resample", "sipf_destroy", "sipf_last_error")
 STAGES = ("zfwd", "yfwd", "xpass", "yinv", "zinv", "particles", "finalize", "binning")
 
 
@@ -89,6 +89,7 @@ def lib():
                                 dp, dp, dp, dp, dp, ctypes.POINTER(vp)]
         L.sipf_step.argtypes = [vp, ctypes.c_int32]
         L.sipf_step_batch.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_int32]
+        L.sipf_step_batch_noalloc.argtypes = [ctypes.POINTER(vp), ctypes.c_int32, ctypes.c_int32]
         L.sipf_set_stream.argtypes = [vp, vp]
         L.sipf_fields.argtypes = [vp, dp, dp, dp, dp, dp, ctypes.POINTER(Diag)]
         L.sipf_aux.argtypes = [vp, dp, dp]
@@ -98,8 +99,8 @@ def lib():
         L.sipf_destroy.restype = None
         L.sipf_last_error.restype = ctypes.c_char_p
         for name in ("sipf_state_bytes", "sipf_init", "sipf_step", "sipf_step_batch",
-                     "sipf_fields", "sipf_aux", "sipf_step_timed", "sipf_set_stream",
-                     "sipf_resample"):
+                     "sipf_step_batch_noalloc", "sipf_fields", "sipf_aux", "sipf_step_timed",
+                     "sipf_set_stream", "sipf_resample"):
             getattr(L, name).restype = ctypes.c_int
         _lib = L
     return _lib
@@ -222,3 +223,10 @@ class Simulation:
 def step_batch(sims, nsteps=1):
     arr = (ctypes.c_void_p * len(sims))(*[s.handle for s in sims])
     _check(lib().sipf_step_batch(arr, len(sims), int(nsteps)))
+
+
+def step_batch_noalloc(sims, nsteps=1):
+    """sipf_step_batch_noalloc: the batched step with its launch table in the library's
+    per-GPU device array (no device allocation, no graph instantiation)."""
+    arr = (ctypes.c_void_p * len(sims))(*[s.handle for s in sims])
+    _check(lib().sipf_step_batch_noalloc(arr, len(sims), int(nsteps)))

@@ -129,3 +129,11 @@ def test_two_dimensional_state_bytes():
     assert expect <= b2 < expect + 64 * 1024
     assert sipf.state_bytes(_p(N=1024, P=100, dim=2)) > 0
     assert sipf.state_bytes(_p(N=512, P=100, dim=3)) == sipf.state_bytes(_p(N=512, P=100, dim=0))
+
+
+def test_noalloc_batch_rejects_more_than_64_simulations():
+    L = sipf.lib()
+    arr = (ctypes.c_void_p * 65)()
+    assert L.sipf_step_batch_noalloc(arr, 65, 1) == -1
+    assert b"at most 64" in L.sipf_last_error()
+    assert L.sipf_step_batch_noalloc(arr, 0, 1) == -1
