@@ -85,6 +85,50 @@ __device__ __forceinline__ float rho_of(float w) {
   return 2.0f * w * __builtin_amdgcn_rcpf(1.0f + w);
 }
 
+// Keep a loop-invariant value in a register for the whole pass.  Values read from the
+// descriptor (constant address space) would otherwise be re-read inside the particle loop,
+// and every scalar load is followed by a wait on the counter it shares with LDS operations,
+// so the next particle would wait for the previous one's deposit atomics to drain.
+// (The values are uniform; readfirstlane moves one that was computed in a vector register.)
+template <typename U>
+__device__ __forceinline__ U keep_in_sgpr(U v) {
+  static_assert(sizeof(U) == 4 || sizeof(U) == 8, "32- or 64-bit values");
+  if constexpr (sizeof(U) == 4) {
+    uint32_t b = (uint32_t)__builtin_amdgcn_readfirstlane((int)__builtin_bit_cast(uint32_t, v));
+    asm volatile("" : "+s"(b));
+    return __builtin_bit_cast(U, b);
+  } else {
+    const uint64_t w = __builtin_bit_cast(uint64_t, v);
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)w);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(w >> 32));
+    asm volatile("" : "+s"(lo), "+s"(hi));
+    return __builtin_bit_cast(U, (uint64_t)lo | ((uint64_t)hi << 32));
+  }
+}
+
+// Mass update a' = a exp(x), x = tau (rho - 1).  float64: the exact exponential.  float32
+// form: a' = a + a expm1(x) with expm1 by its Taylor polynomial to degree 8 in float32
+// (relative truncation error below 1e-8 for |x| <= 1/2, the range of tau |rho - 1| <= tau
+// <= 1/2 for w >= 0) and one float64 multiply-add, so that the mass itself is accumulated
+// in float64 and the relative error of a step's factor is about |x| 2^-24; outside that
+// range (w < 0 at a node of the implicit solve's small negative lobes) the float64 path.
+__device__ __forceinline__ double mass_factor_update(double a, double x) {
+  return a * exp(x);
+}
+__device__ __forceinline__ double mass_factor_update(double a, float x) {
+  if (!(fabsf(x) <= 0.5f)) return a * exp((double)x);
+  float e = 1.0f / 40320.0f;
+  e = fmaf(e, x, 1.0f / 5040.0f);
+  e = fmaf(e, x, 1.0f / 720.0f);
+  e = fmaf(e, x, 1.0f / 120.0f);
+  e = fmaf(e, x, 1.0f / 24.0f);
+  e = fmaf(e, x, 1.0f / 6.0f);
+  e = fmaf(e, x, 0.5f);
+  e = fmaf(e, x, 1.0f);
+  e *= x;
+  return fma(a, (double)e, a);
+}
+
 template <typename T>
 __device__ __forceinline__ T wrap_periodic(T x, T L) {
   if (x < (T)0) x += L;
@@ -392,6 +436,8 @@ __global__ void __launch_bounds__(kThreads)
   }
 
   const uint32_t n = (uint32_t)(*d.step);
+  const T inv_h = keep_in_sgpr(d.inv_h);
+  const T inv_h3 = keep_in_sgpr(d.inv_h3);
   T* xo = d.xs[0] + start;
   T* yo = d.ys[0] + start;
   T* zo = d.zs[0] + start;
@@ -417,12 +463,12 @@ __global__ void __launch_bounds__(kThreads)
       const double a = pa[j];
       int l[3];
       if (deposit_only) {
-        const Stencil<T> s0 = make_stencil(x, y, z, d.inv_h, N);
-        deposit_one<ORDER, R>(ubar, acc, s0, rg, use_region, N, (T)a * d.inv_h3);
+        const Stencil<T> s0 = make_stencil(x, y, z, inv_h, N);
+        deposit_one<ORDER, R>(ubar, acc, s0, rg, use_region, N, (T)a * inv_h3);
         continue;
       }
       // gather (d1 v, d2 v, d3 v, w) at the old position
-      const Stencil<T> st = make_stencil(x, y, z, d.inv_h, N);
+      const Stencil<T> st = make_stencil(x, y, z, inv_h, N);
       T wx[2], wy[2], wz[2];
       weights(st, wx, wy, wz);
       T g0 = 0, g1 = 0, g2 = 0, gw = 0;
@@ -470,7 +516,7 @@ __global__ void __launch_bounds__(kThreads)
       const T zz = wrap_periodic(z + d.drift * g2 + d.noise_amp * zn[2], d.L);
       const T rho = rho_of(gw);
       const double an = linear_mass ? a * (1.0 + d.dt * (double)rho - d.dt)
-                                    : a * exp(d.dt * ((double)rho - 1.0));
+                                    : mass_factor_update(a, (T)d.dt * (rho - (T)1));
       xo[i] = xn;
       yo[i] = yn;
       zo[i] = zz;
@@ -485,8 +531,8 @@ __global__ void __launch_bounds__(kThreads)
       }
 
       // deposit of the new state: ubar^{n+1}
-      const Stencil<T> sn = make_stencil(xn, yn, zz, d.inv_h, N);
-      deposit_one<ORDER, R>(ubar, acc, sn, rg, use_region, N, (T)an * d.inv_h3);
+      const Stencil<T> sn = make_stencil(xn, yn, zz, inv_h, N);
+      deposit_one<ORDER, R>(ubar, acc, sn, rg, use_region, N, (T)an * inv_h3);
     }
     // Next batch, if the chunk has one.  Its loads are issued here, after an explicit wait
     // for this batch's stores: the compiler cannot tell that the exec-masked loads of the
@@ -664,6 +710,8 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
     __syncthreads();
   }
   const uint32_t n = (uint32_t)(*d.step);
+  const T inv_h = keep_in_sgpr(d.inv_h);
+  const T inv_h3 = keep_in_sgpr(d.inv_h3);
   const bool linear_mass = d.flags & SIPF_FLAG_LINEAR_MASS;
   const bool noise = !(d.flags & SIPF_FLAG_NO_NOISE);
   Acc dg;
@@ -678,11 +726,11 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
       const T x = px[j], y = py[j];
       const double a = pa[j];
       if (deposit_only) {
-        deposit2(ubar, acc, make_stencil2(x, y, d.inv_h, N), rg, use_region, N,
-                 (T)a * d.inv_h3);
+        deposit2(ubar, acc, make_stencil2(x, y, inv_h, N), rg, use_region, N,
+                 (T)a * inv_h3);
         continue;
       }
-      const Stencil<T> st = make_stencil2(x, y, d.inv_h, N);
+      const Stencil<T> st = make_stencil2(x, y, inv_h, N);
       const T wx[2] = {(T)1 - st.f[0], st.f[0]};
       const T wy[2] = {(T)1 - st.f[1], st.f[1]};
       T g0 = 0, g1 = 0, gw = 0;
@@ -724,7 +772,7 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
       const T yn = wrap_periodic(y + d.drift * g1 + d.noise_amp * zn[1], d.L);
       const T rho = rho_of(gw);
       const double an = linear_mass ? a * (1.0 + d.dt * (double)rho - d.dt)
-                                    : a * exp(d.dt * ((double)rho - 1.0));
+                                    : mass_factor_update(a, (T)d.dt * (rho - (T)1));
       xo[i] = xn;
       yo[i] = yn;
       ao[i] = an;
@@ -736,8 +784,8 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
       } else {
         dg.cnt[0] += 1;
       }
-      deposit2(ubar, acc, make_stencil2(xn, yn, d.inv_h, N), rg, use_region, N,
-               (T)an * d.inv_h3);
+      deposit2(ubar, acc, make_stencil2(xn, yn, inv_h, N), rg, use_region, N,
+               (T)an * inv_h3);
     }
     if (j0 + kB >= kPer || (uint32_t)((j0 + kB) * kThreads) >= cnt) break;
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);  // see the 3D pass
