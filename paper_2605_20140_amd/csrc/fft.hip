@@ -417,6 +417,24 @@ __device__ __forceinline__ int deriv_freq(int k, int N) {
 // signed frequency for |q|^2 (Nyquist kept as -N/2)
 __device__ __forceinline__ int lap_freq(int k, int N) { return k < (N >> 1) ? k : k - N; }
 
+// Multiplier of the diffusion-decay solve (eq. k_q_tilde_update) of one Fourier mode, c =
+// tau (R + D |k|^2), times the low-pass factor lp (1 without the filter).  For w the solve's
+// multiplier itself, lp / (1 + c).  For m its change, lp / (1 + c) - 1 = (lp - 1 - c) /
+// (1 + c): the inverse pass adds m* back (m^{n+1} = m* + IFFT((M - 1) FFT(m*))), so that the
+// rounding of the transforms, relative to the transformed values, is scaled by the small
+// M - 1 instead of reaching m^{n+1} in full at every step (with float32 transforms it would
+// accumulate in m and, through v' = v exp(-alpha tau m), in v).
+template <typename T>
+__device__ __forceinline__ T solve_multiplier(T c, T lp, bool change) {
+  const T r = (T)1 / ((T)1 + c);
+  return change ? (lp - (T)1 - c) * r : lp * r;
+}
+// the same for a tabulated multiplier M (exponential or aliased kernel)
+template <typename T>
+__device__ __forceinline__ T table_multiplier(T M, T lp, bool change) {
+  return change ? M * lp - (T)1 : M * lp;
+}
+
 // ---- zfwd ---------------------------------------------------------------------------------
 template <typename T, int LG>
 __device__ __forceinline__ void zfwd_body(SimC<T>& d, int lb, unsigned char* smem) {
@@ -432,6 +450,7 @@ __device__ __forceinline__ void zfwd_body(SimC<T>& d, int lb, unsigned char* sme
   tr.load(d.tw);  // in flight with the first batch of field loads
   const T dt = (T)d.dt, gam = (T)d.gamma, adt = (T)(d.alpha * d.dt);
   const bool freeze_v = d.flags & SIPF_FLAG_FREEZE_V;
+  const bool freeze_m = d.flags & SIPF_FLAG_FREEZE_M;
   const bool impl_v = d.flags & SIPF_FLAG_IMPLICIT_V;
   Acc acc;
   acc_init(acc);
@@ -458,11 +477,16 @@ __device__ __forceinline__ void zfwd_body(SimC<T>& d, int lb, unsigned char* sme
       if (e < nel) {
         const int rr = e >> LG, iz = e & (N - 1);
         const T ms = mm[k] + dt * u[k];
+        if (!freeze_m) d.m[g0 + e] = ms;  // m*, to which the inverse pass adds the solve's change
         const T eta = (T)2 * u[k] / ((T)1 + u[k]);
         const T wsr = ww[k] + dt * (gam * vv[k] - eta * ww[k]);
         T vn = vv[k];
         if (!freeze_v) {
-          vn = impl_v ? vv[k] / ((T)1 + adt * mm[k]) : vv[k] * exp(-adt * mm[k]);
+          // v' = v exp(-y) (or v / (1 + y)), y = alpha tau m, written as v plus its small
+          // decrement: the factor itself, rounded next to 1, would carry an absolute error of
+          // up to half an ulp of 1 every step, which float32 v accumulates step after step
+          const T y = adt * mm[k];
+          vn = impl_v ? vv[k] - vv[k] * (y / ((T)1 + y)) : fma(vv[k], expm1(-y), vv[k]);
           d.v[g0 + e] = vn;
         }
         if (isfinite((double)vn)) acc_min(acc, D_MIN_V, (double)vn); else acc.cnt[0] += 1;
@@ -647,17 +671,16 @@ __device__ __forceinline__ void xpass_body(SimC<T>& d, int lb, unsigned char* sm
     const int kx = ufpos<LG>(p);
     const int ky = ufpos<LG>(y0 + c);
     if (f < 2) {
+      const T lp = use_lp ? lpt[kx] * lpt[ky] * lpt[kz] : (T)1;
       T mult;
       if (implicit) {
         const int qx = lap_freq(kx, N), qy = lap_freq(ky, N);
         const T k2 = k0 * k0 * (T)(qx * qx + qy * qy + qz * qz);
-        mult = (T)1 / ((T)1 + dt * (decay + D * k2));
+        mult = solve_multiplier(dt * (decay + D * k2), lp, f == 0);
       } else {
-        mult = e_dec * tab[kx] * tab[ky] * tab[kz];
+        mult = table_multiplier(e_dec * tab[kx] * tab[ky] * tab[kz], lp, f == 0);
       }
-      mult *= inv_n3;
-      if (use_lp) mult *= lpt[kx] * lpt[ky] * lpt[kz];
-      return cscale(val, mult);
+      return cscale(val, mult * inv_n3);
     } else if (f == 2) {
       T kk = k0 * (T)deriv_freq(kx, N) * inv_n3;
       if (use_lp) kk *= lpt[kx] * lpt[ky] * lpt[kz];
@@ -711,11 +734,11 @@ __device__ __forceinline__ void col2d_body(SimC<T>& d, int lb, unsigned char* sm
       T mult;
       if (implicit) {
         const int q1 = lap_freq(k1, N), q2 = lap_freq(k2, N);
-        mult = (T)1 / ((T)1 + dt * (decay + D * k0 * k0 * (T)(q1 * q1 + q2 * q2)));
+        mult = solve_multiplier(dt * (decay + D * k0 * k0 * (T)(q1 * q1 + q2 * q2)), lp, f == 0);
       } else {
-        mult = e_dec * tab[k1] * tab[k2];
+        mult = table_multiplier(e_dec * tab[k1] * tab[k2], lp, f == 0);
       }
-      return cscale(val, mult * inv_nd * lp);
+      return cscale(val, mult * inv_nd);
     } else if (f == 2) {
       const T kk = k0 * (T)deriv_freq(k1, N) * inv_nd * lp;
       return cplx<T>{-kk * val.y, kk * val.x};
@@ -814,11 +837,11 @@ __device__ __forceinline__ void plane_body(SimC<T>& d, int lb, unsigned char* sm
       if (implicit) {
         const int qx = lap_freq(kx, N), qy = lap_freq(ky, N);
         const T k2 = k0 * k0 * (T)(qx * qx + qy * qy + qz * qz);
-        mult = (T)1 / ((T)1 + dt * (decay + D * k2));
+        mult = solve_multiplier(dt * (decay + D * k2), lp, job == 0);
       } else {
-        mult = sep_z * tab[kx] * tab[ky];
+        mult = table_multiplier(sep_z * tab[kx] * tab[ky], lp, job == 0);
       }
-      return cscale(val, mult * inv_n3 * lp);
+      return cscale(val, mult * inv_n3);
     } else if (job < 4) {
       const T kk = k0 * (T)deriv_freq(job == 2 ? kx : ky, N) * inv_n3 * lp;
       return cplx<T>{-kk * val.y, kk * val.x};
@@ -857,7 +880,7 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
   constexpr int ZB = ZBatch<T>::n;
   const int nel = B * N;
   const int64_t g0 = r0 * N;
-  // The old w (and, with m frozen, m) of the first ZB elements per thread - all of them,
+  // The old w and m* (with m frozen, m^n) of the first ZB elements per thread - all of them,
   // unless a block has more than ZB kThreads elements - are loaded first: they are needed
   // only after the transforms, so their loads overlap everything before.
   T wold[ZB], mold[ZB];
@@ -866,7 +889,7 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
     const int e = threadIdx.x + k * kThreads;
     if (e < nel) {
       wold[k] = d.w[g0 + e];
-      if (freeze_m) mold[k] = d.m[g0 + e];
+      mold[k] = d.m[g0 + e];
     }
   }
   TwiddleRegs<T, LG, kThreads> tr;
@@ -938,7 +961,7 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
         const int e = e0 + k * kThreads;
         if (e < nel) {
           wold[k] = d.w[g0 + e];
-          if (freeze_m) mold[k] = d.m[g0 + e];
+          mold[k] = d.m[g0 + e];
         }
       }
     }
@@ -952,8 +975,11 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
       const cplx<T> gg = GG[rr * LS + iz];
       const cplx<T> gzp = GZ[(rr >> 1) * LS + iz];
       d.g4[g] = vec4<T>{gg.x, gg.y, (rr & 1) ? gzp.y : gzp.x, wold[k]};
-      T mn = mw.x, wn = mw.y;
-      if (!freeze_m) d.m[g] = mn; else mn = mold[k];
+      T mn = mold[k], wn = mw.y;  // mold: m* (or, with m frozen, m^n)
+      if (!freeze_m) {
+        mn += mw.x;
+        d.m[g] = mn;
+      }
       if (!freeze_w) d.w[g] = wn; else wn = wold[k];
       const double md = mn, wd = wn;
       if (isfinite(md) && isfinite(wd)) {
