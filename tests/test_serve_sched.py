@@ -19,25 +19,42 @@ class FakeClock:
 
 
 class FakeBackend:
-    """Step cost proportional to the resident work; bytes proportional to N^3 + P."""
+    """Step cost proportional to the resident work; bytes proportional to N^3 + P.
+    Admission and retirement complete after admit_delay / retire_delay seconds of the
+    (simulated) clock, as the GPU backend's worker threads do."""
 
-    def __init__(self, clock):
+    def __init__(self, clock, admit_delay=0.0, retire_delay=0.0):
         self.clock = clock
+        self.admit_delay = admit_delay
+        self.retire_delay = retire_delay
         self.resident = set()
         self.steps_taken = {}
         self.batches = []
+        self.admitting, self.retiring = set(), set()
+        self.ticks_while_admitting = 0
+        self.ticks_while_retiring = 0
 
     def state_bytes(self, r):
         return 100 * r.N ** 3 + 40 * r.P
 
-    def admit(self, r):
-        self.resident.add(r.rid)
-        self.steps_taken[r.rid] = 0
-        self.clock.t += 1e-4
-        return r.rid
+    def admit_start(self, r):
+        self.clock.t += 1e-5
+        self.admitting.add(r.rid)
+        return (r.rid, self.clock.t + self.admit_delay)
+
+    def admit_poll(self, ticket):
+        rid, ready = ticket
+        if self.clock.t < ready:
+            return None
+        self.admitting.remove(rid)
+        self.resident.add(rid)
+        self.steps_taken[rid] = 0
+        return rid
 
     def step(self, handles, k):
-        assert set(handles) <= self.resident
+        assert set(handles) <= self.resident and not set(handles) & self.retiring
+        self.ticks_while_admitting += bool(self.admitting)
+        self.ticks_while_retiring += bool(self.retiring)
         self.batches.append(tuple(handles))
         work = sum(self._req[h].P for h in handles)
         self.clock.t += k * (2e-5 + work * 1e-10)
@@ -50,11 +67,18 @@ class FakeBackend:
     def wait(self, token):
         pass
 
-    def finish(self, h, keep):
-        return dict(steps=self.steps_taken[h])
+    def retire_start(self, h, keep):
+        assert h in self.resident
+        self.retiring.add(h)
+        return (h, self.clock.t + self.retire_delay)
 
-    def release(self, h):
+    def retire_poll(self, ticket):
+        h, ready = ticket
+        if self.clock.t < ready:
+            return None
+        self.retiring.remove(h)
         self.resident.remove(h)
+        return self.clock.t, dict(steps=self.steps_taken[h])
 
 
 def _requests(n=40, seed=0, rate=200.0):
@@ -113,3 +137,25 @@ def test_request_larger_than_budget_is_rejected():
     be._req = {0: r}
     with pytest.raises(ValueError):
         Server(be, 1000, clock=clk, sleep=clk.sleep).run([r])
+
+
+def test_ticks_continue_while_admission_and_retirement_run():
+    """Slow initialisation and slow copies to the host do not stall the resident
+    simulations: ticks keep being issued while other requests are admitted or retired, and a
+    simulation joins the batch only once it is initialised."""
+    clk = FakeClock()
+    be = FakeBackend(clk, admit_delay=2e-3, retire_delay=3e-3)
+    reqs = _requests(n=30, rate=2000.0)
+    be._req = {r.rid: r for r in reqs}
+    srv = Server(be, 10 ** 9, max_slots=8, tick_steps=5, clock=clk, sleep=clk.sleep)
+    recs, summ = srv.run(reqs)
+    assert summ["requests"] == len(reqs)
+    for r in reqs:
+        rec = recs[r.rid]
+        assert rec.output["steps"] == r.steps
+        assert rec.t_join >= rec.t_admit + 2e-3 - 1e-12
+        assert rec.t_done > rec.t_join
+    # batches were stepped while some request was still initialising or being copied out
+    assert be.ticks_while_admitting > 0 and be.ticks_while_retiring > 0
+    assert set(summ["host_ms_per_tick"]) == {"admit", "join", "launch", "wait", "retire", "idle"}
+    assert summ["ticks"] > 0
