@@ -27,16 +27,27 @@ METRIC = ("particle-steps/s + HBM GB/s fraction at 128^3/2^23 (FP32 vs FP64); "
           "p50/p99 served")
 
 
-def stage_bytes(N, P, s):
-    """Bytes each stage must move per step by design (reads + writes), s = 4 or 8."""
+def plane_path(N, s):
+    """The library runs the y and x transforms of a k3 plane in one block (the plane pass)
+    when the plane fits the kernel's LDS: float32 N <= 128, float64 N <= 64 (3D)."""
+    return N <= (128 if s == 4 else 64)
+
+
+def stage_bytes(N, P, s, lowpass=False):
+    """Bytes each stage must move per step by design (reads + writes), s = 4 or 8.  On the
+    plane path the "xpass" stage is the plane pass (reads the M*, W*, V half spectra, writes
+    M, W, G1, G2 and, with the low-pass filter, the filtered V) and the y passes do not run."""
     G = N ** 3
     half = (N // 2 + 1) * N * N * 2 * s  # one half spectrum
+    plane = plane_path(N, s)
     return {
-        "zfwd": G * 4 * s + G * 2 * s + 3 * half,
-        "yfwd": 6 * half,
-        "xpass": 6 * half,
-        "yinv": 9 * half,
-        "zinv": 5 * half + G * s + G * 6 * s,
+        # reads ubar, m, v, w; writes v, m* and the cleared ubar; 3 half spectra
+        "zfwd": G * 4 * s + G * 3 * s + 3 * half,
+        "yfwd": 0 if plane else 6 * half,
+        "xpass": (3 + 4 + (1 if lowpass else 0)) * half if plane else 6 * half,
+        "yinv": 0 if plane else 9 * half,
+        # reads 5 half spectra, w^n and m*; writes m, w and the gather array (4 per node)
+        "zinv": 5 * half + 2 * G * s + G * 6 * s,
         # particles: read x,y,z,a; write x,y,z,a (the 4-byte particle index that keys the
         # noise is not counted) + gather array read once + deposit target written once
         "particles": P * (6 * s + 16) + G * 5 * s,
@@ -114,7 +125,7 @@ def copy_calibration():
     assert rc == 0 and bool((dst == 1).all())
 
 
-def run_form(ic, precision, steps, warmup, profile_steps, workload, **over):
+def run_form(ic, precision, steps, warmup, profile_steps, workload, keep_state=False, **over):
     import torch
     from paper_2605_20140_amd import sipf
     prm = dict(ic["params"], **over)
@@ -137,11 +148,11 @@ def run_form(ic, precision, steps, warmup, profile_steps, workload, **over):
     wall = time.perf_counter() - wall0
     ms = t0.elapsed_time(t1)
     stage_ms = sim.step_timed(profile_steps)
-    out = sim.fields(particles=False)
+    out = sim.fields(particles=keep_state)
     sim.close()
     d = out["diag"]
     s = 4 if precision == 1 else 8
-    sb = stage_bytes(prm["N"], prm["P"], s)
+    sb = stage_bytes(prm["N"], prm["P"], s, lowpass=prm.get("H0", 0) > 0)
     if prm.get("dim") == 2:
         return dict(value=prm["P"] * steps / (ms * 1e-3), ms_per_step=ms / steps,
                     init_s=init_s,
@@ -159,6 +170,7 @@ def run_form(ic, precision, steps, warmup, profile_steps, workload, **over):
     traffic = (measured_traffic(workload, precision)
                if dominant == "particles" and not over else None)
     return dict(
+        state=out if keep_state else None,
         value=prm["P"] * steps / (ms * 1e-3),
         ms_per_step=ms / steps,
         wall_ms_per_step=wall * 1e3 / steps,
@@ -173,8 +185,26 @@ def run_form(ic, precision, steps, warmup, profile_steps, workload, **over):
     )
 
 
-def cpu_baseline(ic, steps=3):
-    """FP64 numpy oracle, a few steps of the same workload on the host (bounded sample)."""
+def host_cpu():
+    """Model name and core counts of the host the CPU baseline runs on."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = None
+    return dict(model=model, nproc=os.cpu_count(), usable=usable,
+                omp_num_threads=os.environ.get("OMP_NUM_THREADS"))
+
+
+def _oracle_time(ic, steps):
     from oracle import step as S
     prm = ic["params"]
     op = S.Params(N=prm["N"], dt=prm["dt"], L=prm["L"], D_u=prm["D_u"], chi=prm["chi"],
@@ -183,10 +213,49 @@ def cpu_baseline(ic, steps=3):
     st = S.State(ic["X0"], ic["a0"], ic["v0"], ic["m0"], ic["w0"], 0)
     t = time.perf_counter()
     S.run(st, op, steps)
-    dt = time.perf_counter() - t
-    return dict(value=prm["P"] * steps / dt, unit="particle-steps/s", cores=1, kind="oracle",
+    return time.perf_counter() - t
+
+
+def cpu_baseline(ic, steps=3):
+    """The FP64 numpy oracle as it stands, timed on the host on bounded samples: a few steps
+    of the benchmark workload (the line's figure), the whole 16^3 / 4096-particle run (100
+    steps) and the first steps of the 64^3 / 2^20-particle run.  The oracle is single-threaded
+    numpy (its FFTs and array operations use one thread), so `cores` is 1."""
+    from paper_2605_20140_amd import workloads as W
+    prm = ic["params"]
+    dt = _oracle_time(ic, steps)
+    small = {}
+    for name, nst in (("blob16", 100), ("modes64", 3)):
+        icn = W.make_initial_state(name)
+        t = _oracle_time(icn, nst)
+        small[name] = dict(steps=nst, seconds=round(t, 2), N=icn["params"]["N"],
+                           P=icn["params"]["P"],
+                           particle_steps_per_s=icn["params"]["P"] * nst / t,
+                           full_run_steps=icn["params"]["steps"])
+    return dict(value=prm["P"] * steps / dt, unit="particle-steps/s", cores=1, threads=1,
+                kind="oracle", host=host_cpu(),
                 sample=f"{steps} steps of the full workload ({prm['N']}^3 grid, {prm['P']} "
-                       "particles), float64 numpy oracle, single thread", seconds=round(dt, 2))
+                       "particles), float64 numpy oracle, single thread", seconds=round(dt, 2),
+                other_configs=small)
+
+
+def precision_errors(s32, s64, L=1.0):
+    """Per-field error of the float32 form against the float64 form after the same steps
+    (both on the GPU, same noise): relative L2 and max norms of v, m, w; positions as the
+    largest and rms minimum-image distance over L; masses as the largest relative error."""
+    import numpy as np
+    out = {}
+    for f in ("v", "m", "w"):
+        d = s32[f] - s64[f]
+        out[f] = dict(l2=float(np.linalg.norm(d) / np.linalg.norm(s64[f])),
+                      max=float(np.abs(d).max() / np.abs(s64[f]).max()))
+    d = s32["X"] - s64["X"]
+    d = np.abs(d - L * np.round(d / L)) / L
+    out["X"] = dict(max=float(d.max()), rms=float(np.sqrt((d ** 2).mean())))
+    out["a"] = dict(max=float(np.abs(s32["a"] / s64["a"] - 1.0).max()))
+    out["total_mass"] = float(abs(s32["a"].sum() / s64["a"].sum() - 1.0))
+    out["step"] = s32["diag"]["step"]
+    return out
 
 
 def next_rows(ic, steps=50, warmup=5, profile_steps=8):
@@ -244,9 +313,11 @@ def next_rows(ic, steps=50, warmup=5, profile_steps=8):
     return out
 
 
-def served(nreq, budget_gib, seed=4):
+def served(nreq, budget_gib, seed=4, graphs=False):
     """Served mix: Poisson arrivals at 0.7 x the solo capacity (requests/s measured by
-    running a few requests alone first), continuous batching, p50/p99 latency."""
+    running a few requests alone first), continuous batching, p50/p99 latency and the tick
+    loop's host time per tick (admission hand-off, joins, launches, fence waits,
+    retirement hand-off, idle)."""
     import numpy as np
     from paper_2605_20140_amd import serve, workloads as W
     from concurrent.futures import ThreadPoolExecutor
@@ -257,9 +328,9 @@ def served(nreq, budget_gib, seed=4):
     with ThreadPoolExecutor(8) as ex:
         for r, ic in zip(reqs, ex.map(W.served_initial_state, q)):
             r.ic = ic
-    be = serve.GpuBackend(precision=1)
+    be = serve.GpuBackend(precision=1, graphs=graphs)
     # solo capacity: the first few requests, one at a time (once untimed, so that first-use
-    # costs such as module loading and graph instantiation do not lower the rate)
+    # costs such as module loading do not lower the rate)
     probe = reqs[:8]
     for _ in range(2):
         t = time.perf_counter()
@@ -273,9 +344,12 @@ def served(nreq, budget_gib, seed=4):
         r.t_arrive = float(ta)
     srv = serve.Server(be, budget_gib << 30, max_slots=64, tick_steps=10)
     _, summ = srv.run(reqs)
+    be.close()
     summ.update(rate_per_s=rate, solo_service_s=solo_s, hbm_budget_gib=budget_gib,
                 max_slots=64, tick_steps=10, form="fp32",
+                step_path="captured graph per batch" if graphs else "allocation-free batched step",
                 mix="N in {32,64,128}, P = 2^U(16,22), chi = 10^U(-3,-2), 200 steps, dt 1e-3")
+    summ["p99_over_p50"] = summ["latency_p99_s"] / summ["latency_p50_s"]
     return summ
 
 
@@ -292,6 +366,9 @@ def main():
                     help="skip the order-4 / low-pass / resampling / 2D measurements")
     ap.add_argument("--served-requests", type=int, default=256,
                     help="requests in the served-mix run (0: skip it)")
+    ap.add_argument("--served-graphs", action="store_true",
+                    help="served mix through sipf_step_batch's captured graphs instead of "
+                         "the allocation-free batched step")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one device-to-device copy of 512 MiB (the reference "
                          "the byte counters are scaled by)")
@@ -306,13 +383,19 @@ def main():
     from paper_2605_20140_amd import workloads as W
     ic = W.make_initial_state(args.workload)
     prm = ic["params"]
-    r32 = run_form(ic, 1, args.steps, args.warmup, args.profile_steps, args.workload)
+    keep = not args.no_fp64
+    r32 = run_form(ic, 1, args.steps, args.warmup, args.profile_steps, args.workload,
+                   keep_state=keep)
     r64 = (None if args.no_fp64 else
-           run_form(ic, 0, args.steps, args.warmup, args.profile_steps, args.workload))
+           run_form(ic, 0, args.steps, args.warmup, args.profile_steps, args.workload,
+                    keep_state=keep))
+    errs = precision_errors(r32.pop("state"), r64.pop("state"), prm["L"]) if keep else None
+    r32.pop("state", None)
     if args.copy_calibration:
         copy_calibration()
     nxt = None if args.no_next_rows else next_rows(ic)
-    srv = served(args.served_requests, 32) if args.served_requests > 0 else None
+    srv = (served(args.served_requests, 32, graphs=args.served_graphs)
+           if args.served_requests > 0 else None)
     cpu = None if args.no_cpu_baseline else cpu_baseline(ic)
     line = {
         "metric": METRIC,
@@ -337,6 +420,7 @@ def main():
         "check": r32["check"],
         "served": srv,
         "next_rows": nxt,
+        "fp32_vs_fp64": errs,
         "fp64": None if r64 is None else {
             "value": r64["value"], "ms_per_step": r64["ms_per_step"], "dtype": "f64",
             "init_s": r64["init_s"],
