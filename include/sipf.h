@@ -133,8 +133,9 @@ int sipf_init(const sipf_params* prm, void* d_workspace, size_t bytes, void* hip
 
 /* Enqueue nsteps >= 0 steps (Alg. sipf-pic loop body) on the simulation's stream; returns
  * without waiting.  Each step also recomputes the diagnostics (the kernels that write a
- * value reduce it as they go).  Errors: SIPF_EINVAL,
- * SIPF_EHIP. */
+ * value reduce it as they go).  The first call with nsteps > 0 captures the step as HIP
+ * graphs (host work only; captures are serialised across threads), which later calls
+ * replay.  Errors: SIPF_EINVAL, SIPF_EHIP. */
 int sipf_step(sipf_sim* sim, int32_t nsteps);
 
 /* Move a simulation to another stream (for example from the stream it was initialised on

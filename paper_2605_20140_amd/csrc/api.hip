@@ -479,8 +479,23 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   launch_diag_init<T>(b, sim->counts[K_DIAG], 1, st);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));  // host staging buffers are freed on return
+  return SIPF_OK;
+}
 
-  // capture one step as a graph on a private stream; replays go to the caller's stream
+// Stream captures are serialised across the process: captures begun on several threads at
+// once (simulations initialised or first stepped concurrently) have failed here with an
+// error recorded in one of them.
+std::mutex g_capture_mu;
+
+// Capture one step (and one step with binning) as graphs on a private stream; replays go to
+// the simulation's stream.  Done on the first sipf_step, so that simulations that are only
+// ever stepped in batches never capture.
+template <typename T>
+int capture_t(sipf_sim* sim) {
+  std::lock_guard<std::mutex> lk(g_capture_mu);
+  const sipf_params& p = sim->prm;
+  const int dim = dim_of(p);
+  const Batch<T> b = single_batch<T>(sim);
   HIPCHK(hipStreamCreateWithFlags(&sim->cap, hipStreamNonBlocking));
   HIPCHK(create_fork(sim->fork));
   const auto groups = single_groups<T>(sim, b);
@@ -761,6 +776,7 @@ int build_batch_graph(sipf_sim* const* sims, int nsims, int dev, BatchGraph** ou
   const Batch<T> b = table_batch<T>(base, nsims);
   for (size_t g = 0; g < sub.size(); ++g)
     groups[g].b = table_batch<T>(base + offs[g], (int)sub[g].size());
+  std::lock_guard<std::mutex> cap_lk(g_capture_mu);
   for (int bin = 0; bin < 2 && rc == SIPF_OK; ++bin) {
     chk(hipStreamBeginCapture(g_cap_stream[dev], hipStreamCaptureModeThreadLocal), "capture");
     if (rc != SIPF_OK) break;
@@ -1204,6 +1220,10 @@ int sipf_step(sipf_sim* sim, int32_t nsteps) {
   if (nsteps < 0) return fail(SIPF_EINVAL, "nsteps must be >= 0");
   int rc = order_after_batch(sim);
   if (rc) return rc;
+  if (nsteps > 0 && !sim->exec_bin) {
+    rc = sim->prm.precision == SIPF_FP64 ? capture_t<double>(sim) : capture_t<float>(sim);
+    if (rc) return rc;
+  }
   for (int32_t s = 0; s < nsteps; ++s) {
     if (sim->since_bin >= sim->resort_every) {
       HIPCHK(hipGraphLaunch(sim->exec_bin, sim->stream));
