@@ -41,13 +41,14 @@ def stage_bytes(N, P, s, lowpass=False):
     half = (N // 2 + 1) * N * N * 2 * s  # one half spectrum
     plane = plane_path(N, s)
     return {
-        # reads ubar, m, v, w; writes v, m* and the cleared ubar; 3 half spectra
+        # reads ubar, m, v, w; writes v, m* and w* (into ubar's array); 3 half spectra
         "zfwd": G * 4 * s + G * 3 * s + 3 * half,
         "yfwd": 0 if plane else 6 * half,
         "xpass": (3 + 4 + (1 if lowpass else 0)) * half if plane else 6 * half,
         "yinv": 0 if plane else 9 * half,
-        # reads 5 half spectra, w^n and m*; writes m, w and the gather array (4 per node)
-        "zinv": 5 * half + 2 * G * s + G * 6 * s,
+        # reads 5 half spectra, w^n, m* and w*; writes m, w, the gather array (4 per node)
+        # and the cleared ubar
+        "zinv": 5 * half + 3 * G * s + G * 7 * s,
         # particles: read x,y,z,a; write x,y,z,a (the 4-byte particle index that keys the
         # noise is not counted) + gather array read once + deposit target written once
         "particles": P * (6 * s + 16) + G * 5 * s,

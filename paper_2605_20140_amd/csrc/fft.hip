@@ -10,12 +10,13 @@
 //
 // Passes per step (each one kernel):
 //   zfwd : reaction (eq. g_hat_phy with S of eq. g_t) on (ubar, m, v, w) at time n, writes
-//          v^{n+1} and clears ubar; real z transforms of m*, w* (packed as m* + i w*) and of
-//          v^n (two rows packed) -> SM, SW, SV.
+//          v^{n+1}, m* (into m) and w* (into ubar's array); real z transforms of m*, w*
+//          (packed as m* + i w*) and of v^n (two rows packed) -> SM, SW, SV.
 //   yfwd : y transforms of SM, SW, SV (in place).
-//   xpass: x transforms, the diagonal multipliers of eq. k_q_tilde_update (m: decay beta,
-//          diffusion D_m; w: decay 1, diffusion D_w) and the x-derivative multiplier of
-//          eq. gradv (i (2 pi/L) q_1, Nyquist zeroed), inverse x transforms -> SM, SW, SGx.
+//   xpass: x transforms, the diagonal multipliers of eq. k_q_tilde_update in change form
+//          (m: decay beta, diffusion D_m; w: decay 1, diffusion D_w) and the x-derivative
+//          multiplier of eq. gradv (i (2 pi/L) q_1, Nyquist zeroed), inverse x transforms
+//          -> SM, SW, SGx.
 //          With the low-pass filter exp(-2 pi^2 |q|^2 / H0^2) (Alg. p2g text, Alg. sipf-pic)
 //          the filter multiplies the m, w and d1 v spectra, and a fourth job writes the
 //          filtered V (x round trip undone) into a buffer of its own, SVg; without it SVg
@@ -24,8 +25,9 @@
 //          spectrum SGy = i (2 pi/L) q_2 SVg.  SVg is transformed along y and z only (x stays
 //          in physical space), so the derivatives formed from it carry 1/N^2.
 //   zinv : forms the z-derivative spectrum i (2 pi/L) q_3 SVg, inverse real z transforms of
-//          (SM, SW), (SGx, SGy) and of row pairs of the z derivative; writes m^{n+1},
-//          w^{n+1} and the gather array g4 = (d1 v^n, d2 v^n, d3 v^n, w^n).
+//          (SM, SW), (SGx, SGy) and of row pairs of the z derivative; writes m^{n+1} =
+//          m* + change, w^{n+1} = w* + change (the solves in change form, below), the gather
+//          array g4 = (d1 v^n, d2 v^n, d3 v^n, w^n), and clears ubar for the deposit.
 //
 // Line transforms (length N = N1 N2, held in LDS): four-step.  Forward: N1 transforms of
 // length N2 over stride-N1 subsequences, twiddles W_N^{n1 k2}, then N2 transforms of length N1
@@ -417,22 +419,21 @@ __device__ __forceinline__ int deriv_freq(int k, int N) {
 // signed frequency for |q|^2 (Nyquist kept as -N/2)
 __device__ __forceinline__ int lap_freq(int k, int N) { return k < (N >> 1) ? k : k - N; }
 
-// Multiplier of the diffusion-decay solve (eq. k_q_tilde_update) of one Fourier mode, c =
-// tau (R + D |k|^2), times the low-pass factor lp (1 without the filter).  For w the solve's
-// multiplier itself, lp / (1 + c).  For m its change, lp / (1 + c) - 1 = (lp - 1 - c) /
-// (1 + c): the inverse pass adds m* back (m^{n+1} = m* + IFFT((M - 1) FFT(m*))), so that the
+// The diffusion-decay solves (eq. k_q_tilde_update) in change form: for f = m, w,
+// f^{n+1} = f* + IFFT((M - 1) FFT(f*)), M the solve's multiplier of one Fourier mode times
+// the low-pass factor lp (1 without the filter).  The inverse pass adds f* back, so that the
 // rounding of the transforms, relative to the transformed values, is scaled by the small
-// M - 1 instead of reaching m^{n+1} in full at every step (with float32 transforms it would
-// accumulate in m and, through v' = v exp(-alpha tau m), in v).
+// M - 1 instead of reaching f^{n+1} in full at every step (with float32 transforms it would
+// accumulate in m and w, and through v' = v exp(-alpha tau m) in v).
+// Implicit multiplier, c = tau (R + D |k|^2): M - 1 = lp / (1 + c) - 1 = (lp - 1 - c) / (1 + c).
 template <typename T>
-__device__ __forceinline__ T solve_multiplier(T c, T lp, bool change) {
-  const T r = (T)1 / ((T)1 + c);
-  return change ? (lp - (T)1 - c) * r : lp * r;
+__device__ __forceinline__ T solve_multiplier(T c, T lp) {
+  return (lp - (T)1 - c) / ((T)1 + c);
 }
 // the same for a tabulated multiplier M (exponential or aliased kernel)
 template <typename T>
-__device__ __forceinline__ T table_multiplier(T M, T lp, bool change) {
-  return change ? M * lp - (T)1 : M * lp;
+__device__ __forceinline__ T table_multiplier(T M, T lp) {
+  return M * lp - (T)1;
 }
 
 // ---- zfwd ---------------------------------------------------------------------------------
@@ -477,7 +478,7 @@ __device__ __forceinline__ void zfwd_body(SimC<T>& d, int lb, unsigned char* sme
       if (e < nel) {
         const int rr = e >> LG, iz = e & (N - 1);
         const T ms = mm[k] + dt * u[k];
-        if (!freeze_m) d.m[g0 + e] = ms;  // m*, to which the inverse pass adds the solve's change
+        if (!freeze_m) d.m[g0 + e] = ms;  // m*: the inverse pass adds the solve's change
         const T eta = (T)2 * u[k] / ((T)1 + u[k]);
         const T wsr = ww[k] + dt * (gam * vv[k] - eta * ww[k]);
         T vn = vv[k];
@@ -490,7 +491,9 @@ __device__ __forceinline__ void zfwd_body(SimC<T>& d, int lb, unsigned char* sme
           d.v[g0 + e] = vn;
         }
         if (isfinite((double)vn)) acc_min(acc, D_MIN_V, (double)vn); else acc.cnt[0] += 1;
-        d.ubar[g0 + e] = (T)0;
+        // w* goes into ubar's array, free until the particle pass deposits into it: the
+        // inverse pass adds it to the solve's change and clears the array
+        d.ubar[g0 + e] = wsr;
         A[rr * LS + iz] = cplx<T>{ms, wsr};
         T* vp = reinterpret_cast<T*>(&Vp[(rr >> 1) * LS + iz]);
         vp[rr & 1] = vv[k];
@@ -676,9 +679,9 @@ __device__ __forceinline__ void xpass_body(SimC<T>& d, int lb, unsigned char* sm
       if (implicit) {
         const int qx = lap_freq(kx, N), qy = lap_freq(ky, N);
         const T k2 = k0 * k0 * (T)(qx * qx + qy * qy + qz * qz);
-        mult = solve_multiplier(dt * (decay + D * k2), lp, f == 0);
+        mult = solve_multiplier(dt * (decay + D * k2), lp);
       } else {
-        mult = table_multiplier(e_dec * tab[kx] * tab[ky] * tab[kz], lp, f == 0);
+        mult = table_multiplier(e_dec * tab[kx] * tab[ky] * tab[kz], lp);
       }
       return cscale(val, mult * inv_n3);
     } else if (f == 2) {
@@ -734,9 +737,9 @@ __device__ __forceinline__ void col2d_body(SimC<T>& d, int lb, unsigned char* sm
       T mult;
       if (implicit) {
         const int q1 = lap_freq(k1, N), q2 = lap_freq(k2, N);
-        mult = solve_multiplier(dt * (decay + D * k0 * k0 * (T)(q1 * q1 + q2 * q2)), lp, f == 0);
+        mult = solve_multiplier(dt * (decay + D * k0 * k0 * (T)(q1 * q1 + q2 * q2)), lp);
       } else {
-        mult = table_multiplier(e_dec * tab[k1] * tab[k2], lp, f == 0);
+        mult = table_multiplier(e_dec * tab[k1] * tab[k2], lp);
       }
       return cscale(val, mult * inv_nd);
     } else if (f == 2) {
@@ -837,9 +840,9 @@ __device__ __forceinline__ void plane_body(SimC<T>& d, int lb, unsigned char* sm
       if (implicit) {
         const int qx = lap_freq(kx, N), qy = lap_freq(ky, N);
         const T k2 = k0 * k0 * (T)(qx * qx + qy * qy + qz * qz);
-        mult = solve_multiplier(dt * (decay + D * k2), lp, job == 0);
+        mult = solve_multiplier(dt * (decay + D * k2), lp);
       } else {
-        mult = table_multiplier(sep_z * tab[kx] * tab[ky], lp, job == 0);
+        mult = table_multiplier(sep_z * tab[kx] * tab[ky], lp);
       }
       return cscale(val, mult * inv_n3);
     } else if (job < 4) {
@@ -880,16 +883,17 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
   constexpr int ZB = ZBatch<T>::n;
   const int nel = B * N;
   const int64_t g0 = r0 * N;
-  // The old w and m* (with m frozen, m^n) of the first ZB elements per thread - all of them,
+  // w^n, m* (with m frozen, m^n) and w* of the first ZB elements per thread - all of them,
   // unless a block has more than ZB kThreads elements - are loaded first: they are needed
   // only after the transforms, so their loads overlap everything before.
-  T wold[ZB], mold[ZB];
+  T wold[ZB], mold[ZB], wst[ZB];
 #pragma unroll
   for (int k = 0; k < ZB; ++k) {
     const int e = threadIdx.x + k * kThreads;
     if (e < nel) {
       wold[k] = d.w[g0 + e];
       mold[k] = d.m[g0 + e];
+      wst[k] = d.ubar[g0 + e];
     }
   }
   TwiddleRegs<T, LG, kThreads> tr;
@@ -962,6 +966,7 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
         if (e < nel) {
           wold[k] = d.w[g0 + e];
           mold[k] = d.m[g0 + e];
+          wst[k] = d.ubar[g0 + e];
         }
       }
     }
@@ -975,12 +980,16 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
       const cplx<T> gg = GG[rr * LS + iz];
       const cplx<T> gzp = GZ[(rr >> 1) * LS + iz];
       d.g4[g] = vec4<T>{gg.x, gg.y, (rr & 1) ? gzp.y : gzp.x, wold[k]};
-      T mn = mold[k], wn = mw.y;  // mold: m* (or, with m frozen, m^n)
+      T mn = mold[k], wn = wold[k];  // mold: m* (or, with m frozen, m^n)
       if (!freeze_m) {
         mn += mw.x;
         d.m[g] = mn;
       }
-      if (!freeze_w) d.w[g] = wn; else wn = wold[k];
+      if (!freeze_w) {
+        wn = wst[k] + mw.y;
+        d.w[g] = wn;
+      }
+      d.ubar[g] = (T)0;  // cleared for the particle pass's deposit
       const double md = mn, wd = wn;
       if (isfinite(md) && isfinite(wd)) {
         acc.sum[2] += md;
