@@ -227,6 +227,11 @@ class GpuBackend:
         self.compute_stream = torch.cuda.Stream(device=device)
         self.retire_stream = torch.cuda.Stream(device=device)
         self._tls = threading.local()
+        # With graphs, a tick may capture a new batch graph; a capture on one thread has
+        # failed here while other threads initialised or read out simulations, so on that path
+        # the library calls of the three threads take turns.  (The allocation-free step
+        # captures nothing.)
+        self._lock = threading.Lock() if graphs else None
         self._admit = ThreadPoolExecutor(admit_workers, thread_name_prefix="sipf-admit")
         self._retire = ThreadPoolExecutor(retire_workers, thread_name_prefix="sipf-retire")
 
@@ -243,10 +248,15 @@ class GpuBackend:
         if st is None:
             st = self._tls.stream = torch.cuda.Stream(device=self.device)
         ic = req.ic
-        sim = self.sipf.Simulation(self._params(req), ic["X0"], ic["a0"], ic["v0"], ic["m0"],
-                                   ic["w0"], device=self.device, stream=st)
-        sim.set_stream(self.compute_stream)   # ordered on the device, no host wait
+        with self._locked():
+            sim = self.sipf.Simulation(self._params(req), ic["X0"], ic["a0"], ic["v0"],
+                                       ic["m0"], ic["w0"], device=self.device, stream=st)
+            sim.set_stream(self.compute_stream)   # ordered on the device, no host wait
         return sim
+
+    def _locked(self):
+        import contextlib
+        return self._lock if self._lock is not None else contextlib.nullcontext()
 
     def admit_start(self, req):
         return self._admit.submit(self._init, req)
@@ -256,7 +266,8 @@ class GpuBackend:
 
     def step(self, handles, nsteps):
         if self.graphs:
-            self.sipf.step_batch(handles, nsteps)
+            with self._lock:
+                self.sipf.step_batch(handles, nsteps)
         else:
             self.sipf.step_batch_noalloc(handles, nsteps)
 
@@ -270,16 +281,18 @@ class GpuBackend:
 
     def _finish(self, handle, keep_output):
         self.torch.cuda.set_device(self.device)
-        out = handle.fields(particles=keep_output)
-        t_done = self.clock()
-        handle.close()
-        handle.workspace = None
+        with self._locked():
+            out = handle.fields(particles=keep_output)
+            t_done = self.clock()
+            handle.close()
+            handle.workspace = None
         return t_done, (out if keep_output else dict(diag=out["diag"]))
 
     def retire_start(self, handle, keep_output):
         # the retirement stream waits (on the device) for the work queued so far, which ends
         # with this simulation's last tick; the copy then needs no wait on the compute stream
-        handle.set_stream(self.retire_stream)
+        with self._locked():
+            handle.set_stream(self.retire_stream)
         return self._retire.submit(self._finish, handle, keep_output)
 
     def retire_poll(self, fut):
