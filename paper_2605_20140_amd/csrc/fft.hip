@@ -76,8 +76,10 @@ void block_counts(const SimDev<T>& d, int c[K_COUNT]) {
   const int64_t pb = (d.P + kThreads - 1) / kThreads;
   c[K_PART] = d.max_chunks;  // bound on the number of (tile, chunk) items
   c[K_SCOUNT] = (int)((d.P + kBinBlock - 1) / kBinBlock);
-  c[K_SSCAN] = 1;
-  c[K_SSCATTER] = (int)pb;
+  // one scan block per segment of 16 kThreads tiles; the scatter also clears the tile counts
+  c[K_SSCAN] = (int)((d.ntiles + 16 * kThreads - 1) / (16 * kThreads));
+  const int64_t tb = (d.ntiles + kThreads - 1) / kThreads;
+  c[K_SSCATTER] = (int)(pb > tb ? pb : tb);
   const int64_t work = d.P > d.G ? d.P : d.G;
   int64_t db = (work + kThreads * 8 - 1) / (kThreads * 8);
   if (db < 1) db = 1;

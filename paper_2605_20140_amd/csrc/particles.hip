@@ -931,22 +931,50 @@ __global__ void __launch_bounds__(kThreads) k_bin_count(Batch<T> bt) {
 }
 
 // Exclusive scans of the tile counts (tile offsets) and of ceil(count / kChunk) (chunk
-// offsets); clears the counts for the next binning.  One block of kThreads per simulation.
+// offsets), and the chunk table.  One block per segment of kSegTiles tiles: a block first
+// sums the counts of every earlier segment (its carry), then scans its own segment.  The
+// counts are cleared for the next binning by the scatter, after every block has read them.
+constexpr int kScanSeg = 16;                    // tiles per thread in a segment
+constexpr int kSegTiles = kScanSeg * kThreads;  // tiles per segment (block)
+
+__device__ __forceinline__ uint32_t chunks_of(uint32_t c) { return (c + kChunk - 1) / kChunk; }
+
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_bin_scan(Batch<T> bt) {
   int lb;
   const int s = find_sim(bt, K_SSCAN, lb);
   SimC<T>& d = sim_view(bt, s);
   const int nt = d.ntiles;
-  // Segments of kScanSeg tiles per thread: the counts are loaded coalesced, all of a
-  // segment's loads in flight together, into LDS; each thread then scans kScanSeg
-  // consecutive tiles from there (a running carry links the segments).
-  constexpr int kScanSeg = 16;
-  constexpr int kSegTiles = kScanSeg * kThreads;
+  const int s0 = lb * kSegTiles;
   __shared__ uint32_t cnt[kSegTiles];
   __shared__ uint32_t pp[kThreads], pc[kThreads];
-  uint32_t carry_p = 0, carry_c = 0;  // tiles and chunks before the segment (uniform)
-  for (int s0 = 0; s0 < nt; s0 += kSegTiles) {
+  // carry: tiles and chunks of the segments before this one (kScanSeg loads per thread in
+  // flight together per earlier segment)
+  uint32_t ap = 0, ac = 0;
+  for (int e0 = 0; e0 < s0; e0 += kSegTiles) {
+    uint32_t v[kScanSeg];
+#pragma unroll
+    for (int j = 0; j < kScanSeg; ++j) v[j] = d.tcount[e0 + (int)threadIdx.x + j * kThreads];
+#pragma unroll
+    for (int j = 0; j < kScanSeg; ++j) {
+      ap += v[j];
+      ac += chunks_of(v[j]);
+    }
+  }
+  pp[threadIdx.x] = ap;
+  pc[threadIdx.x] = ac;
+  __syncthreads();
+  for (int off = kThreads / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      pp[threadIdx.x] += pp[threadIdx.x + off];
+      pc[threadIdx.x] += pc[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  const uint32_t carry_p = pp[0], carry_c = pc[0];
+  __syncthreads();
+  // this segment: counts into LDS (coalesced), kScanSeg consecutive tiles per thread
+  {
     uint32_t v[kScanSeg];
 #pragma unroll
     for (int j = 0; j < kScanSeg; ++j) {
@@ -955,54 +983,50 @@ __global__ void __launch_bounds__(kThreads) k_bin_scan(Batch<T> bt) {
     }
 #pragma unroll
     for (int j = 0; j < kScanSeg; ++j) cnt[threadIdx.x + j * kThreads] = v[j];
-    __syncthreads();
-    const int b0 = (int)threadIdx.x * kScanSeg;
-    uint32_t sp = 0, sc = 0;
-#pragma unroll
-    for (int j = 0; j < kScanSeg; ++j) {
-      const uint32_t c = cnt[b0 + j];
-      sp += c;
-      sc += (c + kChunk - 1) / kChunk;
-    }
-    pp[threadIdx.x] = sp;
-    pc[threadIdx.x] = sc;
-    __syncthreads();
-    // inclusive Hillis-Steele scan of the per-thread sums
-    for (int off = 1; off < kThreads; off <<= 1) {
-      uint32_t ap = 0, ac = 0;
-      if ((int)threadIdx.x >= off) {
-        ap = pp[threadIdx.x - off];
-        ac = pc[threadIdx.x - off];
-      }
-      __syncthreads();
-      pp[threadIdx.x] += ap;
-      pc[threadIdx.x] += ac;
-      __syncthreads();
-    }
-    uint32_t rp = carry_p + (threadIdx.x ? pp[threadIdx.x - 1] : 0u);
-    uint32_t rc = carry_c + (threadIdx.x ? pc[threadIdx.x - 1] : 0u);
-    for (int j = 0; j < kScanSeg; ++j) {
-      const int t = s0 + b0 + j;
-      if (t >= nt) break;
-      const uint32_t c = cnt[b0 + j];
-      const uint32_t nch = (c + kChunk - 1) / kChunk;
-      d.toff[t] = rp;
-      d.coff[t] = rc;
-      for (uint32_t k = 0; k < nch; ++k) {
-        const uint32_t cs = rp + k * kChunk;
-        d.cinfo[rc + k] = uint4{cs, cs + kChunk < rp + c ? cs + kChunk : rp + c, (uint32_t)t, 0u};
-      }
-      rp += c;
-      rc += nch;
-      d.tcount[t] = 0;
-    }
-    carry_p += pp[kThreads - 1];
-    carry_c += pc[kThreads - 1];
-    __syncthreads();  // pp, pc and cnt are rewritten by the next segment
   }
-  if (threadIdx.x == 0) {
-    d.toff[nt] = carry_p;
-    d.coff[nt] = carry_c;
+  __syncthreads();
+  const int b0 = (int)threadIdx.x * kScanSeg;
+  uint32_t sp = 0, sc = 0;
+#pragma unroll
+  for (int j = 0; j < kScanSeg; ++j) {
+    const uint32_t c = cnt[b0 + j];
+    sp += c;
+    sc += chunks_of(c);
+  }
+  pp[threadIdx.x] = sp;
+  pc[threadIdx.x] = sc;
+  __syncthreads();
+  // inclusive Hillis-Steele scan of the per-thread sums
+  for (int off = 1; off < kThreads; off <<= 1) {
+    uint32_t xp = 0, xc = 0;
+    if ((int)threadIdx.x >= off) {
+      xp = pp[threadIdx.x - off];
+      xc = pc[threadIdx.x - off];
+    }
+    __syncthreads();
+    pp[threadIdx.x] += xp;
+    pc[threadIdx.x] += xc;
+    __syncthreads();
+  }
+  uint32_t rp = carry_p + (threadIdx.x ? pp[threadIdx.x - 1] : 0u);
+  uint32_t rc = carry_c + (threadIdx.x ? pc[threadIdx.x - 1] : 0u);
+  for (int j = 0; j < kScanSeg; ++j) {
+    const int t = s0 + b0 + j;
+    if (t >= nt) break;
+    const uint32_t c = cnt[b0 + j];
+    const uint32_t nch = chunks_of(c);
+    d.toff[t] = rp;
+    d.coff[t] = rc;
+    for (uint32_t k = 0; k < nch; ++k) {
+      const uint32_t cs = rp + k * kChunk;
+      d.cinfo[rc + k] = uint4{cs, cs + kChunk < rp + c ? cs + kChunk : rp + c, (uint32_t)t, 0u};
+    }
+    rp += c;
+    rc += nch;
+  }
+  if (s0 + kSegTiles >= nt && threadIdx.x == 0) {  // the last segment closes the tables
+    d.toff[nt] = carry_p + pp[kThreads - 1];
+    d.coff[nt] = carry_c + pc[kThreads - 1];
   }
 }
 
@@ -1012,6 +1036,8 @@ __global__ void __launch_bounds__(kThreads) k_bin_scatter(Batch<T> bt) {
   const int s = find_sim<kFieldRun>(bt, K_SSCATTER, lb);
   SimC<T>& d = sim_view(bt, s);
   const int64_t i = (int64_t)lb * kThreads + threadIdx.x;
+  // tile counts cleared for the next binning (the scan has read them all)
+  if (i < d.ntiles) d.tcount[i] = 0;
   if (i >= d.P) return;
   const uint32_t dst = d.toff[d.key[2 * i]] + d.key[2 * i + 1];
   d.xs[1][dst] = d.xs[0][i];
