@@ -137,11 +137,11 @@ Layout make_layout(const sipf_params& p) {
   L.coff = take((ntiles + 1) * 4);
   L.cinfo = take(((P + kChunk - 1) / kChunk + ntiles) * 16);
   L.key = take(P * 8);
-  L.ubar = take(G * s);
+  L.ubar = take(2 * G * s);    // two buffers, by step parity
   L.v = take(G * s);
   L.m = take(G * s);
   L.w = take(G * s);
-  L.g4 = take(G * 4 * s);
+  L.g4 = take(2 * G * 4 * s);  // two buffers, by step parity
   const size_t spec = H * (G / N) * 2 * s;  // half spectrum: (N/2+1) N^(dim-1) complex
   L.SM = take(spec);
   L.SW = take(spec);
@@ -218,38 +218,46 @@ struct FftGroup {
   int lg;
 };
 
+// the field passes (mode 0: a step's; kGradOnly: the gather array of the current state)
 template <typename T>
-void enqueue_fft(const FftGroup<T>* groups, int ng, hipStream_t st) {
-  for (int i = 0; i < ng; ++i) launch_zfwd<T>(groups[i].b, groups[i].tot[K_ZFWD], groups[i].lg, st);
-  for (int i = 0; i < ng; ++i) launch_yfwd<T>(groups[i].b, groups[i].tot[K_YFWD], groups[i].lg, st);
+void enqueue_fft(const FftGroup<T>* groups, int ng, hipStream_t st, int mode) {
   for (int i = 0; i < ng; ++i)
-    launch_xpass<T>(groups[i].b, groups[i].tot[K_XPASS], groups[i].lg, st);
+    launch_zfwd<T>(groups[i].b, groups[i].tot[K_ZFWD], groups[i].lg, st, mode);
+  for (int i = 0; i < ng; ++i)
+    launch_yfwd<T>(groups[i].b, groups[i].tot[K_YFWD], groups[i].lg, st, mode);
+  for (int i = 0; i < ng; ++i)
+    launch_xpass<T>(groups[i].b, groups[i].tot[K_XPASS], groups[i].lg, st, mode);
   for (int i = 0; i < ng; ++i)
     launch_plane<T>(groups[i].b, groups[i].tot[K_PLANE], groups[i].lg, st, 0);
-  for (int i = 0; i < ng; ++i) launch_yinv<T>(groups[i].b, groups[i].tot[K_YINV], groups[i].lg, st);
-  for (int i = 0; i < ng; ++i) launch_zinv<T>(groups[i].b, groups[i].tot[K_ZINV], groups[i].lg, st);
+  for (int i = 0; i < ng; ++i)
+    launch_yinv<T>(groups[i].b, groups[i].tot[K_YINV], groups[i].lg, st, mode);
+  for (int i = 0; i < ng; ++i)
+    launch_zinv<T>(groups[i].b, groups[i].tot[K_ZINV], groups[i].lg, st, mode);
 }
 
 // One step; with bin != 0 the particles are first binned into set 1 and the particle pass
-// reads set 1 (and writes set 0).
+// reads set 1 (and writes set 0).  The field passes of step n and its particle pass share no
+// buffer: the particle pass gathers from the array the previous step's field passes (or the
+// initialisation) formed and deposits into the other ubar buffer, while the field passes read
+// ubar^n and form the next gather array.  With a fork the two halves run side by side: the
+// field passes on the second stream, the binning (when due) and the particle pass on the
+// first; the finalize kernel (diagnostics, step index) waits for both.  Without one they run
+// in sequence on st.
 template <typename T>
 void enqueue_step(const Batch<T>& b, const int* tot, int nsims, const FftGroup<T>* groups,
                   int ngroups, int bin, int order, int dim, hipStream_t st,
                   const StepFork* fk) {
-  // The binning kernels touch only the particles and their tables, the field passes only
-  // grids and spectra: on binning steps the binning runs on a second stream beside the field
-  // passes (filling the CUs they leave idle), and the particle pass waits for both.
-  if (bin && fk) {
+  if (fk) {
     (void)hipEventRecord(fk->fork, st);
     (void)hipStreamWaitEvent(fk->aux, fk->fork, 0);
-    launch_binning<T>(b, tot, nsims, dim, fk->aux);
+    enqueue_fft<T>(groups, ngroups, fk->aux, 0);
     (void)hipEventRecord(fk->join, fk->aux);
-  } else if (bin) {
-    launch_binning<T>(b, tot, nsims, dim, st);
+  } else {
+    enqueue_fft<T>(groups, ngroups, st, 0);
   }
-  enqueue_fft<T>(groups, ngroups, st);
-  if (bin && fk) (void)hipStreamWaitEvent(st, fk->join, 0);
+  if (bin) launch_binning<T>(b, tot, nsims, dim, st);
   launch_particles<T>(b, tot[K_PART], bin ? 1 : 0, 0, order, dim, st);
+  if (fk) (void)hipStreamWaitEvent(st, fk->join, 0);
   launch_finalize<T>(b, nsims, st);
 }
 
@@ -365,11 +373,13 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   d.cinfo = reinterpret_cast<uint4*>(ws + L.cinfo);
   d.max_chunks = (int)((P + kChunk - 1) / kChunk + d.ntiles);
   d.key = reinterpret_cast<uint32_t*>(ws + L.key);
-  d.ubar = reinterpret_cast<T*>(ws + L.ubar);
+  for (int k = 0; k < 2; ++k) {
+    d.ubar[k] = reinterpret_cast<T*>(ws + L.ubar) + k * G;
+    d.g4[k] = reinterpret_cast<vec4<T>*>(ws + L.g4) + k * G;
+  }
   d.v = reinterpret_cast<T*>(ws + L.v);
   d.m = reinterpret_cast<T*>(ws + L.m);
   d.w = reinterpret_cast<T*>(ws + L.w);
-  d.g4 = reinterpret_cast<vec4<T>*>(ws + L.g4);
   d.SM = reinterpret_cast<cplx<T>*>(ws + L.SM);
   d.SW = reinterpret_cast<cplx<T>*>(ws + L.SW);
   d.SV = reinterpret_cast<cplx<T>*>(ws + L.SV);
@@ -454,8 +464,8 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   HIPCHK(hipMemcpyAsync(d.w, hw.data(), G * sizeof(T), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(d.tw, htw.data(), (N / 2) * sizeof(cplx<T>), hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(d.mtab, hmt.data(), 3 * N * sizeof(T), hipMemcpyHostToDevice, st));
-  HIPCHK(hipMemsetAsync(d.ubar, 0, G * sizeof(T), st));
-  HIPCHK(hipMemsetAsync(d.g4, 0, G * sizeof(vec4<T>), st));
+  HIPCHK(hipMemsetAsync(d.ubar[0], 0, 2 * G * sizeof(T), st));        // both buffers
+  HIPCHK(hipMemsetAsync(d.g4[0], 0, 2 * G * sizeof(vec4<T>), st));    // both buffers
   HIPCHK(hipMemsetAsync(d.tcount, 0, (size_t)d.ntiles * sizeof(uint32_t), st));
   // 2D: no y derivative spectrum is ever formed; the inverse row pass reads zeros from it
   if (dim == 2)
@@ -474,6 +484,9 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   }
   sim->resort_every = p.resort_every > 0 ? p.resort_every : default_resort(p);
   sim->since_bin = 0;
+  // the gather array of the first step: (grad v^0, w^0)
+  const auto groups = single_groups<T>(sim, b);
+  enqueue_fft<T>(groups.data(), (int)groups.size(), st, kGradOnly);
   launch_particles<T>(b, sim->counts[K_PART], 0, 1, p.deposit_order, dim, st);  // ubar^0
   launch_diag_clear<T>(b, 1, st);
   launch_diag_init<T>(b, sim->counts[K_DIAG], 1, st);
@@ -501,7 +514,7 @@ int capture_t(sipf_sim* sim) {
   const auto groups = single_groups<T>(sim, b);
   HIPCHK(hipStreamBeginCapture(sim->cap, hipStreamCaptureModeThreadLocal));
   enqueue_step<T>(b, sim->counts, 1, groups.data(), (int)groups.size(), 0, p.deposit_order,
-                  dim, sim->cap, nullptr);
+                  dim, sim->cap, &sim->fork);
   HIPCHK(hipStreamEndCapture(sim->cap, &sim->graph));
   HIPCHK(hipGetLastError());
   HIPCHK(hipGraphInstantiate(&sim->exec, sim->graph, nullptr, nullptr, 0));
@@ -631,14 +644,18 @@ int aux_t(sipf_sim* sim, double* u_bar, double* grad_v) {
   const size_t G = grid_nodes(p);
   if (sim->last_stream) HIPCHK(hipStreamSynchronize(sim->last_stream));
   HIPCHK(hipStreamSynchronize(sim->stream));
+  uint64_t n = 0;  // the state's step index selects the buffers
+  HIPCHK(hipMemcpy(&n, d.step, sizeof(n), hipMemcpyDeviceToHost));
   if (u_bar) {
     std::vector<T> buf(G);
-    HIPCHK(hipMemcpy(buf.data(), d.ubar, G * sizeof(T), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(buf.data(), d.ubar[n & 1], G * sizeof(T), hipMemcpyDeviceToHost));
     for (size_t i = 0; i < G; ++i) u_bar[i] = (double)buf[i];
   }
   if (grad_v) {
+    // the gather array of the last step (step n - 1); zeros before the first step
     std::vector<vec4<T>> buf(G);
-    HIPCHK(hipMemcpy(buf.data(), d.g4, G * sizeof(vec4<T>), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(buf.data(), d.g4[(n - 1) & 1], G * sizeof(vec4<T>),
+                     hipMemcpyDeviceToHost));
     for (size_t i = 0; i < G; ++i) {
       grad_v[i] = (double)buf[i].x;
       if (dim_of(p) == 3) {
@@ -857,13 +874,15 @@ constexpr int kNoAllocMaxSims = 64;
 constexpr size_t kNoAllocBytes = 128 * 1024;
 static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
-// Per device: the array's device address, and a host image of the table last written to it
-// (a call whose table is unchanged writes nothing).  Both are set up by sipf_init, the first
-// time a simulation is created on the device, with that device current.
+// Per device: the array's device address, a host image of the table last written to it (a
+// call whose table is unchanged writes nothing), and the stream and events on which a step's
+// field passes run beside its particle pass.  All are set up by sipf_init, the first time a
+// simulation is created on the device, with that device current.
 struct DevScratch {
   void* ptr = nullptr;
   unsigned char* last = nullptr;  // kNoAllocBytes
   size_t last_bytes = 0;          // 0: nothing written yet
+  StepFork fork;                  // second stream and events of the step's two halves
 };
 std::mutex g_scratch_mu;
 DevScratch g_scratch[64];
@@ -878,6 +897,11 @@ int scratch_setup(int dev, DevScratch** out) {
     if (e != hipSuccess || !p)
       return fail(SIPF_EHIP, std::string("hipGetSymbolAddress(scratch): ") +
                                  hipGetErrorString(e));
+    const hipError_t ef = create_fork(d.fork);
+    if (ef != hipSuccess) {
+      destroy_fork(d.fork);
+      return fail(SIPF_EHIP, std::string("step fork: ") + hipGetErrorString(ef));
+    }
     d.last = new unsigned char[kNoAllocBytes];
     d.ptr = p;
   }
@@ -984,7 +1008,8 @@ int step_batch_noalloc_t(sipf_sim* const* sims, int nsims, int nsteps) {
   for (int s = 0; s < nsteps; ++s) {
     int bin = 0;
     for (int i = 0; i < nsims; ++i) bin |= sims[i]->since_bin >= sims[i]->resort_every;
-    enqueue_step<T>(b, tot, nsims, groups, ng, bin, sims[0]->prm.deposit_order, 3, st, nullptr);
+    enqueue_step<T>(b, tot, nsims, groups, ng, bin, sims[0]->prm.deposit_order, 3, st,
+                    &ds->fork);
     for (int i = 0; i < nsims; ++i) sims[i]->since_bin = bin ? 1 : sims[i]->since_bin + 1;
   }
   HIPCHK(hipGetLastError());
@@ -1006,16 +1031,16 @@ int step_timed_t(sipf_sim* sim, int nsteps, float* stage_ms) {
     (void)hipEventRecord(ev[SIPF_NUM_STAGES], st);
     if (bin) launch_binning<T>(b, c, 1, dim_of(sim->prm), st);
     (void)hipEventRecord(ev[0], st);
-    launch_zfwd<T>(b, c[K_ZFWD], lg, st);
+    launch_zfwd<T>(b, c[K_ZFWD], lg, st, 0);
     (void)hipEventRecord(ev[1], st);
-    launch_yfwd<T>(b, c[K_YFWD], lg, st);
+    launch_yfwd<T>(b, c[K_YFWD], lg, st, 0);
     (void)hipEventRecord(ev[2], st);
-    launch_xpass<T>(b, c[K_XPASS], lg, st);
+    launch_xpass<T>(b, c[K_XPASS], lg, st, 0);
     launch_plane<T>(b, c[K_PLANE], lg, st, 0);
     (void)hipEventRecord(ev[3], st);
-    launch_yinv<T>(b, c[K_YINV], lg, st);
+    launch_yinv<T>(b, c[K_YINV], lg, st, 0);
     (void)hipEventRecord(ev[4], st);
-    launch_zinv<T>(b, c[K_ZINV], lg, st);
+    launch_zinv<T>(b, c[K_ZINV], lg, st, 0);
     (void)hipEventRecord(ev[5], st);
     launch_particles<T>(b, c[K_PART], bin, 0, sim->prm.deposit_order, dim_of(sim->prm), st);
     (void)hipEventRecord(ev[6], st);
@@ -1056,10 +1081,12 @@ int resample_t(sipf_sim* sim, sipf_resample_info* info) {
   hipStream_t st = sim->stream;
   unsigned long long* rs = reinterpret_cast<unsigned long long*>(sim->ws + sim->lay.rs);
   unsigned long long head[RS_BLOCKS];
+  uint64_t n = 0;  // the state's step index: its ubar buffer is ubar[n & 1]
   HIPCHK(hipMemsetAsync(rs, 0, sizeof(head), st));
   launch_resample_stats<T>(d, rs, st);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(head, rs, sizeof(head), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(&n, d.step, sizeof(n), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   // on a rejected input the state is unchanged (only set 1, free between steps, was written)
   if (head[RS_FLAGS] & RS_BAD_VALUE)
@@ -1080,7 +1107,7 @@ int resample_t(sipf_sim* sim, sipf_resample_info* info) {
   HIPCHK(hipMemcpyAsync(d.as[0], d.as[1], P * sizeof(double), hipMemcpyDeviceToDevice, st));
   HIPCHK(hipMemcpyAsync(d.ids[0], d.ids[1], P * sizeof(uint32_t), hipMemcpyDeviceToDevice, st));
   const size_t G = grid_nodes(p);
-  HIPCHK(hipMemsetAsync(d.ubar, 0, G * sizeof(T), st));
+  HIPCHK(hipMemsetAsync(d.ubar[n & 1], 0, G * sizeof(T), st));
   launch_particles<T>(b, sim->counts[K_PART], 0, 1, p.deposit_order, dim, st);
   launch_diag_clear<T>(b, 1, st);
   launch_diag_init<T>(b, sim->counts[K_DIAG], 1, st);

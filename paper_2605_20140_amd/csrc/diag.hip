@@ -94,9 +94,10 @@ __global__ void __launch_bounds__(kThreads) k_diag_full(Batch<T> bt, int state, 
     }
   }
   const int64_t G = d.G;
+  const T* const ub = d.ubar[(uint32_t)(*d.step) & 1u];  // the state's deposit
   for (int64_t i = (int64_t)lb * kThreads + threadIdx.x; i < G; i += stride) {
     if (u) {
-      const double uu = d.ubar[i];
+      const double uu = ub[i];
       if (!isfinite(uu)) {
         a.cnt[0] += 1;
       } else {

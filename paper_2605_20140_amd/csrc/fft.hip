@@ -10,8 +10,8 @@
 //
 // Passes per step (each one kernel):
 //   zfwd : reaction (eq. g_hat_phy with S of eq. g_t) on (ubar, m, v, w) at time n, writes
-//          v^{n+1}, m* (into m) and w* (into ubar's array); real z transforms of m*, w*
-//          (packed as m* + i w*) and of v^n (two rows packed) -> SM, SW, SV.
+//          v^{n+1}, m* (into m) and w* (into ubar^n's array); real z transforms of m*, w*
+//          (packed as m* + i w*) and of v^{n+1} (two rows packed) -> SM, SW, SV.
 //   yfwd : y transforms of SM, SW, SV (in place).
 //   xpass: x transforms, the diagonal multipliers of eq. k_q_tilde_update in change form
 //          (m: decay beta, diffusion D_m; w: decay 1, diffusion D_w) and the x-derivative
@@ -27,7 +27,12 @@
 //   zinv : forms the z-derivative spectrum i (2 pi/L) q_3 SVg, inverse real z transforms of
 //          (SM, SW), (SGx, SGy) and of row pairs of the z derivative; writes m^{n+1} =
 //          m* + change, w^{n+1} = w* + change (the solves in change form, below), the gather
-//          array g4 = (d1 v^n, d2 v^n, d3 v^n, w^n), and clears ubar for the deposit.
+//          array of the next step g4 = (d1 v^{n+1}, d2 v^{n+1}, d3 v^{n+1}, w^{n+1}), and
+//          clears ubar^n's array for the next step's deposit.
+// The particle pass of step n gathers (grad v^n, w^n) from the array the previous step's
+// passes formed (at initialisation, these passes run once in gradient-only mode on v^0, w^0),
+// so the field passes and the particle pass of one step are independent and run side by
+// side; the gather array and ubar are double-buffered by the parity of n.
 //
 // Line transforms (length N = N1 N2, held in LDS): four-step.  Forward: N1 transforms of
 // length N2 over stride-N1 subsequences, twiddles W_N^{n1 k2}, then N2 transforms of length N1
@@ -440,7 +445,7 @@ __device__ __forceinline__ T table_multiplier(T M, T lp) {
 
 // ---- zfwd ---------------------------------------------------------------------------------
 template <typename T, int LG>
-__device__ __forceinline__ void zfwd_body(SimC<T>& d, int lb, unsigned char* smem) {
+__device__ __forceinline__ void zfwd_body(SimC<T>& d, int lb, unsigned char* smem, int mode) {
   constexpr int N = 1 << LG;
   const int B = d.rows_per_blk;
   const int64_t N2 = d.nrows;  // rows per k3 plane of the spectra (N^2; N in 2D)
@@ -455,6 +460,8 @@ __device__ __forceinline__ void zfwd_body(SimC<T>& d, int lb, unsigned char* sme
   const bool freeze_v = d.flags & SIPF_FLAG_FREEZE_V;
   const bool freeze_m = d.flags & SIPF_FLAG_FREEZE_M;
   const bool impl_v = d.flags & SIPF_FLAG_IMPLICIT_V;
+  const bool grad_only = mode == kGradOnly;
+  T* const ub = d.ubar[(uint32_t)(*d.step) & 1u];  // ubar^n
   Acc acc;
   acc_init(acc);
   // ZBatch elements per thread have their loads in flight together (the stores to v and ubar
@@ -468,16 +475,22 @@ __device__ __forceinline__ void zfwd_body(SimC<T>& d, int lb, unsigned char* sme
     for (int k = 0; k < ZB; ++k) {
       const int e = e0 + k * kThreads;
       if (e < nel) {
-        u[k] = d.ubar[g0 + e];
-        mm[k] = d.m[g0 + e];
         vv[k] = d.v[g0 + e];
-        ww[k] = d.w[g0 + e];
+        if (!grad_only) {
+          u[k] = ub[g0 + e];
+          mm[k] = d.m[g0 + e];
+          ww[k] = d.w[g0 + e];
+        }
       }
     }
 #pragma unroll
     for (int k = 0; k < ZB; ++k) {
       const int e = e0 + k * kThreads;
-      if (e < nel) {
+      if (e < nel && grad_only) {  // v^n itself; the m and w lines are not used
+        const int rr = e >> LG, iz = e & (N - 1);
+        A[rr * LS + iz] = cplx<T>{(T)0, (T)0};
+        reinterpret_cast<T*>(&Vp[(rr >> 1) * LS + iz])[rr & 1] = vv[k];
+      } else if (e < nel) {
         const int rr = e >> LG, iz = e & (N - 1);
         const T ms = mm[k] + dt * u[k];
         if (!freeze_m) d.m[g0 + e] = ms;  // m*: the inverse pass adds the solve's change
@@ -493,12 +506,13 @@ __device__ __forceinline__ void zfwd_body(SimC<T>& d, int lb, unsigned char* sme
           d.v[g0 + e] = vn;
         }
         if (isfinite((double)vn)) acc_min(acc, D_MIN_V, (double)vn); else acc.cnt[0] += 1;
-        // w* goes into ubar's array, free until the particle pass deposits into it: the
-        // inverse pass adds it to the solve's change and clears the array
-        d.ubar[g0 + e] = wsr;
+        // w* goes into ubar^n's array, which this step needs no more: the inverse pass adds
+        // it to the solve's change and clears the array for the next step's deposit
+        ub[g0 + e] = wsr;
         A[rr * LS + iz] = cplx<T>{ms, wsr};
+        // v^{n+1}: its gradient is the next step's gather array
         T* vp = reinterpret_cast<T*>(&Vp[(rr >> 1) * LS + iz]);
-        vp[rr & 1] = vv[k];
+        vp[rr & 1] = vn;
       }
     }
   }
@@ -525,15 +539,15 @@ __device__ __forceinline__ void zfwd_body(SimC<T>& d, int lb, unsigned char* sme
     }
     d.SV[o] = Vv;
   }
-  acc_flush(acc, diag_stripe(d));
+  if (!grad_only) acc_flush(acc, diag_stripe(d));
 }
 
 template <typename T, int LG>
-__global__ void __launch_bounds__(kThreads) k_zfwd(Batch<T> bt) {
+__global__ void __launch_bounds__(kThreads) k_zfwd(Batch<T> bt, int mode) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
   const int s = find_sim<kFieldRun>(bt, K_ZFWD, lb);
-  zfwd_body<T, LG>(sim_view(bt, s), lb, smem_raw);
+  zfwd_body<T, LG>(sim_view(bt, s), lb, smem_raw, mode);
 }
 
 // ---- y passes -------------------------------------------------------------------------------
@@ -558,7 +572,7 @@ __device__ __forceinline__ void yfwd_body(SimC<T>& d, int lb, unsigned char* sme
 }
 
 template <typename T, int LG>
-__global__ void __launch_bounds__(kThreads) k_yfwd(Batch<T> bt) {
+__global__ void __launch_bounds__(kThreads) k_yfwd(Batch<T> bt, int /*mode*/) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
   const int s = find_sim<kFieldRun>(bt, K_YFWD, lb);
@@ -613,7 +627,7 @@ __device__ __forceinline__ void yinv_body(SimC<T>& d, int lb, unsigned char* sme
 }
 
 template <typename T, int LG>
-__global__ void __launch_bounds__(kThreads) k_yinv(Batch<T> bt) {
+__global__ void __launch_bounds__(kThreads) k_yinv(Batch<T> bt, int /*mode*/) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
   const int s = find_sim<kFieldRun>(bt, K_YINV, lb);
@@ -756,7 +770,7 @@ __device__ __forceinline__ void col2d_body(SimC<T>& d, int lb, unsigned char* sm
 }
 
 template <typename T, int LG>
-__global__ void __launch_bounds__(kThreads) k_xpass(Batch<T> bt) {
+__global__ void __launch_bounds__(kThreads) k_xpass(Batch<T> bt, int /*mode*/) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
   const int s = find_sim<kFieldRun>(bt, K_XPASS, lb);
@@ -869,7 +883,7 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane(Batch<T> bt) {
 
 // ---- zinv ---------------------------------------------------------------------------------
 template <typename T, int LG>
-__device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* smem) {
+__device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* smem, int mode) {
   constexpr int N = 1 << LG;
   const int B = d.rows_zinv;
   const int64_t N2 = d.nrows;  // rows per k3 plane of the spectra (N^2; N in 2D)
@@ -882,6 +896,11 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
   cplx<T>* tw = GZ + Bh * LS;
   const bool freeze_m = d.flags & SIPF_FLAG_FREEZE_M;
   const bool freeze_w = d.flags & SIPF_FLAG_FREEZE_W;
+  const bool grad_only = mode == kGradOnly;
+  const uint32_t par = (uint32_t)(*d.step) & 1u;
+  T* const ub = d.ubar[par];  // holds w* (see zfwd)
+  // the gather array of step n + 1, or with grad_only that of step n
+  vec4<T>* const gout = d.g4[grad_only ? par : par ^ 1u];
   constexpr int ZB = ZBatch<T>::n;
   const int nel = B * N;
   const int64_t g0 = r0 * N;
@@ -894,8 +913,10 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
     const int e = threadIdx.x + k * kThreads;
     if (e < nel) {
       wold[k] = d.w[g0 + e];
-      mold[k] = d.m[g0 + e];
-      wst[k] = d.ubar[g0 + e];
+      if (!grad_only) {
+        mold[k] = d.m[g0 + e];
+        wst[k] = ub[g0 + e];
+      }
     }
   }
   TwiddleRegs<T, LG, kThreads> tr;
@@ -967,8 +988,10 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
         const int e = e0 + k * kThreads;
         if (e < nel) {
           wold[k] = d.w[g0 + e];
-          mold[k] = d.m[g0 + e];
-          wst[k] = d.ubar[g0 + e];
+          if (!grad_only) {
+            mold[k] = d.m[g0 + e];
+            wst[k] = ub[g0 + e];
+          }
         }
       }
     }
@@ -981,7 +1004,11 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
       const cplx<T> mw = MW[rr * LS + iz];
       const cplx<T> gg = GG[rr * LS + iz];
       const cplx<T> gzp = GZ[(rr >> 1) * LS + iz];
-      d.g4[g] = vec4<T>{gg.x, gg.y, (rr & 1) ? gzp.y : gzp.x, wold[k]};
+      const T gzv = (rr & 1) ? gzp.y : gzp.x;
+      if (grad_only) {
+        gout[g] = vec4<T>{gg.x, gg.y, gzv, wold[k]};
+        continue;
+      }
       T mn = mold[k], wn = wold[k];  // mold: m* (or, with m frozen, m^n)
       if (!freeze_m) {
         mn += mw.x;
@@ -991,7 +1018,8 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
         wn = wst[k] + mw.y;
         d.w[g] = wn;
       }
-      d.ubar[g] = (T)0;  // cleared for the particle pass's deposit
+      gout[g] = vec4<T>{gg.x, gg.y, gzv, wn};  // (grad v^{n+1}, w^{n+1})
+      ub[g] = (T)0;  // cleared for the deposit of the next step's particle pass
       const double md = mn, wd = wn;
       if (isfinite(md) && isfinite(wd)) {
         acc.sum[2] += md;
@@ -1006,15 +1034,15 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
       }
     }
   }
-  acc_flush(acc, diag_stripe(d));
+  if (!grad_only) acc_flush(acc, diag_stripe(d));
 }
 
 template <typename T, int LG>
-__global__ void __launch_bounds__(kThreads) k_zinv(Batch<T> bt) {
+__global__ void __launch_bounds__(kThreads) k_zinv(Batch<T> bt, int mode) {
   extern __shared__ __align__(16) unsigned char smem_raw[];
   int lb;
   const int s = find_sim<kFieldRun>(bt, K_ZINV, lb);
-  zinv_body<T, LG>(sim_view(bt, s), lb, smem_raw);
+  zinv_body<T, LG>(sim_view(bt, s), lb, smem_raw, mode);
 }
 
 // ---- LDS sizes and launchers ----------------------------------------------------------------
@@ -1068,11 +1096,11 @@ template void configure_fft<float>(int);
 #define SIPF_LG_CASE(KER, KIND, L)                                                          \
   case L:                                                                                   \
     hipLaunchKernelGGL((k_##KER<T, L>), dim3(nblk), dim3(kThreads),                        \
-                       fft_lds_bytes<T>(KIND, L), st, b);                                   \
+                       fft_lds_bytes<T>(KIND, L), st, b, mode);                             \
     break;
 #define SIPF_LAUNCH(KER, KIND)                                                     \
   template <typename T>                                                            \
-  void launch_##KER(const Batch<T>& b, int nblk, int lg, hipStream_t st) {         \
+  void launch_##KER(const Batch<T>& b, int nblk, int lg, hipStream_t st, int mode) { \
     if (nblk <= 0) return;                                                         \
     switch (lg) {                                                                  \
       SIPF_LG_CASE(KER, KIND, 2)                                                   \
@@ -1087,8 +1115,8 @@ template void configure_fft<float>(int);
       default: break;                                                              \
     }                                                                              \
   }                                                                                \
-  template void launch_##KER<double>(const Batch<double>&, int, int, hipStream_t); \
-  template void launch_##KER<float>(const Batch<float>&, int, int, hipStream_t);
+  template void launch_##KER<double>(const Batch<double>&, int, int, hipStream_t, int); \
+  template void launch_##KER<float>(const Batch<float>&, int, int, hipStream_t, int);
 
 SIPF_LAUNCH(zfwd, K_ZFWD)
 SIPF_LAUNCH(yfwd, K_YFWD)

@@ -372,7 +372,11 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll
   for (int j = 0; j < 3; ++j) rgg.o[j] = rg.o[j] + (Reg<ORDER>::M - Reg<2>::M);
   const bool use_region = d.use_region;
-  T* const ubar = d.ubar;
+  // buffers of step n: gather array g4[n & 1]; the deposit goes to ubar[(n + 1) & 1] (the
+  // state's own ubar[n & 1] when only depositing)
+  const uint32_t n = (uint32_t)(*d.step);
+  const vec4<T>* const g4 = d.g4[n & 1u];
+  T* const ubar = d.ubar[deposit_only ? (n & 1u) : ((n & 1u) ^ 1u)];
 
   const T* xi = d.xs[src_set] + start;
   const T* yi = d.ys[src_set] + start;
@@ -414,7 +418,7 @@ __global__ void __launch_bounds__(kThreads)
           const int e = threadIdx.x + (k0 + k) * kThreads;
           if (k0 + k < kS && e < RG3) {
             const int rz = e % RG, ry = (e / RG) % RG, rx = e / (RG * RG);
-            const vec4<T> q = d.g4[node((rgg.o[0] + rx) & (N - 1), (rgg.o[1] + ry) & (N - 1),
+            const vec4<T> q = g4[node((rgg.o[0] + rx) & (N - 1), (rgg.o[1] + ry) & (N - 1),
                                         (rgg.o[2] + rz) & (N - 1), N)];
             s0[k] = q.x;
             s1[k] = q.y;
@@ -435,7 +439,6 @@ __global__ void __launch_bounds__(kThreads)
     __syncthreads();
   }
 
-  const uint32_t n = (uint32_t)(*d.step);
   const T inv_h = keep_in_sgpr(d.inv_h);
   const T inv_h3 = keep_in_sgpr(d.inv_h3);
   T* xo = d.xs[0] + start;
@@ -492,7 +495,7 @@ __global__ void __launch_bounds__(kThreads)
 #pragma unroll 1
         for (int k = 0; k < 8; ++k) {
           const int aa = k >> 2, bb = (k >> 1) & 1, cc = k & 1;
-          const vec4<T> q = d.g4[node((st.c[0] + aa) & (N - 1), (st.c[1] + bb) & (N - 1),
+          const vec4<T> q = g4[node((st.c[0] + aa) & (N - 1), (st.c[1] + bb) & (N - 1),
                                       (st.c[2] + cc) & (N - 1), N)];
           const T wgt = (aa ? wx[1] : wx[0]) * (bb ? wy[1] : wy[0]) * (cc ? wz[1] : wz[0]);
           g0 += wgt * q.x;
@@ -549,7 +552,7 @@ __global__ void __launch_bounds__(kThreads)
       const LdsAcc<T> v = acc[e];
       if (v != (LdsAcc<T>)0) {
         const int rz = e % R, ry = (e / R) % R, rx = e / (R * R);
-        unsafeAtomicAdd(&d.ubar[node((rg.o[0] + rx) & (N - 1), (rg.o[1] + ry) & (N - 1),
+        unsafeAtomicAdd(&ubar[node((rg.o[0] + rx) & (N - 1), (rg.o[1] + ry) & (N - 1),
                                      (rg.o[2] + rz) & (N - 1), N)],
                         (T)v);
       }
@@ -651,7 +654,11 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
   rg.o[1] = (tile % nt) * kTile2 - kM2;
   rg.o[2] = 0;
   const bool use_region = d.use_region;
-  T* const ubar = d.ubar;
+  // buffers of step n: gather array g4[n & 1]; the deposit goes to ubar[(n + 1) & 1] (the
+  // state's own ubar[n & 1] when only depositing)
+  const uint32_t n = (uint32_t)(*d.step);
+  const vec4<T>* const g4 = d.g4[n & 1u];
+  T* const ubar = d.ubar[deposit_only ? (n & 1u) : ((n & 1u) ^ 1u)];
   const T* xi = d.xs[src_set] + start;
   const T* yi = d.ys[src_set] + start;
   const double* ai = d.as[src_set] + start;
@@ -691,7 +698,7 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
         if (e < kR2sq) {
           const int ry = e % kR2, rx = e / kR2;
           const vec4<T> q =
-              d.g4[(int64_t)((rg.o[0] + rx) & (N - 1)) * N + ((rg.o[1] + ry) & (N - 1))];
+              g4[(int64_t)((rg.o[0] + rx) & (N - 1)) * N + ((rg.o[1] + ry) & (N - 1))];
           s0[k] = q.x;
           s1[k] = q.y;
           s2[k] = q.z;
@@ -709,7 +716,6 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
     }
     __syncthreads();
   }
-  const uint32_t n = (uint32_t)(*d.step);
   const T inv_h = keep_in_sgpr(d.inv_h);
   const T inv_h3 = keep_in_sgpr(d.inv_h3);
   const bool linear_mass = d.flags & SIPF_FLAG_LINEAR_MASS;
@@ -755,7 +761,7 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
         for (int k = 0; k < 4; ++k) {
           const int aa = k >> 1, bb = k & 1;
           const vec4<T> q =
-              d.g4[(int64_t)((st.c[0] + aa) & (N - 1)) * N + ((st.c[1] + bb) & (N - 1))];
+              g4[(int64_t)((st.c[0] + aa) & (N - 1)) * N + ((st.c[1] + bb) & (N - 1))];
           const T wgt = (aa ? wx[1] : wx[0]) * (bb ? wy[1] : wy[0]);
           g0 += wgt * q.x;
           g1 += wgt * q.z;
@@ -797,7 +803,7 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
       const LdsAcc<T> v = acc[e];
       if (v != (LdsAcc<T>)0) {
         const int ry = e % kR2, rx = e / kR2;
-        unsafeAtomicAdd(&d.ubar[(int64_t)((rg.o[0] + rx) & (N - 1)) * N +
+        unsafeAtomicAdd(&ubar[(int64_t)((rg.o[0] + rx) & (N - 1)) * N +
                                 ((rg.o[1] + ry) & (N - 1))],
                         (T)v);
       }

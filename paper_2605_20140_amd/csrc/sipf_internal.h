@@ -140,8 +140,14 @@ struct SimDesc {
   int max_chunks;     // bound on the number of chunks: ceil(P / kChunk) + ntiles
   Ptr<uint32_t> key;     // 2P: (tile, rank within tile) per particle
   // grid (real, N^3 row-major)
-  Ptr<T> ubar, v, m, w;
-  Ptr<vec4<T>> g4;       // gather field per node: (d1 v, d2 v, d3 v, w^n)
+  Ptr<T> v, m, w;
+  // Deposited density and gather array, two buffers each, chosen by the parity of the step
+  // index n: the particle pass of step n gathers from g4[n & 1] = (d1 v^n, d2 v^n, d3 v^n,
+  // w^n) and deposits ubar^{n+1} into ubar[(n + 1) & 1], while the field passes of the same
+  // step read ubar^n from ubar[n & 1] and write the next gather array into g4[(n + 1) & 1].
+  // The two halves of a step share no buffer and run side by side.
+  Ptr<T> ubar[2];
+  Ptr<vec4<T>> g4[2];
   // spectra, half-spectrum layout S[k3][i1][i2], k3 in [0, N/2]
   Ptr<cplx<T>> SM, SW, SV, SGx, SGy;
   Ptr<cplx<T>> SVg;      // V spectrum the y and z derivatives are formed from: SV, or with the
@@ -288,11 +294,20 @@ constexpr int kXpassElems1024 = 4096;
 inline int xpass_elems(int lg) { return lg == 10 ? kXpassElems1024 : kXpassElems; }
 template <typename T> void block_counts(const SimDev<T>& d, int counts[K_COUNT]);
 
-template <typename T> void launch_zfwd(const Batch<T>& b, int nblk, int lg, hipStream_t s);
-template <typename T> void launch_yfwd(const Batch<T>& b, int nblk, int lg, hipStream_t s);
-template <typename T> void launch_xpass(const Batch<T>& b, int nblk, int lg, hipStream_t s);
-template <typename T> void launch_yinv(const Batch<T>& b, int nblk, int lg, hipStream_t s);
-template <typename T> void launch_zinv(const Batch<T>& b, int nblk, int lg, hipStream_t s);
+// Field passes.  mode 0: the field half of a step; mode kGradOnly: only the gather array of
+// the current state (the gradient of v^n and w^n into g4[n & 1]; m, v, w, ubar and the
+// diagnostics untouched), for initialisation.  The y and x passes do the same in both modes.
+constexpr int kGradOnly = 1;
+template <typename T> void launch_zfwd(const Batch<T>& b, int nblk, int lg, hipStream_t s,
+                                       int mode);
+template <typename T> void launch_yfwd(const Batch<T>& b, int nblk, int lg, hipStream_t s,
+                                       int mode);
+template <typename T> void launch_xpass(const Batch<T>& b, int nblk, int lg, hipStream_t s,
+                                        int mode);
+template <typename T> void launch_yinv(const Batch<T>& b, int nblk, int lg, hipStream_t s,
+                                       int mode);
+template <typename T> void launch_zinv(const Batch<T>& b, int nblk, int lg, hipStream_t s,
+                                       int mode);
 template <typename T>
 void launch_plane(const Batch<T>& b, int nblk, int lg, hipStream_t s, int configure);
 template <typename T> bool plane_fits(int lg);

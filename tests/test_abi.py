@@ -55,10 +55,10 @@ def test_state_bytes_scales():
     b64 = sipf.state_bytes(_p(N=64, P=1 << 20))
     b32 = sipf.state_bytes(_p(N=64, P=1 << 20, precision=1))
     assert b32 < b64
-    # particles: two sets of (3 s + 8 + 4) bytes + an 8-byte binning key; grid: (4 + 4) s N^3
-    # real + 5 half spectra
+    # particles: two sets of (3 s + 8 + 4) bytes + an 8-byte binning key; grid: s N^3 times
+    # (2 ubar buffers + v, m, w + 2 four-component gather arrays) real + 5 half spectra
     N, P = 64, 1 << 20
-    expect64 = P * (2 * (24 + 12) + 8) + N ** 3 * 8 * 8 + 5 * (N // 2 + 1) * N * N * 16
+    expect64 = P * (2 * (24 + 12) + 8) + N ** 3 * 13 * 8 + 5 * (N // 2 + 1) * N * N * 16
     assert expect64 <= b64 < expect64 + 64 * 1024
     assert sipf.state_bytes(_p(P=0)) > 0
 
@@ -125,7 +125,7 @@ def test_two_dimensional_state_bytes():
     b3 = sipf.state_bytes(_p(N=64, P=1 << 16))
     assert b2 < b3
     N, P = 64, 1 << 16
-    expect = P * (2 * (16 + 12) + 8) + N ** 2 * 8 * 8 + 5 * (N // 2 + 1) * N * 16
+    expect = P * (2 * (16 + 12) + 8) + N ** 2 * 13 * 8 + 5 * (N // 2 + 1) * N * 16
     assert expect <= b2 < expect + 64 * 1024
     assert sipf.state_bytes(_p(N=1024, P=100, dim=2)) > 0
     assert sipf.state_bytes(_p(N=512, P=100, dim=3)) == sipf.state_bytes(_p(N=512, P=100, dim=0))
