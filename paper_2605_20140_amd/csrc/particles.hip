@@ -106,17 +106,30 @@ __device__ __forceinline__ U keep_in_sgpr(U v) {
   }
 }
 
+// exp(x) for the float32 mass update outside |x| <= 1/2: x log2(e) = k + f with k an integer
+// and |f| <= 1/2, 2^f by the hardware float32 exp2 (about 1 ulp) and 2^k exactly by a
+// float64 ldexp, so that the result neither overflows nor underflows before float64 does.
+// Relative error about (|x| + 2) 2^-24, from rounding x log2(e) to float32.  (No float64
+// polynomial: its constants would occupy registers for the whole particle loop.)
+__device__ __forceinline__ double exp_wide(float x) {
+  if (__builtin_isinf(x)) return x > 0.0f ? (double)x : 0.0;
+  const float t = x * 1.44269504088896341f;
+  const float k = __builtin_rintf(t);
+  return ldexp((double)__builtin_amdgcn_exp2f(t - k), (int)k);
+}
+
 // Mass update a' = a exp(x), x = tau (rho - 1).  float64: the exact exponential.  float32
 // form: a' = a + a expm1(x) with expm1 by its Taylor polynomial to degree 8 in float32
 // (relative truncation error below 1e-8 for |x| <= 1/2, the range of tau |rho - 1| <= tau
 // <= 1/2 for w >= 0) and one float64 multiply-add, so that the mass itself is accumulated
 // in float64 and the relative error of a step's factor is about |x| 2^-24; outside that
-// range (w < 0 at a node of the implicit solve's small negative lobes) the float64 path.
+// range (w < 0 at a node of the implicit solve's small negative lobes, or non-finite)
+// exp_wide.
 __device__ __forceinline__ double mass_factor_update(double a, double x) {
   return a * exp(x);
 }
 __device__ __forceinline__ double mass_factor_update(double a, float x) {
-  if (!(fabsf(x) <= 0.5f)) return a * exp((double)x);
+  if (!(fabsf(x) <= 0.5f)) return a * exp_wide(x);
   float e = 1.0f / 40320.0f;
   e = fmaf(e, x, 1.0f / 5040.0f);
   e = fmaf(e, x, 1.0f / 720.0f);
@@ -231,7 +244,9 @@ template <typename T> using LdsAcc = typename LdsAccT<T>::type;
 // Particles per load batch.  3D float32: six, which with a cap of 96 VGPRs lets five waves
 // per SIMD run (the LDS region of 32 KB allows five blocks per CU): 154.5 us against 158-161 us
 // with eight particles at four waves.  The 2D pass keeps eight (LoadBatch2).
-template <typename T> struct LoadBatch { static constexpr int n = 6; };
+template <typename T> struct LoadBatch { static constexpr int n = 4; };
+// float32 3D pass: gather loads issued before the noise is drawn
+constexpr bool kEarlyGather = true;
 template <> struct LoadBatch<double> { static constexpr int n = 4; };
 template <typename T> struct LoadBatch2 { static constexpr int n = 8; };
 template <> struct LoadBatch2<double> { static constexpr int n = 4; };
@@ -439,13 +454,27 @@ __global__ void __launch_bounds__(kThreads)
     __syncthreads();
   }
 
+  // loop invariants held in scalar registers (see keep_in_sgpr); float64 pins only the two
+  // it always held, the others would take twice the registers and spill
+  constexpr bool kPin = sizeof(T) == 4;
   const T inv_h = keep_in_sgpr(d.inv_h);
   const T inv_h3 = keep_in_sgpr(d.inv_h3);
-  T* xo = d.xs[0] + start;
-  T* yo = d.ys[0] + start;
-  T* zo = d.zs[0] + start;
-  double* ao = d.as[0] + start;
-  uint32_t* ido = d.ids[0] + start;
+  const T drift_s = kPin ? keep_in_sgpr(d.drift) : (T)0;
+  const T noise_amp_s = kPin ? keep_in_sgpr(d.noise_amp) : (T)0;
+  const T L_s = kPin ? keep_in_sgpr(d.L) : (T)0;
+  const double dt_s = kPin ? keep_in_sgpr(d.dt) : 0.0;
+  const uint32_t sim_lo_s = kPin ? keep_in_sgpr(d.sim_lo) : 0u;
+  const uint32_t sim_hi_s = kPin ? keep_in_sgpr(d.sim_hi) : 0u;
+  const uint32_t seed_lo_s = kPin ? keep_in_sgpr(d.seed_lo) : 0u;
+  const uint32_t seed_hi_s = kPin ? keep_in_sgpr(d.seed_hi) : 0u;
+#define SIPF_INV(name, field) (kPin ? name##_s : d.field)
+  // outputs at 32-bit byte offsets from the chunk's first particle (scalar base + vector
+  // offset addressing)
+  unsigned char* const xo = reinterpret_cast<unsigned char*>(d.xs[0] + start);
+  unsigned char* const yo = reinterpret_cast<unsigned char*>(d.ys[0] + start);
+  unsigned char* const zo = reinterpret_cast<unsigned char*>(d.zs[0] + start);
+  unsigned char* const ao = reinterpret_cast<unsigned char*>(d.as[0] + start);
+  unsigned char* const ido = reinterpret_cast<unsigned char*>(d.ids[0] + start);
   const bool linear_mass = d.flags & SIPF_FLAG_LINEAR_MASS;
   const bool noise = !(d.flags & SIPF_FLAG_NO_NOISE);
   Acc dg;
@@ -470,61 +499,87 @@ __global__ void __launch_bounds__(kThreads)
         deposit_one<ORDER, R>(ubar, acc, s0, rg, use_region, N, (T)a * inv_h3);
         continue;
       }
-      // gather (d1 v, d2 v, d3 v, w) at the old position
+      // gather (d1 v, d2 v, d3 v, w) at the old position.  float32: the eight LDS loads are
+      // issued first and used after the noise is drawn, so that their latency (and that of
+      // the previous particle's deposit atomics, which the LDS completes in order) overlaps
+      // the Philox rounds; a stencil outside the staged region loads the region's first
+      // nodes instead and is gathered from global memory below.  (float64: 64 registers of
+      // loads in flight would cost occupancy; its loads follow the noise.)
       const Stencil<T> st = make_stencil(x, y, z, inv_h, N);
-      T wx[2], wy[2], wz[2];
-      weights(st, wx, wy, wz);
-      T g0 = 0, g1 = 0, g2 = 0, gw = 0;
-      if (use_region && in_region<RG>(st, rgg, N, l)) {
+      const bool inr = use_region && in_region<RG>(st, rgg, N, l);
+      constexpr bool kEarly = sizeof(T) == 4 && kEarlyGather;
+      vec4<T> q[kEarly ? 8 : 1];
+      const int b0 = inr ? rindex<RG>(l[0], l[1], l[2]) : 0;
+      if constexpr (kEarly) {
 #pragma unroll
-        for (int aa = 0; aa < 2; ++aa)
-#pragma unroll
-          for (int bb = 0; bb < 2; ++bb)
-#pragma unroll
-            for (int cc = 0; cc < 2; ++cc) {
-              const vec4<T> q = gl[rindex<RG>(l[0] + aa, l[1] + bb, l[2] + cc)];
-              const T wgt = wx[aa] * wy[bb] * wz[cc];
-              g0 += wgt * q.x;
-              g1 += wgt * q.y;
-              g2 += wgt * q.z;
-              gw += wgt * q.w;
-            }
-      } else {
-        // the stencil leaves the staged region (or there is none): one corner at a time, so
-        // that this rare path does not raise the register count of the whole kernel
-#pragma unroll 1
-        for (int k = 0; k < 8; ++k) {
-          const int aa = k >> 2, bb = (k >> 1) & 1, cc = k & 1;
-          const vec4<T> q = g4[node((st.c[0] + aa) & (N - 1), (st.c[1] + bb) & (N - 1),
-                                      (st.c[2] + cc) & (N - 1), N)];
-          const T wgt = (aa ? wx[1] : wx[0]) * (bb ? wy[1] : wy[0]) * (cc ? wz[1] : wz[0]);
-          g0 += wgt * q.x;
-          g1 += wgt * q.y;
-          g2 += wgt * q.z;
-          gw += wgt * q.w;
-        }
+        for (int k = 0; k < 8; ++k)
+          q[k] = gl[b0 + ((k >> 2) * RG + ((k >> 1) & 1)) * RG + (k & 1)];
       }
 
       // Wiener increment: Philox counter (particle index, step, simulation)
       T zn[3] = {0, 0, 0};
       if (noise) {
-        uint32_t c0 = pid[j], c1 = n, c2 = d.sim_lo, c3 = d.sim_hi;
-        philox4x32_10(c0, c1, c2, c3, d.seed_lo, d.seed_hi);
+        uint32_t c0 = pid[j], c1 = n, c2 = SIPF_INV(sim_lo, sim_lo), c3 = SIPF_INV(sim_hi, sim_hi);
+        philox4x32_10(c0, c1, c2, c3, SIPF_INV(seed_lo, seed_lo), SIPF_INV(seed_hi, seed_hi));
         box_muller(c0, c1, c2, c3, zn);
       }
 
+      T wx[2], wy[2], wz[2];
+      weights(st, wx, wy, wz);
+      T g0 = 0, g1 = 0, g2 = 0, gw = 0;
+      if constexpr (kEarly) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const T wgt = wx[k >> 2] * wy[(k >> 1) & 1] * wz[k & 1];
+          g0 += wgt * q[k].x;
+          g1 += wgt * q[k].y;
+          g2 += wgt * q[k].z;
+          gw += wgt * q[k].w;
+        }
+      } else if (inr) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          const vec4<T> qk = gl[b0 + ((k >> 2) * RG + ((k >> 1) & 1)) * RG + (k & 1)];
+          const T wgt = wx[k >> 2] * wy[(k >> 1) & 1] * wz[k & 1];
+          g0 += wgt * qk.x;
+          g1 += wgt * qk.y;
+          g2 += wgt * qk.z;
+          gw += wgt * qk.w;
+        }
+      }
+      if (!inr) {
+        // the stencil leaves the staged region (or there is none): one corner at a time, so
+        // that this rare path does not raise the register count of the whole kernel
+        g0 = g1 = g2 = gw = (T)0;
+#pragma unroll 1
+        for (int k = 0; k < 8; ++k) {
+          const int aa = k >> 2, bb = (k >> 1) & 1, cc = k & 1;
+          const vec4<T> qg = g4[node((st.c[0] + aa) & (N - 1), (st.c[1] + bb) & (N - 1),
+                                     (st.c[2] + cc) & (N - 1), N)];
+          const T wgt = (aa ? wx[1] : wx[0]) * (bb ? wy[1] : wy[0]) * (cc ? wz[1] : wz[0]);
+          g0 += wgt * qg.x;
+          g1 += wgt * qg.y;
+          g2 += wgt * qg.z;
+          gw += wgt * qg.w;
+        }
+      }
+
       // push and mass update
-      const T xn = wrap_periodic(x + d.drift * g0 + d.noise_amp * zn[0], d.L);
-      const T yn = wrap_periodic(y + d.drift * g1 + d.noise_amp * zn[1], d.L);
-      const T zz = wrap_periodic(z + d.drift * g2 + d.noise_amp * zn[2], d.L);
+      const T drift = SIPF_INV(drift, drift), noise_amp = SIPF_INV(noise_amp, noise_amp);
+      const T Lbox = SIPF_INV(L, L);
+      const double dt = SIPF_INV(dt, dt);
+      const T xn = wrap_periodic(x + drift * g0 + noise_amp * zn[0], Lbox);
+      const T yn = wrap_periodic(y + drift * g1 + noise_amp * zn[1], Lbox);
+      const T zz = wrap_periodic(z + drift * g2 + noise_amp * zn[2], Lbox);
       const T rho = rho_of(gw);
-      const double an = linear_mass ? a * (1.0 + d.dt * (double)rho - d.dt)
-                                    : mass_factor_update(a, (T)d.dt * (rho - (T)1));
-      xo[i] = xn;
-      yo[i] = yn;
-      zo[i] = zz;
-      ao[i] = an;
-      if (src_set) ido[i] = pid[j];
+      const double an = linear_mass ? a * (1.0 + dt * (double)rho - dt)
+                                    : mass_factor_update(a, (T)dt * (rho - (T)1));
+      const uint32_t bo = i * (uint32_t)sizeof(T);
+      *reinterpret_cast<T*>(xo + bo) = xn;
+      *reinterpret_cast<T*>(yo + bo) = yn;
+      *reinterpret_cast<T*>(zo + bo) = zz;
+      *reinterpret_cast<double*>(ao + i * 8u) = an;
+      if (src_set) *reinterpret_cast<uint32_t*>(ido + i * 4u) = pid[j];
       if (isfinite(an) && isfinite(xn) && isfinite(yn) && isfinite(zz)) {
         dg.sum[0] += an;
         acc_min(dg, D_MIN_A, an);
@@ -560,6 +615,8 @@ __global__ void __launch_bounds__(kThreads)
   }
   if (!deposit_only) acc_flush(dg, diag_stripe(d));
 }
+
+#undef SIPF_INV
 
 // ---- two-dimensional particle pass ---------------------------------------------------------
 // The same pass on an N^2 grid (the paper's two-dimensional example): bilinear stencils,
@@ -936,14 +993,43 @@ __global__ void __launch_bounds__(kThreads) k_bin_count(Batch<T> bt) {
   }
 }
 
-// Exclusive scans of the tile counts (tile offsets) and of ceil(count / kChunk) (chunk
-// offsets), and the chunk table.  One block per segment of kSegTiles tiles: a block first
-// sums the counts of every earlier segment (its carry), then scans its own segment.  The
-// counts are cleared for the next binning by the scatter, after every block has read them.
+// Exclusive scan of the tile counts (tile offsets, in tile order) and the chunk table, with
+// the chunks in decreasing size: a tile of c particles has floor(c / kChunk) full chunks and,
+// if c mod kChunk > 0, one smaller chunk.  The table holds the full chunks first (in tile
+// order), then the smaller ones by size class (halving from kChunk / 2 to kChunk / 16, and
+// a last class below that), each class in tile order.  The particle pass takes chunks in
+// table order as CUs free up, so the large chunks start first and the small ones fill the
+// end of the pass, which shortens its tail (longest-first list scheduling).  With more than
+// kSizeOrderMax chunks the tail is a small part of the pass, and the table stays in tile order
+// (all chunks of a tile together, neighbouring tiles next to each other).
+// One block per segment of kSegTiles tiles: every block sums the counts of all segments
+// (class totals, for the class bases) and of the earlier ones (its carries), then scans its
+// own segment.  The counts are cleared for the next binning by the scatter, after every block
+// has read them.
 constexpr int kScanSeg = 16;                    // tiles per thread in a segment
 constexpr int kSegTiles = kScanSeg * kThreads;  // tiles per segment (block)
+constexpr int kClasses = 6;                     // size classes of the chunk table
+constexpr uint32_t kSizeOrderMax = 8192;        // chunks up to which they go by size
 
-__device__ __forceinline__ uint32_t chunks_of(uint32_t c) { return (c + kChunk - 1) / kChunk; }
+// size class of a chunk of n particles, 0 < n <= kChunk
+__device__ __forceinline__ int chunk_class(uint32_t n) {
+  int c = 0;
+#pragma unroll
+  for (int k = 0; k < kClasses - 1; ++k) c += n < (uint32_t)(kChunk >> k);
+  return c;
+}
+
+// chunks of each class contributed by a tile of c particles
+struct ClassCount {
+  uint32_t n[kClasses];
+};
+__device__ __forceinline__ void add_tile(ClassCount& a, uint32_t c) {
+  a.n[0] += c / kChunk;
+  const uint32_t r = c % kChunk;
+  const int cl = chunk_class(r);
+#pragma unroll
+  for (int k = 1; k < kClasses; ++k) a.n[k] += (r != 0u && cl == k) ? 1u : 0u;
+}
 
 template <typename T>
 __global__ void __launch_bounds__(kThreads) k_bin_scan(Batch<T> bt) {
@@ -953,32 +1039,66 @@ __global__ void __launch_bounds__(kThreads) k_bin_scan(Batch<T> bt) {
   const int nt = d.ntiles;
   const int s0 = lb * kSegTiles;
   __shared__ uint32_t cnt[kSegTiles];
-  __shared__ uint32_t pp[kThreads], pc[kThreads];
-  // carry: tiles and chunks of the segments before this one (kScanSeg loads per thread in
-  // flight together per earlier segment)
-  uint32_t ap = 0, ac = 0;
-  for (int e0 = 0; e0 < s0; e0 += kSegTiles) {
+  __shared__ uint32_t sh[kClasses + 1][kThreads];  // scan arrays: classes, then particles
+  __shared__ uint32_t base[kClasses];              // first table entry of each class, here
+  __shared__ uint32_t carry_all;                   // chunks of the earlier segments
+  __shared__ uint32_t by_size;                     // table by size class (else tile order)
+  // class totals over all segments and carries (chunks per class, particles) of the earlier
+  // ones; kScanSeg loads per thread in flight together per segment
+  ClassCount tot{}, car{};
+  uint32_t ap = 0;
+  for (int e0 = 0; e0 < nt; e0 += kSegTiles) {
     uint32_t v[kScanSeg];
 #pragma unroll
-    for (int j = 0; j < kScanSeg; ++j) v[j] = d.tcount[e0 + (int)threadIdx.x + j * kThreads];
+    for (int j = 0; j < kScanSeg; ++j) {
+      const int t = e0 + (int)threadIdx.x + j * kThreads;
+      v[j] = t < nt ? d.tcount[t] : 0u;
+    }
 #pragma unroll
     for (int j = 0; j < kScanSeg; ++j) {
-      ap += v[j];
-      ac += chunks_of(v[j]);
+      add_tile(tot, v[j]);
+      if (e0 < s0) {
+        add_tile(car, v[j]);
+        ap += v[j];
+      }
     }
   }
-  pp[threadIdx.x] = ap;
-  pc[threadIdx.x] = ac;
-  __syncthreads();
-  for (int off = kThreads / 2; off > 0; off >>= 1) {
-    if ((int)threadIdx.x < off) {
-      pp[threadIdx.x] += pp[threadIdx.x + off];
-      pc[threadIdx.x] += pc[threadIdx.x + off];
+  // block sums: totals into sh[0..kClasses), then carries (and particles) the same way
+  for (int pass = 0; pass < 2; ++pass) {
+    const ClassCount& a = pass ? car : tot;
+#pragma unroll
+    for (int k = 0; k < kClasses; ++k) sh[k][threadIdx.x] = a.n[k];
+    sh[kClasses][threadIdx.x] = ap;
+    __syncthreads();
+    for (int off = kThreads / 2; off > 0; off >>= 1) {
+      if ((int)threadIdx.x < off) {
+#pragma unroll
+        for (int k = 0; k <= kClasses; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + off];
+      }
+      __syncthreads();
     }
+    if (threadIdx.x == 0) {
+      if (pass == 0) {
+        uint32_t b = 0;  // exclusive scan of the class totals: class bases
+        for (int k = 0; k < kClasses; ++k) {
+          base[k] = b;
+          b += sh[k][0];
+        }
+        by_size = b <= kSizeOrderMax ? 1u : 0u;
+        if (s0 + kSegTiles >= nt) d.coff[nt] = b;  // number of chunks
+      } else {
+        uint32_t ca = 0;
+        for (int k = 0; k < kClasses; ++k) {
+          base[k] += sh[k][0];  // + this block's carries
+          ca += sh[k][0];
+        }
+        carry_all = ca;
+      }
+    }
+    if (pass == 1) ap = sh[kClasses][0];
     __syncthreads();
   }
-  const uint32_t carry_p = pp[0], carry_c = pc[0];
-  __syncthreads();
+  const uint32_t carry_p = ap;
   // this segment: counts into LDS (coalesced), kScanSeg consecutive tiles per thread
   {
     uint32_t v[kScanSeg];
@@ -992,48 +1112,70 @@ __global__ void __launch_bounds__(kThreads) k_bin_scan(Batch<T> bt) {
   }
   __syncthreads();
   const int b0 = (int)threadIdx.x * kScanSeg;
-  uint32_t sp = 0, sc = 0;
+  ClassCount mine{};
+  uint32_t sp = 0;
 #pragma unroll
   for (int j = 0; j < kScanSeg; ++j) {
     const uint32_t c = cnt[b0 + j];
     sp += c;
-    sc += chunks_of(c);
+    add_tile(mine, c);
   }
-  pp[threadIdx.x] = sp;
-  pc[threadIdx.x] = sc;
+#pragma unroll
+  for (int k = 0; k < kClasses; ++k) sh[k][threadIdx.x] = mine.n[k];
+  sh[kClasses][threadIdx.x] = sp;
   __syncthreads();
   // inclusive Hillis-Steele scan of the per-thread sums
   for (int off = 1; off < kThreads; off <<= 1) {
-    uint32_t xp = 0, xc = 0;
-    if ((int)threadIdx.x >= off) {
-      xp = pp[threadIdx.x - off];
-      xc = pc[threadIdx.x - off];
-    }
+    uint32_t x[kClasses + 1];
+#pragma unroll
+    for (int k = 0; k <= kClasses; ++k)
+      x[k] = (int)threadIdx.x >= off ? sh[k][threadIdx.x - off] : 0u;
     __syncthreads();
-    pp[threadIdx.x] += xp;
-    pc[threadIdx.x] += xc;
+#pragma unroll
+    for (int k = 0; k <= kClasses; ++k) sh[k][threadIdx.x] += x[k];
     __syncthreads();
   }
-  uint32_t rp = carry_p + (threadIdx.x ? pp[threadIdx.x - 1] : 0u);
-  uint32_t rc = carry_c + (threadIdx.x ? pc[threadIdx.x - 1] : 0u);
-  for (int j = 0; j < kScanSeg; ++j) {
+  uint32_t rp = carry_p + (threadIdx.x ? sh[kClasses][threadIdx.x - 1] : 0u);
+  uint32_t nx[kClasses];  // next table entry of each class for this thread's tiles
+  uint32_t na = carry_all;  // next entry in tile order
+#pragma unroll
+  for (int k = 0; k < kClasses; ++k) {
+    nx[k] = base[k] + (threadIdx.x ? sh[k][threadIdx.x - 1] : 0u);
+    na += threadIdx.x ? sh[k][threadIdx.x - 1] : 0u;
+  }
+  if (!by_size) {
+    for (int j = 0; j < kScanSeg; ++j) {
+      const int t = s0 + b0 + j;
+      if (t >= nt) break;
+      const uint32_t c = cnt[b0 + j];
+      d.toff[t] = rp;
+      for (uint32_t k = 0; k * kChunk < c; ++k) {
+        const uint32_t cs = rp + k * kChunk;
+        d.cinfo[na++] = uint4{cs, cs + kChunk < rp + c ? cs + kChunk : rp + c, (uint32_t)t, 0u};
+      }
+      rp += c;
+    }
+  }
+  for (int j = 0; j < kScanSeg && by_size; ++j) {
     const int t = s0 + b0 + j;
     if (t >= nt) break;
     const uint32_t c = cnt[b0 + j];
-    const uint32_t nch = chunks_of(c);
     d.toff[t] = rp;
-    d.coff[t] = rc;
-    for (uint32_t k = 0; k < nch; ++k) {
-      const uint32_t cs = rp + k * kChunk;
-      d.cinfo[rc + k] = uint4{cs, cs + kChunk < rp + c ? cs + kChunk : rp + c, (uint32_t)t, 0u};
+    const uint32_t full = c / kChunk, r = c % kChunk;
+    for (uint32_t k = 0; k < full; ++k)
+      d.cinfo[nx[0]++] = uint4{rp + k * kChunk, rp + (k + 1) * kChunk, (uint32_t)t, 0u};
+    if (r != 0u) {
+      const int cl = chunk_class(r);
+      uint32_t at = 0;
+#pragma unroll
+      for (int k = 1; k < kClasses; ++k)
+        if (cl == k) at = nx[k]++;
+      d.cinfo[at] = uint4{rp + full * kChunk, rp + c, (uint32_t)t, 0u};
     }
     rp += c;
-    rc += nch;
   }
-  if (s0 + kSegTiles >= nt && threadIdx.x == 0) {  // the last segment closes the tables
-    d.toff[nt] = carry_p + pp[kThreads - 1];
-    d.coff[nt] = carry_c + pc[kThreads - 1];
-  }
+  if (s0 + kSegTiles >= nt && threadIdx.x == kThreads - 1)  // the last segment closes toff
+    d.toff[nt] = carry_p + sh[kClasses][kThreads - 1];
 }
 
 template <typename T, int DIM>
