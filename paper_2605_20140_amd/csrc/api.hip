@@ -591,7 +591,7 @@ int fields_t(sipf_sim* sim, double* v, double* m, double* w, double* X, double* 
       for (int64_t i = 0; i < P; ++i) a[id[i]] = ha[i];
     }
   }
-  // read-time reduction of the deposited density into buffer 2
+  // read-time reduction of the particles and the deposited density into buffer 2
   {
     const Batch<T> b = single_batch<T>(sim);
     launch_diag_u<T>(b, sim->counts[K_DIAG], 1, sim->stream);
@@ -605,8 +605,7 @@ int fields_t(sipf_sim* sim, double* v, double* m, double* w, double* X, double* 
   unsigned long long acc[D_COUNT];
   memcpy(acc, all, sizeof(acc));
   const unsigned long long* ub = all + kStripeWords;
-  acc[D_SUM_U] = ub[D_SUM_U];
-  acc[D_MIN_U] = ub[D_MIN_U];
+  for (int sl : {D_SUM_A, D_MIN_A, D_MAX_A, D_SUM_U, D_MIN_U}) acc[sl] = ub[sl];
   acc[D_NAN] += ub[D_NAN];
   sipf_diag dg;
   dg.mass_particles = as_double(acc[D_SUM_A]);

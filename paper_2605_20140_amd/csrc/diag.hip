@@ -2,12 +2,12 @@
 // mass; partition of unity: h^3 sum ubar equals it), minima / maxima for the positivity
 // lemma and Lemma mass, and counts of non-finite and negative values.
 //
-// Per step, the kernels that produce a value fold it into the diagnostics as they write it
-// (zfwd: v; zinv: m, w; particle pass: a and positions), into striped accumulator copies; the
-// one-block finalize kernel at the end of the step folds the copies into the diagnostics of
-// the new state, clears them and advances the step index.  The deposited density ubar is
-// reduced when the diagnostics are read (it is complete only after the last atomic of the
-// particle pass), into words of its own.
+// Per step, the field passes fold the values they write into the diagnostics (zfwd: v; zinv:
+// m, w), into striped accumulator copies; the one-block finalize kernel at the end of the step
+// folds the copies into the diagnostics of the new state, clears them and advances the step
+// index.  The particles (masses, positions) and the deposited density ubar are reduced when
+// the diagnostics are read, into words of their own: the particle pass, bound by instruction
+// issue, carries no per-particle reduction, and ubar is complete only after its last atomic.
 #include "diag_acc.h"
 
 namespace sipf {
@@ -66,10 +66,12 @@ __global__ void k_diag_clear(Batch<T> bt) {
     d.diag[e] = slot_identity(e % kStripeWords);
 }
 
-// Full reduction into the accumulator copies: particles and v, m, w if state != 0; ubar if
-// u != 0.
+// Full reduction into the accumulator copies of what the bits of `what` select.
+constexpr int kDiagParticles = 1;  // masses and positions
+constexpr int kDiagGrid = 2;       // v, m, w
+constexpr int kDiagU = 4;          // ubar
 template <typename T>
-__global__ void __launch_bounds__(kThreads) k_diag_full(Batch<T> bt, int state, int u) {
+__global__ void __launch_bounds__(kThreads) k_diag_full(Batch<T> bt, int what) {
   int lb;
   const int s = find_sim(bt, K_DIAG, lb);
   SimC<T>& d = sim_view(bt, s);
@@ -78,7 +80,8 @@ __global__ void __launch_bounds__(kThreads) k_diag_full(Batch<T> bt, int state, 
   Acc a;
   acc_init(a);
   const int64_t stride = (int64_t)nb * kThreads;
-  if (state) {
+  const bool state = what & kDiagGrid, u = what & kDiagU;
+  if (what & kDiagParticles) {
     for (int64_t i = (int64_t)lb * kThreads + threadIdx.x; i < d.P; i += stride) {
       const double am = d.as[0][i];
       const bool bad = !isfinite(am) || !isfinite((double)d.xs[0][i]) ||
@@ -131,13 +134,17 @@ void launch_diag_clear(const Batch<T>& b, int nsims, hipStream_t st) {
 
 template <typename T>
 void launch_diag_init(const Batch<T>& b, int nblk, int nsims, hipStream_t st) {
-  if (nblk > 0) hipLaunchKernelGGL(k_diag_full<T>, dim3(nblk), dim3(kThreads), 0, st, b, 1, 0);
+  if (nblk > 0)
+    hipLaunchKernelGGL(k_diag_full<T>, dim3(nblk), dim3(kThreads), 0, st, b,
+                       kDiagParticles | kDiagGrid);
   hipLaunchKernelGGL(k_diag_finalize<T>, dim3(nsims), dim3(kFinThreads), 0, st, b, 1);
 }
 
 template <typename T>
 void launch_diag_u(const Batch<T>& b, int nblk, int nsims, hipStream_t st) {
-  if (nblk > 0) hipLaunchKernelGGL(k_diag_full<T>, dim3(nblk), dim3(kThreads), 0, st, b, 0, 1);
+  if (nblk > 0)
+    hipLaunchKernelGGL(k_diag_full<T>, dim3(nblk), dim3(kThreads), 0, st, b,
+                       kDiagParticles | kDiagU);
   hipLaunchKernelGGL(k_diag_finalize<T>, dim3(nsims), dim3(kFinThreads), 0, st, b, 2);
 }
 

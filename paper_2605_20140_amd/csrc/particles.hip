@@ -258,14 +258,15 @@ __device__ __forceinline__ void deposit_lds(LdsAcc<T>* acc, const Stencil<T>& st
                                             T q) {
   T wx[2], wy[2], wz[2];
   weights(st, wx, wy, wz);
+  // one address; the eight nodes sit at constant offsets from it
+  LdsAcc<T>* const a0 = acc + rindex<R>(l[0], l[1], l[2]);
 #pragma unroll
   for (int aa = 0; aa < 2; ++aa)
 #pragma unroll
     for (int bb = 0; bb < 2; ++bb)
 #pragma unroll
       for (int cc = 0; cc < 2; ++cc)
-        atomicAdd(&acc[rindex<R>(l[0] + aa, l[1] + bb, l[2] + cc)],
-                  (LdsAcc<T>)(q * wx[aa] * wy[bb] * wz[cc]));
+        atomicAdd(&a0[(aa * R + bb) * R + cc], (LdsAcc<T>)(q * wx[aa] * wy[bb] * wz[cc]));
 }
 
 // Fourth-order assignment R_h^(4) (Sec. 2.2.1) in factored form.  With f the fractional
@@ -324,8 +325,11 @@ template <int R, typename T>
 __device__ __forceinline__ void deposit4_lds(LdsAcc<T>* acc, const Stencil<T>& st, const int l[3],
                                              T q) {
   const W4<T> w = weights4(st);
+  // one address (node l - 1 on every axis, inside the region); the 32 nodes at constant
+  // offsets from it
+  LdsAcc<T>* const a0 = acc + rindex<R>(l[0] - 1, l[1] - 1, l[2] - 1);
   for_r4(w, [&](int a, int b, int c, T wt) {
-    atomicAdd(&acc[rindex<R>(l[0] + a, l[1] + b, l[2] + c)], (LdsAcc<T>)(q * wt));
+    atomicAdd(&a0[((a + 1) * R + (b + 1)) * R + (c + 1)], (LdsAcc<T>)(q * wt));
   });
 }
 
@@ -477,8 +481,6 @@ __global__ void __launch_bounds__(kThreads)
   unsigned char* const ido = reinterpret_cast<unsigned char*>(d.ids[0] + start);
   const bool linear_mass = d.flags & SIPF_FLAG_LINEAR_MASS;
   const bool noise = !(d.flags & SIPF_FLAG_NO_NOISE);
-  Acc dg;
-  acc_init(dg);
 
   for (int j0 = 0; j0 < kPer; j0 += kB) {
     // The batch's loads were issued together, so waiting for all of them costs about what
@@ -580,13 +582,6 @@ __global__ void __launch_bounds__(kThreads)
       *reinterpret_cast<T*>(zo + bo) = zz;
       *reinterpret_cast<double*>(ao + i * 8u) = an;
       if (src_set) *reinterpret_cast<uint32_t*>(ido + i * 4u) = pid[j];
-      if (isfinite(an) && isfinite(xn) && isfinite(yn) && isfinite(zz)) {
-        dg.sum[0] += an;
-        acc_min(dg, D_MIN_A, an);
-        acc_min(dg, D_MAX_A, an);
-      } else {
-        dg.cnt[0] += 1;
-      }
 
       // deposit of the new state: ubar^{n+1}
       const Stencil<T> sn = make_stencil(xn, yn, zz, inv_h, N);
@@ -613,7 +608,6 @@ __global__ void __launch_bounds__(kThreads)
       }
     }
   }
-  if (!deposit_only) acc_flush(dg, diag_stripe(d));
 }
 
 #undef SIPF_INV
@@ -777,8 +771,6 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
   const T inv_h3 = keep_in_sgpr(d.inv_h3);
   const bool linear_mass = d.flags & SIPF_FLAG_LINEAR_MASS;
   const bool noise = !(d.flags & SIPF_FLAG_NO_NOISE);
-  Acc dg;
-  acc_init(dg);
   for (int j0 = 0; j0 < kPer; j0 += kB) {
     __builtin_amdgcn_s_waitcnt(kWaitVmcnt0);  // the batch's loads, as in the 3D pass
 #pragma unroll
@@ -840,13 +832,6 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
       yo[i] = yn;
       ao[i] = an;
       if (src_set) ido[i] = pid[j];
-      if (isfinite(an) && isfinite(xn) && isfinite(yn)) {
-        dg.sum[0] += an;
-        acc_min(dg, D_MIN_A, an);
-        acc_min(dg, D_MAX_A, an);
-      } else {
-        dg.cnt[0] += 1;
-      }
       deposit2(ubar, acc, make_stencil2(xn, yn, inv_h, N), rg, use_region, N,
                (T)an * inv_h3);
     }
@@ -866,7 +851,6 @@ __global__ void __launch_bounds__(kThreads) k_particles2(Batch<T> bt, int src_se
       }
     }
   }
-  if (!deposit_only) acc_flush(dg, diag_stripe(d));
 }
 
 // ---- binning ----------------------------------------------------------------------------
