@@ -339,13 +339,32 @@ def served(nreq, budget_gib, seed=4, graphs=False):
         srv.run([serve.Request(r.rid, 0.0, r.N, r.P, r.steps, r.params, r.ic) for r in probe])
         solo_s = (time.perf_counter() - t) / len(probe)
     rate = 0.7 / solo_s
+    # one request of each size class alone, with the mix's tick length: its solo latency
+    cls = lambda r: f"N{r.N}_P{'lo' if r.P < (1 << 19) else 'hi'}"
+    firsts = {}
+    for r in reqs:
+        firsts.setdefault(cls(r), r)
+    solo_by = {}
+    for k, r in sorted(firsts.items()):
+        srv = serve.Server(be, budget_gib << 30, max_slots=1, tick_steps=10)
+        rec, _ = srv.run([serve.Request(r.rid, 0.0, r.N, r.P, r.steps, r.params, r.ic)])
+        solo_by[k] = round(1e3 * rec[r.rid].latency, 1)
     rng = np.random.Generator(np.random.Philox(seed))
     arrivals = np.cumsum(rng.exponential(1.0 / rate, size=len(reqs)))
     for r, ta in zip(reqs, arrivals):
         r.t_arrive = float(ta)
     srv = serve.Server(be, budget_gib << 30, max_slots=64, tick_steps=10)
-    _, summ = srv.run(reqs)
+    recs, summ = srv.run(reqs)
     be.close()
+    # latency by request size: the grid and the particle count's half of the log range
+    by = {}
+    for r in reqs:
+        key = f"N{r.N}_P{'lo' if r.P < (1 << 19) else 'hi'}"
+        by.setdefault(key, []).append(recs[r.rid].latency)
+    summ["latency_by_size_ms"] = {
+        k: dict(n=len(v), p50=round(1e3 * float(np.percentile(v, 50)), 1),
+                p99=round(1e3 * float(np.percentile(v, 99)), 1), solo=solo_by.get(k))
+        for k, v in sorted(by.items())}
     summ.update(rate_per_s=rate, solo_service_s=solo_s, hbm_budget_gib=budget_gib,
                 max_slots=64, tick_steps=10, form="fp32",
                 step_path="captured graph per batch" if graphs else "allocation-free batched step",
