@@ -156,21 +156,24 @@ Layout make_layout(const sipf_params& p) {
   return L;
 }
 
-// second stream and events of a captured step's fork (binning) and join (particle pass)
+// second stream and events of a step's two halves: fork (the field passes start), zfwd (the
+// forward z pass is done) and join (the field passes are done)
 struct StepFork {
   hipStream_t aux = nullptr;
-  hipEvent_t fork = nullptr, join = nullptr;
+  hipEvent_t fork = nullptr, zfwd = nullptr, join = nullptr;
 };
 
 hipError_t create_fork(StepFork& f) {
   hipError_t e = hipStreamCreateWithFlags(&f.aux, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&f.fork, hipEventDisableTiming);
+  if (e == hipSuccess) e = hipEventCreateWithFlags(&f.zfwd, hipEventDisableTiming);
   if (e == hipSuccess) e = hipEventCreateWithFlags(&f.join, hipEventDisableTiming);
   return e;
 }
 
 void destroy_fork(StepFork& f) {
   if (f.join) (void)hipEventDestroy(f.join);
+  if (f.zfwd) (void)hipEventDestroy(f.zfwd);
   if (f.fork) (void)hipEventDestroy(f.fork);
   if (f.aux) (void)hipStreamDestroy(f.aux);
   f = StepFork{};
@@ -218,11 +221,14 @@ struct FftGroup {
   int lg;
 };
 
-// the field passes (mode 0: a step's; kGradOnly: the gather array of the current state)
+// the field passes (mode 0: a step's; kGradOnly: the gather array of the current state);
+// after_zfwd, if given, is recorded once the forward z pass is launched
 template <typename T>
-void enqueue_fft(const FftGroup<T>* groups, int ng, hipStream_t st, int mode) {
+void enqueue_fft(const FftGroup<T>* groups, int ng, hipStream_t st, int mode,
+                 hipEvent_t after_zfwd = nullptr) {
   for (int i = 0; i < ng; ++i)
     launch_zfwd<T>(groups[i].b, groups[i].tot[K_ZFWD], groups[i].lg, st, mode);
+  if (after_zfwd) (void)hipEventRecord(after_zfwd, st);
   for (int i = 0; i < ng; ++i)
     launch_yfwd<T>(groups[i].b, groups[i].tot[K_YFWD], groups[i].lg, st, mode);
   for (int i = 0; i < ng; ++i)
@@ -241,8 +247,11 @@ void enqueue_fft(const FftGroup<T>* groups, int ng, hipStream_t st, int mode) {
 // initialisation) formed and deposits into the other ubar buffer, while the field passes read
 // ubar^n and form the next gather array.  With a fork the two halves run side by side: the
 // field passes on the second stream, the binning (when due) and the particle pass on the
-// first; the finalize kernel (diagnostics, step index) waits for both.  Without one they run
-// in sequence on st.
+// first; the finalize kernel (diagnostics, step index) waits for both.  The particle pass
+// starts once the forward z pass is done: the particle blocks take every CU's LDS, and a z
+// pass started beside them ran at a fraction of its speed (128^3 / 2^23 float32: 207.9 ->
+// 202.9 us per step; starting it after the plane pass as well took 209.7).  Without a fork
+// the passes run in sequence on st.
 template <typename T>
 void enqueue_step(const Batch<T>& b, const int* tot, int nsims, const FftGroup<T>* groups,
                   int ngroups, int bin, int order, int dim, hipStream_t st,
@@ -250,12 +259,13 @@ void enqueue_step(const Batch<T>& b, const int* tot, int nsims, const FftGroup<T
   if (fk) {
     (void)hipEventRecord(fk->fork, st);
     (void)hipStreamWaitEvent(fk->aux, fk->fork, 0);
-    enqueue_fft<T>(groups, ngroups, fk->aux, 0);
+    enqueue_fft<T>(groups, ngroups, fk->aux, 0, fk->zfwd);
     (void)hipEventRecord(fk->join, fk->aux);
   } else {
     enqueue_fft<T>(groups, ngroups, st, 0);
   }
   if (bin) launch_binning<T>(b, tot, nsims, dim, st);
+  if (fk) (void)hipStreamWaitEvent(st, fk->zfwd, 0);
   launch_particles<T>(b, tot[K_PART], bin ? 1 : 0, 0, order, dim, st);
   if (fk) (void)hipStreamWaitEvent(st, fk->join, 0);
   launch_finalize<T>(b, nsims, st);
