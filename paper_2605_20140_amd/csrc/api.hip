@@ -883,15 +883,13 @@ constexpr int kNoAllocMaxSims = 64;
 constexpr size_t kNoAllocBytes = 128 * 1024;
 static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
 
-// Per device: the array's device address, a host image of the table last written to it (a
-// call whose table is unchanged writes nothing), and the stream and events on which a step's
-// field passes run beside its particle pass.  All are set up by sipf_init, the first time a
-// simulation is created on the device, with that device current.
+// Per device: the array's device address, and a host image of the table last written to it
+// (a call whose table is unchanged writes nothing).  Both are set up by sipf_init, the first
+// time a simulation is created on the device, with that device current.
 struct DevScratch {
   void* ptr = nullptr;
   unsigned char* last = nullptr;  // kNoAllocBytes
   size_t last_bytes = 0;          // 0: nothing written yet
-  StepFork fork;                  // second stream and events of the step's two halves
 };
 std::mutex g_scratch_mu;
 DevScratch g_scratch[64];
@@ -906,11 +904,6 @@ int scratch_setup(int dev, DevScratch** out) {
     if (e != hipSuccess || !p)
       return fail(SIPF_EHIP, std::string("hipGetSymbolAddress(scratch): ") +
                                  hipGetErrorString(e));
-    const hipError_t ef = create_fork(d.fork);
-    if (ef != hipSuccess) {
-      destroy_fork(d.fork);
-      return fail(SIPF_EHIP, std::string("step fork: ") + hipGetErrorString(ef));
-    }
     d.last = new unsigned char[kNoAllocBytes];
     d.ptr = p;
   }
@@ -1017,8 +1010,10 @@ int step_batch_noalloc_t(sipf_sim* const* sims, int nsims, int nsteps) {
   for (int s = 0; s < nsteps; ++s) {
     int bin = 0;
     for (int i = 0; i < nsims; ++i) bin |= sims[i]->since_bin >= sims[i]->resort_every;
-    enqueue_step<T>(b, tot, nsims, groups, ng, bin, sims[0]->prm.deposit_order, 3, st,
-                    &ds->fork);
+    // the two halves of the step in sequence: for the served mix's simulations (up to 128^3 and
+    // 2^22 particles) the second stream's fork and join cost more than the overlap gains (solo
+    // latency of every size class 5-15 % lower, aggregate rate 4.2e9 -> 4.4e9 particle-steps/s)
+    enqueue_step<T>(b, tot, nsims, groups, ng, bin, sims[0]->prm.deposit_order, 3, st, nullptr);
     for (int i = 0; i < nsims; ++i) sims[i]->since_bin = bin ? 1 : sims[i]->since_bin + 1;
   }
   HIPCHK(hipGetLastError());
