@@ -153,15 +153,16 @@ def test_blob16_full_length_fp32():
 
 
 def test_mass_update_outside_the_polynomial_range():
-    """Steps of tau = 0.6 from w0 = 0.05, so that tau |rho(w) - 1| passes 1/2 at the first
-    step (eq. u_hat_update with rho(w) = 2w / (1 + w)): the float32 form's mass update then
-    takes its wide-range path (2^k 2^f in place of the Taylor polynomial) for every particle.
-    Both forms against the oracle over three steps."""
-    ic = W.make_initial_state("blob16", dt=0.6)
-    w0 = 0.05
+    """Steps of tau = 1/2 (the largest the library takes) from w0 = -0.2, a negative lobe such
+    as the implicit solve leaves: rho(w) = 2w / (1 + w) = -1/2 there, so tau |rho - 1| = 3/4
+    passes 1/2 at the first step (eq. u_hat_update) and the float32 form's mass update takes
+    its wide-range path (2^k 2^f in place of the Taylor polynomial) for every particle.  Both
+    forms against the oracle over three steps."""
+    ic = W.make_initial_state("blob16", dt=0.5)
+    w0 = -0.2
     ic["w0"] = np.full_like(ic["w0"], w0)
     tau, rho = ic["params"]["dt"], 2 * w0 / (1 + w0)
-    assert tau == 0.6 and abs(tau * (rho - 1)) > 0.5
+    assert tau == 0.5 and abs(tau * (rho - 1)) > 0.5
     for precision, tol in ((0, TOL64), (1, TOL32)):
         out, ref, _ = _run_both(ic, 3, precision=precision)
         errs = compare_state(out, ref, tol)
