@@ -105,7 +105,8 @@ typedef struct {
   double min_a, max_a;
   double min_u;          /* min_q ubar_q (>= 0 for the trilinear assignment only: R_h^(4)   *
                           * has negative outer weights)                                     */
-  int64_t n_nan;         /* non-finite values among particles and fields                   */
+  int64_t n_nan;         /* particles with a non-finite mass or position, plus nodes with a *
+                          * non-finite ubar, plus nodes with a non-finite v, m or w         */
   int64_t n_neg_m, n_neg_w;
   int64_t step;          /* absolute step index n of the state                             */
 } sipf_diag;
@@ -132,8 +133,8 @@ int sipf_init(const sipf_params* prm, void* d_workspace, size_t bytes, void* hip
               const double* w0, sipf_sim** out);
 
 /* Enqueue nsteps >= 0 steps (Alg. sipf-pic loop body) on the simulation's stream; returns
- * without waiting.  Each step also recomputes the diagnostics (the kernels that write a
- * value reduce it as they go).  The first call with nsteps > 0 captures the step as HIP
+ * without waiting.  The steps reduce no diagnostics: sipf_fields reduces them from the
+ * state it reads.  The first call with nsteps > 0 captures the step as HIP
  * graphs (host work only; captures are serialised across threads), which later calls
  * replay.  Errors: SIPF_EINVAL, SIPF_EHIP. */
 int sipf_step(sipf_sim* sim, int32_t nsteps);
@@ -190,7 +191,7 @@ int sipf_aux(sipf_sim* sim, double* u_bar, double* grad_v);
 #define SIPF_STAGE_YINV 3      /* inverse y transforms + d2 v                */
 #define SIPF_STAGE_ZINV 4      /* inverse z transforms + d3 v, field writes  */
 #define SIPF_STAGE_PARTICLES 5 /* gather + push + mass update + deposit      */
-#define SIPF_STAGE_FINALIZE 6  /* diagnostics buffer swap, step index        */
+#define SIPF_STAGE_FINALIZE 6  /* step index                                 */
 #define SIPF_STAGE_BINNING 7   /* tile binning of the particles (when due)   */
 int sipf_step_timed(sipf_sim* sim, int32_t nsteps, float* stage_ms);
 
@@ -206,8 +207,8 @@ int sipf_step_timed(sipf_sim* sim, int32_t nsteps, float* stage_ms);
  * (j, n, sim_id_lo, sim_id_hi | 2^31), key (seed_lo, seed_hi), and selects the particle whose
  * interval of the running sum of R holds floor((r0 + 2^32 r1) sum_p R_p / 2^64) (uniformly
  * over all P if every R_p is 0).  Positions are copied unchanged (in SIPF_FP32, the float32
- * positions of the state).  The deposited density and the diagnostics are recomputed for
- * the new particles; the fields and the step index are unchanged.  Synchronous; info (may be
+ * positions of the state).  The deposited density is recomputed for the new particles; the
+ * fields and the step index are unchanged.  Synchronous; info (may be
  * NULL) receives a0 and the two counts.  P = 0 is a no-op.
  * Errors: SIPF_EINVAL (P >= 2^31; sim_id >= 2^63; a mass negative or not finite; total mass
  * zero; largest mass outside [2^-775, 2^990) or a non-zero mass below 2^-160 of the largest:

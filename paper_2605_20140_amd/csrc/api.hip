@@ -499,7 +499,6 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   enqueue_fft<T>(groups.data(), (int)groups.size(), st, kGradOnly);
   launch_particles<T>(b, sim->counts[K_PART], 0, 1, p.deposit_order, dim, st);  // ubar^0
   launch_diag_clear<T>(b, 1, st);
-  launch_diag_init<T>(b, sim->counts[K_DIAG], 1, st);
   HIPCHK(hipGetLastError());
   HIPCHK(hipStreamSynchronize(st));  // host staging buffers are freed on return
   return SIPF_OK;
@@ -601,22 +600,17 @@ int fields_t(sipf_sim* sim, double* v, double* m, double* w, double* X, double* 
       for (int64_t i = 0; i < P; ++i) a[id[i]] = ha[i];
     }
   }
-  // read-time reduction of the particles and the deposited density into buffer 2
+  // diagnostics: one reduction over the particles, ubar and the fields of the state
   {
     const Batch<T> b = single_batch<T>(sim);
-    launch_diag_u<T>(b, sim->counts[K_DIAG], 1, sim->stream);
+    launch_diag_read<T>(b, sim->counts[K_DIAG], 1, sim->stream);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(sim->stream));
   }
-  unsigned long long all[2 * kStripeWords];
-  uint64_t step = 0;
-  HIPCHK(hipMemcpy(all, d.diag + kDiagResult, sizeof(all), hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(&step, d.step, sizeof(step), hipMemcpyDeviceToHost));
   unsigned long long acc[D_COUNT];
-  memcpy(acc, all, sizeof(acc));
-  const unsigned long long* ub = all + kStripeWords;
-  for (int sl : {D_SUM_A, D_MIN_A, D_MAX_A, D_SUM_U, D_MIN_U}) acc[sl] = ub[sl];
-  acc[D_NAN] += ub[D_NAN];
+  uint64_t step = 0;
+  HIPCHK(hipMemcpy(acc, d.diag + kDiagResult, sizeof(acc), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(&step, d.step, sizeof(step), hipMemcpyDeviceToHost));
   sipf_diag dg;
   dg.mass_particles = as_double(acc[D_SUM_A]);
   dg.mass_grid = as_double(acc[D_SUM_U]) * d.h3;
@@ -1114,7 +1108,6 @@ int resample_t(sipf_sim* sim, sipf_resample_info* info) {
   HIPCHK(hipMemsetAsync(d.ubar[n & 1], 0, G * sizeof(T), st));
   launch_particles<T>(b, sim->counts[K_PART], 0, 1, p.deposit_order, dim, st);
   launch_diag_clear<T>(b, 1, st);
-  launch_diag_init<T>(b, sim->counts[K_DIAG], 1, st);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(head, rs, sizeof(head), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));

@@ -2,12 +2,13 @@
 // mass; partition of unity: h^3 sum ubar equals it), minima / maxima for the positivity
 // lemma and Lemma mass, and counts of non-finite and negative values.
 //
-// Per step, the field passes fold the values they write into the diagnostics (zfwd: v; zinv:
-// m, w), into striped accumulator copies; the one-block finalize kernel at the end of the step
-// folds the copies into the diagnostics of the new state, clears them and advances the step
-// index.  The particles (masses, positions) and the deposited density ubar are reduced when
-// the diagnostics are read, into words of their own: the particle pass, bound by instruction
-// issue, carries no per-particle reduction, and ubar is complete only after its last atomic.
+// The diagnostics describe the state they are read from, so they are reduced when they are
+// read: one pass over the particles (masses, positions), the deposited density ubar and the
+// fields v, m, w folds into striped accumulator copies, and a one-block kernel folds the
+// copies into the result words and clears them.  The step's own passes carry no reduction
+// (the particle pass and the z passes are bound by instruction issue, and ubar is complete
+// only after the particle pass's last atomic); the kernel that ends a step only advances the
+// step index.
 #include "diag_acc.h"
 
 namespace sipf {
@@ -17,15 +18,18 @@ __device__ __forceinline__ unsigned long long slot_identity(int sl) {
   return 0ull;
 }
 
-// Fold the accumulator copies into the result words and clear them.  mode 0: end of a step
-// (state diagnostics, then advance the step index); 1: initialisation (state diagnostics,
-// no advance); 2: read-time reduction of ubar (into its own words).  One block of
-// kStripes * kStripeWords threads per simulation: every thread loads one word.
+// Fold the accumulator copies into the result words and clear them (one block of
+// kStripes * kStripeWords threads per simulation: every thread loads one word); with
+// step_end, only advance the step index.
 constexpr int kFinThreads = kStripes * kStripeWords;
 
 template <typename T>
-__global__ void __launch_bounds__(kFinThreads) k_diag_finalize(Batch<T> bt, int mode) {
+__global__ void __launch_bounds__(kFinThreads) k_diag_finalize(Batch<T> bt, int step_end) {
   SimC<T>& d = sim_view(bt, (int)blockIdx.x);
+  if (step_end) {
+    if (threadIdx.x == 0) *d.step += 1;
+    return;
+  }
   __shared__ unsigned long long w[kFinThreads];
   const int t = threadIdx.x;
   const int sl = t % kStripeWords;
@@ -51,10 +55,7 @@ __global__ void __launch_bounds__(kFinThreads) k_diag_finalize(Batch<T> bt, int 
         r = cnt ? r + v : (mx ? (v > r ? v : r) : (v < r ? v : r));
       }
     }
-    if (lane == 0) {
-      d.diag[(mode == 2 ? kDiagResultU : kDiagResult) + slot] = r;
-      if (slot == 0 && mode == 0) *d.step += 1;
-    }
+    if (lane == 0) d.diag[kDiagResult + slot] = r;
   }
 }
 
@@ -133,32 +134,22 @@ void launch_diag_clear(const Batch<T>& b, int nsims, hipStream_t st) {
 }
 
 template <typename T>
-void launch_diag_init(const Batch<T>& b, int nblk, int nsims, hipStream_t st) {
+void launch_diag_read(const Batch<T>& b, int nblk, int nsims, hipStream_t st) {
   if (nblk > 0)
     hipLaunchKernelGGL(k_diag_full<T>, dim3(nblk), dim3(kThreads), 0, st, b,
-                       kDiagParticles | kDiagGrid);
-  hipLaunchKernelGGL(k_diag_finalize<T>, dim3(nsims), dim3(kFinThreads), 0, st, b, 1);
-}
-
-template <typename T>
-void launch_diag_u(const Batch<T>& b, int nblk, int nsims, hipStream_t st) {
-  if (nblk > 0)
-    hipLaunchKernelGGL(k_diag_full<T>, dim3(nblk), dim3(kThreads), 0, st, b,
-                       kDiagParticles | kDiagU);
-  hipLaunchKernelGGL(k_diag_finalize<T>, dim3(nsims), dim3(kFinThreads), 0, st, b, 2);
+                       kDiagParticles | kDiagGrid | kDiagU);
+  hipLaunchKernelGGL(k_diag_finalize<T>, dim3(nsims), dim3(kFinThreads), 0, st, b, 0);
 }
 
 template <typename T>
 void launch_finalize(const Batch<T>& b, int nsims, hipStream_t st) {
-  hipLaunchKernelGGL(k_diag_finalize<T>, dim3(nsims), dim3(kFinThreads), 0, st, b, 0);
+  hipLaunchKernelGGL(k_diag_finalize<T>, dim3(nsims), dim3(64), 0, st, b, 1);
 }
 
 template void launch_diag_clear<double>(const Batch<double>&, int, hipStream_t);
 template void launch_diag_clear<float>(const Batch<float>&, int, hipStream_t);
-template void launch_diag_init<double>(const Batch<double>&, int, int, hipStream_t);
-template void launch_diag_init<float>(const Batch<float>&, int, int, hipStream_t);
-template void launch_diag_u<double>(const Batch<double>&, int, int, hipStream_t);
-template void launch_diag_u<float>(const Batch<float>&, int, int, hipStream_t);
+template void launch_diag_read<double>(const Batch<double>&, int, int, hipStream_t);
+template void launch_diag_read<float>(const Batch<float>&, int, int, hipStream_t);
 template void launch_finalize<double>(const Batch<double>&, int, hipStream_t);
 template void launch_finalize<float>(const Batch<float>&, int, hipStream_t);
 

@@ -43,7 +43,7 @@
 // is folded into the multipliers.
 #include <algorithm>
 
-#include "diag_acc.h"
+#include "sipf_internal.h"
 
 namespace sipf {
 
@@ -149,7 +149,10 @@ __device__ __forceinline__ void reg_dft(cplx<T> (&a)[R]) {
       const int ti = k * (32 >> (s + 1));
       const cplx<T> u = a[i0];
       cplx<T> v = a[i0 + hs];
-      if (k != 0) v = cmul(v, cplx<T>{(T)kW32[ti].c, (T)(-DIR * kW32[ti].s)});
+      if (ti == 8)  // the twiddle is -DIR i: a swap of the parts and one sign, no products
+        v = DIR > 0 ? cplx<T>{v.y, -v.x} : cplx<T>{-v.y, v.x};
+      else if (k != 0)
+        v = cmul(v, cplx<T>{(T)kW32[ti].c, (T)(-DIR * kW32[ti].s)});
       a[i0] = cadd(u, v);
       a[i0 + hs] = csub(u, v);
     }
@@ -196,11 +199,25 @@ __device__ __forceinline__ int ufpos(int p) {
   return (p >> S::L1) + ((p & (S::N1 - 1)) << S::L2);
 }
 
-// W_N^e (DIR +1) or W_N^{-e} (DIR -1) for 0 <= e < N from tw[k] = W_N^k, k < N/2
+// Entries of a pass's twiddle table in LDS: all N powers W_N^k up to N = 512, so that a
+// twiddle is one load; at N = 1024 (the 2D form's largest rows) the N/2 of the first half
+// only, which keeps its blocks' LDS within the occupancy they have (the second half is the
+// first negated).
+template <int LG>
+constexpr int tw_len() {
+  return LG <= 9 ? (1 << LG) : (1 << LG) >> 1;
+}
+inline int tw_len_rt(int lg) { return lg <= 9 ? (1 << lg) : (1 << lg) >> 1; }
+
+// W_N^e (DIR +1) or W_N^{-e} (DIR -1) for 0 <= e < N from the table tw[k] = W_N^k
 template <typename T, int LG, int DIR>
 __device__ __forceinline__ cplx<T> twid(const cplx<T>* tw, int e) {
   constexpr int H = (1 << LG) >> 1;
-  cplx<T> w = e < H ? tw[e] : cplx<T>{-tw[e - H].x, -tw[e - H].y};
+  cplx<T> w;
+  if (tw_len<LG>() == (1 << LG))
+    w = tw[e];
+  else
+    w = e < H ? tw[e] : cplx<T>{-tw[e - H].x, -tw[e - H].y};
   if (DIR < 0) w.y = -w.y;
   return w;
 }
@@ -326,10 +343,18 @@ __device__ __forceinline__ void line_round_trip(cplx<T>* buf, int nlines, int ls
   fwd_stage1<T, LG, LINE_FAST, NT>(buf, nlines, ls, es, tw);
   if (LG > 7) {
     fwd_stage2<T, LG, LINE_FAST, NT>(buf, nlines, ls, es);
-    for (int e = threadIdx.x; e < (nlines << LG); e += NT) {
-      const int line = e >> LG, p = e & ((1 << LG) - 1);
-      cplx<T>* q = buf + line * ls + p * es;
-      *q = mul(line, p, *q);
+    if (NT % (1 << LG) == 0) {  // each thread keeps one position p on every line it visits
+      const int p = threadIdx.x & ((1 << LG) - 1);
+      for (int line = threadIdx.x >> LG; line < nlines; line += NT >> LG) {
+        cplx<T>* q = buf + line * ls + p * es;
+        *q = mul(line, p, *q);
+      }
+    } else {
+      for (int e = threadIdx.x; e < (nlines << LG); e += NT) {
+        const int line = e >> LG, p = e & ((1 << LG) - 1);
+        cplx<T>* q = buf + line * ls + p * es;
+        *q = mul(line, p, *q);
+      }
     }
     __syncthreads();
     line_inv<T, LG, LINE_FAST, NT>(buf, nlines, ls, es, tw);
@@ -354,9 +379,16 @@ __device__ __forceinline__ void line_round_trip(cplx<T>* buf, int nlines, int ls
   inv_stage2<T, LG, LINE_FAST, NT>(buf, nlines, ls, es);
 }
 
-template <typename T>
+// The pass's LDS twiddle table (tw_len entries) from the N/2 values W_N^k, k < N/2, in
+// global memory: W_N^{k + N/2} = -W_N^k.
+template <typename T, int LG>
 __device__ __forceinline__ void load_twiddles(cplx<T>* tw, SimC<T>& d) {
-  for (int k = threadIdx.x; k < (d.N >> 1); k += kThreads) tw[k] = d.tw[k];
+  constexpr int H = (1 << LG) >> 1;
+  for (int k = threadIdx.x; k < H; k += kThreads) {
+    const cplx<T> v = d.tw[k];
+    tw[k] = v;
+    if (tw_len<LG>() > H) tw[k + H] = cplx<T>{-v.x, -v.y};
+  }
 }
 
 // The N/2 twiddles in two steps, so that their loads join a batch of other loads: issue them
@@ -377,10 +409,14 @@ struct TwiddleRegs {
     }
   }
   __device__ __forceinline__ void store(cplx<T>* twl) const {
+    constexpr int H = (1 << LG) >> 1;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const int t = threadIdx.x + k * NT;
-      if (t < ((1 << LG) >> 1)) twl[t] = cplx<T>{x[k], y[k]};
+      if (t < H) {
+        twl[t] = cplx<T>{x[k], y[k]};
+        if (tw_len<LG>() > H) twl[t + H] = cplx<T>{-x[k], -y[k]};
+      }
     }
   }
 };
@@ -433,9 +469,15 @@ __device__ __forceinline__ int lap_freq(int k, int N) { return k < (N >> 1) ? k 
 // M - 1 instead of reaching f^{n+1} in full at every step (with float32 transforms it would
 // accumulate in m and w, and through v' = v exp(-alpha tau m) in v).
 // Implicit multiplier, c = tau (R + D |k|^2): M - 1 = lp / (1 + c) - 1 = (lp - 1 - c) / (1 + c).
+// In float32 the quotient takes the hardware reciprocal (within 1 ulp; 1 + c >= 1) instead of
+// the correctly rounded division sequence: about ten instructions less per mode.
 template <typename T>
 __device__ __forceinline__ T solve_multiplier(T c, T lp) {
   return (lp - (T)1 - c) / ((T)1 + c);
+}
+template <>
+__device__ __forceinline__ float solve_multiplier<float>(float c, float lp) {
+  return (lp - 1.0f - c) * __builtin_amdgcn_rcpf(1.0f + c);
 }
 // the same for a tabulated multiplier M (exponential or aliased kernel)
 template <typename T>
@@ -462,8 +504,6 @@ __device__ __forceinline__ void zfwd_body(SimC<T>& d, int lb, unsigned char* sme
   const bool impl_v = d.flags & SIPF_FLAG_IMPLICIT_V;
   const bool grad_only = mode == kGradOnly;
   T* const ub = d.ubar[(uint32_t)(*d.step) & 1u];  // ubar^n
-  Acc acc;
-  acc_init(acc);
   // ZBatch elements per thread have their loads in flight together (the stores to v and ubar
   // would otherwise order each element's loads after the previous element's stores)
   constexpr int ZB = ZBatch<T>::n;
@@ -505,7 +545,6 @@ __device__ __forceinline__ void zfwd_body(SimC<T>& d, int lb, unsigned char* sme
           vn = impl_v ? vv[k] - vv[k] * (y / ((T)1 + y)) : fma(vv[k], expm1(-y), vv[k]);
           d.v[g0 + e] = vn;
         }
-        if (isfinite((double)vn)) acc_min(acc, D_MIN_V, (double)vn); else acc.cnt[0] += 1;
         // w* goes into ubar^n's array, which this step needs no more: the inverse pass adds
         // it to the solve's change and clears the array for the next step's deposit
         ub[g0 + e] = wsr;
@@ -539,7 +578,6 @@ __device__ __forceinline__ void zfwd_body(SimC<T>& d, int lb, unsigned char* sme
     }
     d.SV[o] = Vv;
   }
-  if (!grad_only) acc_flush(acc, diag_stripe(d));
 }
 
 template <typename T, int LG>
@@ -606,7 +644,7 @@ __device__ __forceinline__ void yinv_body(SimC<T>& d, int lb, unsigned char* sme
     const int nl = (int)((lines - l0) < Bh ? (lines - l0) : Bh);
     const cplx<T>* SV = d.SVg + l0 * N;
     const T c = d.two_pi_over_L * d.inv_n2;
-    load_twiddles(tw, d);
+    load_twiddles<T, LG>(tw, d);
     for (int e = threadIdx.x; e < nl * N; e += kThreads) {
       const int line = e >> LG, p = e & (N - 1);
       const cplx<T> V = SV[e];
@@ -652,7 +690,7 @@ __device__ __forceinline__ void xpass_body(SimC<T>& d, int lb, unsigned char* sm
   constexpr int LS = row_stride<LG>();
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);  // Bx lines of N along i1
   cplx<T>* tw = buf + Bx * LS;
-  load_twiddles(tw, d);
+  load_twiddles<T, LG>(tw, d);
   {  // columns of the plane into LDS lines, CopyBatch loads per thread in flight together
     constexpr int CB = CopyBatch<T>::n;
     const int n = Bx * N;
@@ -979,8 +1017,6 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
   tr.store(tw);
   __syncthreads();
   line_inv<T, LG, true>(MW, 2 * B + Bh, LS, 1, tw);
-  Acc acc;
-  acc_init(acc);
   for (int e0 = threadIdx.x; e0 < nel; e0 += ZB * kThreads) {
     if (e0 != (int)threadIdx.x) {  // elements beyond the first ZB per thread
 #pragma unroll
@@ -1020,21 +1056,8 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
       }
       gout[g] = vec4<T>{gg.x, gg.y, gzv, wn};  // (grad v^{n+1}, w^{n+1})
       ub[g] = (T)0;  // cleared for the deposit of the next step's particle pass
-      const double md = mn, wd = wn;
-      if (isfinite(md) && isfinite(wd)) {
-        acc.sum[2] += md;
-        acc_min(acc, D_MIN_M, md);
-        acc_min(acc, D_MAX_M, md);
-        acc_min(acc, D_MIN_W, wd);
-        acc_min(acc, D_MAX_W, wd);
-        acc.cnt[1] += md < 0.0;
-        acc.cnt[2] += wd < 0.0;
-      } else {
-        acc.cnt[0] += 1;
-      }
     }
   }
-  if (!grad_only) acc_flush(acc, diag_stripe(d));
 }
 
 template <typename T, int LG>
@@ -1054,7 +1077,7 @@ size_t fft_lds_bytes(int kind, int lg) {
   const size_t LS = (size_t)row_stride_rt(lg);    // x pass, plane
   const size_t LZ = (size_t)zy_stride_rt(lg);     // z and y passes
   const size_t c = sizeof(cplx<T>);
-  const size_t tw = (size_t)(N / 2) * c;
+  const size_t tw = (size_t)tw_len_rt(lg) * c;
   const size_t B = (size_t)std::min(N * N, std::max(zfwd_min_rows<T>(lg), E / N));  // z forward
   const size_t Bz = (size_t)std::min(N * N, std::max(2, zinv_elems<T>(N) / N));  // z inverse
   const size_t Bl = (size_t)(E / N);                // lines per block (y passes)

@@ -68,8 +68,8 @@ enum KernelKind {
 };
 
 // Diagnostic accumulator slots (uint64 words; sums stored as float64 bit patterns).
-// Layout of SimDesc::diag: kStripes accumulator copies of kStripeWords words, then the reduced
-// diagnostics of the latest state (D_COUNT words), then the read-time reduction of ubar.
+// Layout of SimDesc::diag: kStripes accumulator copies of kStripeWords words, then the
+// diagnostics of the latest read (D_COUNT words).
 enum DiagSlot {
   D_SUM_A = 0, D_SUM_U, D_SUM_M,
   D_MIN_V, D_MIN_M, D_MIN_W, D_MAX_M, D_MAX_W, D_MIN_A, D_MAX_A, D_MIN_U,
@@ -78,9 +78,8 @@ enum DiagSlot {
 };
 constexpr int kStripes = 64;
 constexpr int kStripeWords = 16;  // >= D_COUNT, 128 bytes
-constexpr int kDiagResult = kStripes * kStripeWords;   // offset of the reduced state diag
-constexpr int kDiagResultU = kDiagResult + kStripeWords;  // offset of the ubar reduction
-constexpr int kDiagWords = kDiagResultU + kStripeWords;
+constexpr int kDiagResult = kStripes * kStripeWords;  // offset of the reduced diagnostics
+constexpr int kDiagWords = kDiagResult + kStripeWords;
 
 // Pointer kinds of a descriptor.  The host writes plain pointers.  Kernels read the same
 // bytes as pointers into the global address space: a pointer loaded from memory is generic to
@@ -341,8 +340,9 @@ template <typename T>
 void launch_resample_apply(const SimDev<T>& d, unsigned long long* rs, hipStream_t s);
 template <typename T>
 void launch_binning(const Batch<T>& b, const int* tot, int nsims, int dim, hipStream_t s);
-template <typename T> void launch_diag_init(const Batch<T>& b, int nblk, int nsims, hipStream_t s);
-template <typename T> void launch_diag_u(const Batch<T>& b, int nblk, int nsims, hipStream_t s);
+// diagnostics of the current state: full reduction into the result words (read time)
+template <typename T> void launch_diag_read(const Batch<T>& b, int nblk, int nsims, hipStream_t s);
+// end of a step: advance the step index
 template <typename T> void launch_finalize(const Batch<T>& b, int nsims, hipStream_t s);
 template <typename T> void launch_diag_clear(const Batch<T>& b, int nsims, hipStream_t s);
 
