@@ -165,14 +165,7 @@ struct Split {
   static constexpr int N1 = 1 << L1, N2 = 1 << L2, N = 1 << LG;
 };
 
-// LDS row stride of N-point lines: padded so that rows 1 KB apart do not fall on the same
-// LDS banks when one wavefront transforms several rows
-template <int LG>
-constexpr int row_stride() {
-  return (1 << LG) + (LG >= 4 ? 4 : 0);
-}
-inline int row_stride_rt(int lg) { return (1 << lg) + (lg >= 4 ? 4 : 0); }
-// The z and y passes also read and write their lines across rows (one row per thread when
+// The z and y passes read and write their lines across rows (one row per thread when
 // packing spectra), so they pad by one complex value (an odd stride spreads consecutive rows
 // over all LDS banks) and map consecutive threads to consecutive lines in the transforms.
 template <int LG>
@@ -186,6 +179,24 @@ template <int LG>
 constexpr int plane_stride() {
   return (1 << LG) + 2;
 }
+// Lines whose sub-transforms run one per thread on consecutive threads (the x pass, the 2D
+// column pass) are stored skewed: position p at p + floor(p / N1), one gap after every group
+// of N1.  The second stage's threads then read their groups N1 + 1 values apart instead of
+// N1, which spreads them over the LDS banks (N1 apart, 16 threads of a wavefront met on the
+// same banks).  The odd line stride N + N2 + 1 holds the N2 - 1 gaps.
+template <int LG, bool SKEW>
+constexpr int group_stride() {
+  return Split<LG>::N1 + (SKEW ? 1 : 0);
+}
+template <int LG, bool SKEW>
+__device__ __forceinline__ int skp(int p) {
+  return SKEW ? p + (p >> Split<LG>::L1) : p;
+}
+template <int LG>
+constexpr int skew_stride() {
+  return (1 << LG) + Split<LG>::N2 + 1;
+}
+inline int skew_stride_rt(int lg) { return (1 << lg) + (1 << (lg - lg / 2)) + 1; }
 
 // position of frequency k after a forward line transform, and its inverse map
 template <int LG>
@@ -245,32 +256,34 @@ struct TaskMap {
 // N1 strided subsequences, times the twiddles; second stage: N1-point transforms of
 // contiguous groups, leaving frequency k at position fpos(k).  The inverse takes that order
 // and runs the stages the other way round.  Each stage ends at a barrier.
-template <typename T, int LG, bool LINE_FAST, int NT>
+template <typename T, int LG, bool LINE_FAST, int NT, bool SKEW = false>
 __device__ __forceinline__ void fwd_stage1(cplx<T>* buf, int nlines, int ls, int es,
                                            const cplx<T>* tw) {
   using S = Split<LG>;
+  constexpr int GS = group_stride<LG, SKEW>();
   for (int t = threadIdx.x; t < nlines * S::N1; t += NT) {
     int line, n1;
     TaskMap<LG, LINE_FAST>::template map<S::L1>(t, nlines, line, n1);
     cplx<T>* Lp = buf + line * ls + n1 * es;
     cplx<T> a[S::N2];
 #pragma unroll
-    for (int n2 = 0; n2 < S::N2; ++n2) a[n2] = Lp[(n2 << S::L1) * es];
+    for (int n2 = 0; n2 < S::N2; ++n2) a[n2] = Lp[n2 * GS * es];
     reg_dft<T, S::N2, 1>(a);
     Lp[0] = a[0];
 #pragma unroll
     for (int k2 = 1; k2 < S::N2; ++k2)
-      Lp[(k2 << S::L1) * es] = cmul(a[k2], twid<T, LG, 1>(tw, n1 * k2));
+      Lp[k2 * GS * es] = cmul(a[k2], twid<T, LG, 1>(tw, n1 * k2));
   }
   __syncthreads();
 }
-template <typename T, int LG, bool LINE_FAST, int NT>
+template <typename T, int LG, bool LINE_FAST, int NT, bool SKEW = false>
 __device__ __forceinline__ void fwd_stage2(cplx<T>* buf, int nlines, int ls, int es) {
   using S = Split<LG>;
+  constexpr int GS = group_stride<LG, SKEW>();
   for (int t = threadIdx.x; t < nlines * S::N2; t += NT) {
     int line, k2;
     TaskMap<LG, LINE_FAST>::template map<S::L2>(t, nlines, line, k2);
-    cplx<T>* Lp = buf + line * ls + (k2 << S::L1) * es;
+    cplx<T>* Lp = buf + line * ls + k2 * GS * es;
     cplx<T> a[S::N1];
 #pragma unroll
     for (int n1 = 0; n1 < S::N1; ++n1) a[n1] = Lp[n1 * es];
@@ -280,14 +293,15 @@ __device__ __forceinline__ void fwd_stage2(cplx<T>* buf, int nlines, int ls, int
   }
   __syncthreads();
 }
-template <typename T, int LG, bool LINE_FAST, int NT>
+template <typename T, int LG, bool LINE_FAST, int NT, bool SKEW = false>
 __device__ __forceinline__ void inv_stage1(cplx<T>* buf, int nlines, int ls, int es,
                                            const cplx<T>* tw) {
   using S = Split<LG>;
+  constexpr int GS = group_stride<LG, SKEW>();
   for (int t = threadIdx.x; t < nlines * S::N2; t += NT) {
     int line, a2;
     TaskMap<LG, LINE_FAST>::template map<S::L2>(t, nlines, line, a2);
-    cplx<T>* Lp = buf + line * ls + (a2 << S::L1) * es;
+    cplx<T>* Lp = buf + line * ls + a2 * GS * es;
     cplx<T> v[S::N1];
 #pragma unroll
     for (int b = 0; b < S::N1; ++b) v[b] = Lp[b * es];
@@ -298,19 +312,20 @@ __device__ __forceinline__ void inv_stage1(cplx<T>* buf, int nlines, int ls, int
   }
   __syncthreads();
 }
-template <typename T, int LG, bool LINE_FAST, int NT>
+template <typename T, int LG, bool LINE_FAST, int NT, bool SKEW = false>
 __device__ __forceinline__ void inv_stage2(cplx<T>* buf, int nlines, int ls, int es) {
   using S = Split<LG>;
+  constexpr int GS = group_stride<LG, SKEW>();
   for (int t = threadIdx.x; t < nlines * S::N1; t += NT) {
     int line, c;
     TaskMap<LG, LINE_FAST>::template map<S::L1>(t, nlines, line, c);
     cplx<T>* Lp = buf + line * ls + c * es;
     cplx<T> v[S::N2];
 #pragma unroll
-    for (int a2 = 0; a2 < S::N2; ++a2) v[a2] = Lp[(a2 << S::L1) * es];
+    for (int a2 = 0; a2 < S::N2; ++a2) v[a2] = Lp[a2 * GS * es];
     reg_dft<T, S::N2, -1>(v);
 #pragma unroll
-    for (int dd = 0; dd < S::N2; ++dd) Lp[(dd << S::L1) * es] = v[dd];
+    for (int dd = 0; dd < S::N2; ++dd) Lp[dd * GS * es] = v[dd];
   }
   __syncthreads();
 }
@@ -322,10 +337,10 @@ __device__ __forceinline__ void line_fwd(cplx<T>* buf, int nlines, int ls, int e
   fwd_stage2<T, LG, LINE_FAST, NT>(buf, nlines, ls, es);
 }
 // inverse transforms (unnormalised): fpos order -> natural order
-template <typename T, int LG, bool LINE_FAST = false, int NT = kThreads>
+template <typename T, int LG, bool LINE_FAST = false, int NT = kThreads, bool SKEW = false>
 __device__ __forceinline__ void line_inv(cplx<T>* buf, int nlines, int ls, int es, const cplx<T>* tw) {
-  inv_stage1<T, LG, LINE_FAST, NT>(buf, nlines, ls, es, tw);
-  inv_stage2<T, LG, LINE_FAST, NT>(buf, nlines, ls, es);
+  inv_stage1<T, LG, LINE_FAST, NT, SKEW>(buf, nlines, ls, es, tw);
+  inv_stage2<T, LG, LINE_FAST, NT, SKEW>(buf, nlines, ls, es);
 }
 
 // Forward transform, pointwise multiplier and inverse transform of nlines lines.  The
@@ -336,34 +351,35 @@ __device__ __forceinline__ void line_inv(cplx<T>* buf, int nlines, int ls, int e
 // (Above 128 points the two transforms and the multiplier in registers cost more registers
 // than the pass saves - the x pass at 256 points went from 7 to 3 waves per SIMD in float32
 // - so there the multiplier is a pass of its own.)
-template <typename T, int LG, bool LINE_FAST, int NT, typename Mul>
+template <typename T, int LG, bool LINE_FAST, int NT, bool SKEW = false, typename Mul>
 __device__ __forceinline__ void line_round_trip(cplx<T>* buf, int nlines, int ls, int es,
                                                 const cplx<T>* tw, const Mul& mul) {
   using S = Split<LG>;
-  fwd_stage1<T, LG, LINE_FAST, NT>(buf, nlines, ls, es, tw);
+  constexpr int GS = group_stride<LG, SKEW>();
+  fwd_stage1<T, LG, LINE_FAST, NT, SKEW>(buf, nlines, ls, es, tw);
   if (LG > 7) {
-    fwd_stage2<T, LG, LINE_FAST, NT>(buf, nlines, ls, es);
+    fwd_stage2<T, LG, LINE_FAST, NT, SKEW>(buf, nlines, ls, es);
     if (NT % (1 << LG) == 0) {  // each thread keeps one position p on every line it visits
       const int p = threadIdx.x & ((1 << LG) - 1);
       for (int line = threadIdx.x >> LG; line < nlines; line += NT >> LG) {
-        cplx<T>* q = buf + line * ls + p * es;
+        cplx<T>* q = buf + line * ls + skp<LG, SKEW>(p) * es;
         *q = mul(line, p, *q);
       }
     } else {
       for (int e = threadIdx.x; e < (nlines << LG); e += NT) {
         const int line = e >> LG, p = e & ((1 << LG) - 1);
-        cplx<T>* q = buf + line * ls + p * es;
+        cplx<T>* q = buf + line * ls + skp<LG, SKEW>(p) * es;
         *q = mul(line, p, *q);
       }
     }
     __syncthreads();
-    line_inv<T, LG, LINE_FAST, NT>(buf, nlines, ls, es, tw);
+    line_inv<T, LG, LINE_FAST, NT, SKEW>(buf, nlines, ls, es, tw);
     return;
   }
   for (int t = threadIdx.x; t < nlines * S::N2; t += NT) {
     int line, k2;
     TaskMap<LG, LINE_FAST>::template map<S::L2>(t, nlines, line, k2);
-    cplx<T>* Lp = buf + line * ls + (k2 << S::L1) * es;
+    cplx<T>* Lp = buf + line * ls + k2 * GS * es;
     cplx<T> a[S::N1];
 #pragma unroll
     for (int n1 = 0; n1 < S::N1; ++n1) a[n1] = Lp[n1 * es];
@@ -376,7 +392,7 @@ __device__ __forceinline__ void line_round_trip(cplx<T>* buf, int nlines, int ls
     for (int c = 1; c < S::N1; ++c) Lp[c * es] = cmul(a[c], twid<T, LG, -1>(tw, c * k2));
   }
   __syncthreads();
-  inv_stage2<T, LG, LINE_FAST, NT>(buf, nlines, ls, es);
+  inv_stage2<T, LG, LINE_FAST, NT, SKEW>(buf, nlines, ls, es);
 }
 
 // The pass's LDS twiddle table (tw_len entries) from the N/2 values W_N^k, k < N/2, in
@@ -428,7 +444,7 @@ template <typename T> struct CopyBatch { static constexpr int n = 32 / (int)size
 // and (unless twg is null) the N/2 twiddles into twl.  The loads of CopyBatch values per thread (and of the
 // twiddles) are in flight together: a plain loop waits for each load before its LDS store,
 // one memory round trip per value.  Component arrays keep the batch in registers.
-template <typename T, int LG, int NT>
+template <typename T, int LG, int NT, bool SKEW = false>
 __device__ __forceinline__ void rows_in(cplx<T>* buf, int LS, const cplx<T>* src, int n,
                                         cplx<T>* twl, const cplx<T>* twg) {
   constexpr int N = 1 << LG;
@@ -449,7 +465,7 @@ __device__ __forceinline__ void rows_in(cplx<T>* buf, int LS, const cplx<T>* src
 #pragma unroll
     for (int k = 0; k < B; ++k) {
       const int e = e0 + k * NT;
-      if (e < n) buf[(e >> LG) * LS + (e & (N - 1))] = cplx<T>{vx[k], vy[k]};
+      if (e < n) buf[(e >> LG) * LS + skp<LG, SKEW>(e & (N - 1))] = cplx<T>{vx[k], vy[k]};
     }
   }
   if (twg) tr.store(twl);
@@ -559,8 +575,9 @@ __device__ __forceinline__ void zfwd_body(SimC<T>& d, int lb, unsigned char* sme
   __syncthreads();
   line_fwd<T, LG, true>(A, B + (B >> 1), LS, 1, tw);
   constexpr int H = (N >> 1) + 1;
+  const int lgB = __builtin_ctz((unsigned)B);  // B is a power of two: no vector division
   for (int e = threadIdx.x; e < H * B; e += kThreads) {
-    const int kz = e / B, rr = e - kz * B;
+    const int kz = e >> lgB, rr = e & (B - 1);
     const int pk = fpos<LG>(kz), pc = fpos<LG>((N - kz) & (N - 1));
     const int64_t o = (int64_t)kz * N2 + r0 + rr;
     const cplx<T> Z = A[rr * LS + pk], Zc = cconj(A[rr * LS + pc]);
@@ -684,11 +701,12 @@ __device__ __forceinline__ void xpass_body(SimC<T>& d, int lb, unsigned char* sm
   const int rem = lb - f * per_field;
   const int kz = rem / ncb;
   const int y0 = (rem - kz * ncb) * Bx;
+  const int lbx = __builtin_ctz((unsigned)Bx);  // Bx is a power of two: no vector division
   const int64_t N2 = (int64_t)N * N;
   const cplx<T>* src = (f == 0 ? d.SM : (f == 1 ? d.SW : d.SV)) + (int64_t)kz * N2;
   cplx<T>* dst = (f == 0 ? d.SM : (f == 1 ? d.SW : (f == 2 ? d.SGx : d.SVg))) + (int64_t)kz * N2;
-  constexpr int LS = row_stride<LG>();
-  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);  // Bx lines of N along i1
+  constexpr int LS = skew_stride<LG>();
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);  // Bx lines of N along i1, skewed
   cplx<T>* tw = buf + Bx * LS;
   load_twiddles<T, LG>(tw, d);
   {  // columns of the plane into LDS lines, CopyBatch loads per thread in flight together
@@ -700,7 +718,7 @@ __device__ __forceinline__ void xpass_body(SimC<T>& d, int lb, unsigned char* sm
       for (int k = 0; k < CB; ++k) {
         const int e = e0 + k * kThreads;
         if (e < n) {
-          const int c = e % Bx, ix = e / Bx;
+          const int c = e & (Bx - 1), ix = e >> lbx;
           const cplx<T> v = src[(int64_t)ix * N + y0 + c];
           vx[k] = v.x;
           vy[k] = v.y;
@@ -709,7 +727,7 @@ __device__ __forceinline__ void xpass_body(SimC<T>& d, int lb, unsigned char* sm
 #pragma unroll
       for (int k = 0; k < CB; ++k) {
         const int e = e0 + k * kThreads;
-        if (e < n) buf[(e % Bx) * LS + e / Bx] = cplx<T>{vx[k], vy[k]};
+        if (e < n) buf[(e & (Bx - 1)) * LS + skp<LG, true>(e >> lbx)] = cplx<T>{vx[k], vy[k]};
       }
     }
   }
@@ -746,10 +764,10 @@ __device__ __forceinline__ void xpass_body(SimC<T>& d, int lb, unsigned char* sm
     // low-pass filtered V for the y and z derivatives; 1/N undoes this x round trip
     return cscale(val, lpt[kx] * lpt[ky] * lpt[kz] / (T)N);
   };
-  line_round_trip<T, LG, false, kThreads>(buf, Bx, LS, 1, tw, mul);
+  line_round_trip<T, LG, false, kThreads, true>(buf, Bx, LS, 1, tw, mul);
   for (int e = threadIdx.x; e < Bx * N; e += kThreads) {
-    const int c = e % Bx, ix = e / Bx;
-    dst[(int64_t)ix * N + y0 + c] = buf[c * LS + ix];
+    const int c = e & (Bx - 1), ix = e >> lbx;
+    dst[(int64_t)ix * N + y0 + c] = buf[c * LS + skp<LG, true>(ix)];
   }
 }
 
@@ -770,10 +788,10 @@ __device__ __forceinline__ void col2d_body(SimC<T>& d, int lb, unsigned char* sm
   const int nl = H - kl0 < Bl ? H - kl0 : Bl;
   const cplx<T>* src = (f == 0 ? d.SM : (f == 1 ? d.SW : d.SV)) + (int64_t)kl0 * N;
   cplx<T>* dst = (f == 0 ? d.SM : (f == 1 ? d.SW : (f == 2 ? d.SGx : d.SVg))) + (int64_t)kl0 * N;
-  constexpr int LS = row_stride<LG>();
-  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
+  constexpr int LS = skew_stride<LG>();
+  cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);  // nl lines, skewed
   cplx<T>* tw = buf + Bl * LS;
-  rows_in<T, LG, kThreads>(buf, LS, src, nl * N, tw, d.tw);
+  rows_in<T, LG, kThreads, true>(buf, LS, src, nl * N, tw, d.tw);
   __syncthreads();
   const T k0 = d.two_pi_over_L;
   const T D = (T)(f == 0 ? d.D_m : d.D_w);
@@ -802,9 +820,9 @@ __device__ __forceinline__ void col2d_body(SimC<T>& d, int lb, unsigned char* sm
     }
     return cscale(val, lp / (T)N);
   };
-  line_round_trip<T, LG, false, kThreads>(buf, nl, LS, 1, tw, mul);
+  line_round_trip<T, LG, false, kThreads, true>(buf, nl, LS, 1, tw, mul);
   for (int e = threadIdx.x; e < nl * N; e += kThreads)
-    dst[e] = buf[(e >> LG) * LS + (e & (N - 1))];
+    dst[e] = buf[(e >> LG) * LS + skp<LG, true>(e & (N - 1))];
 }
 
 template <typename T, int LG>
@@ -964,13 +982,14 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
   // spectra of IB (k3, row pair) items per thread loaded together: 5 spectra x 2 rows each
   constexpr int IB = sizeof(T) == 4 ? 2 : 1;
   const int n1 = H * Bh;
+  const int lgBh = __builtin_ctz((unsigned)Bh);  // B is a power of two: no vector division
   for (int e0 = threadIdx.x; e0 < n1; e0 += IB * kThreads) {
     T sv[IB][2][10];  // (M, W, Gx, Gy, V) x (re, im) of rows 2q and 2q + 1
 #pragma unroll
     for (int ib = 0; ib < IB; ++ib) {
       const int e = e0 + ib * kThreads;
       if (e < n1) {
-        const int kz = e / Bh, q = e - kz * Bh;
+        const int kz = e >> lgBh, q = e & (Bh - 1);
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
           const int64_t o = (int64_t)kz * N2 + r0 + 2 * q + h;
@@ -992,7 +1011,7 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
     for (int ib = 0; ib < IB; ++ib) {
       const int e = e0 + ib * kThreads;
       if (e < n1) {
-        const int kz = e / Bh, q = e - kz * Bh;
+        const int kz = e >> lgBh, q = e & (Bh - 1);
         const bool mirror = kz > 0 && kz < (N >> 1);
         const int pk = fpos<LG>(kz), pc = fpos<LG>((N - kz) & (N - 1));
         const T kk = cz * (T)deriv_freq(kz, N);
@@ -1074,7 +1093,7 @@ template <typename T>
 size_t fft_lds_bytes(int kind, int lg) {
   const int E = elems_per_block<T>();
   const int N = 1 << lg;
-  const size_t LS = (size_t)row_stride_rt(lg);    // x pass, plane
+  const size_t LK = (size_t)skew_stride_rt(lg);   // x pass, 2D column pass
   const size_t LZ = (size_t)zy_stride_rt(lg);     // z and y passes
   const size_t c = sizeof(cplx<T>);
   const size_t tw = (size_t)tw_len_rt(lg) * c;
@@ -1086,7 +1105,7 @@ size_t fft_lds_bytes(int kind, int lg) {
     case K_ZFWD: return (B + B / 2) * LZ * c + tw;
     case K_YFWD: return Bl * LZ * c + tw;
     case K_YINV: return Bl * LZ * c + tw;
-    case K_XPASS: return Bx * LS * c + tw;
+    case K_XPASS: return Bx * LK * c + tw;
     case K_ZINV: return (2 * Bz + Bz / 2) * LZ * c + tw;
     case K_PLANE: return (size_t)N * (N + 2) * c + tw;  // plane_stride
     default: return 0;
