@@ -661,14 +661,30 @@ __device__ __forceinline__ void yinv_body(SimC<T>& d, int lb, unsigned char* sme
     const int nl = (int)((lines - l0) < Bh ? (lines - l0) : Bh);
     const cplx<T>* SV = d.SVg + l0 * N;
     const T c = d.two_pi_over_L * d.inv_n2;
-    load_twiddles<T, LG>(tw, d);
-    for (int e = threadIdx.x; e < nl * N; e += kThreads) {
-      const int line = e >> LG, p = e & (N - 1);
-      const cplx<T> V = SV[e];
-      const T kk = c * (T)deriv_freq(ufpos<LG>(p), N);
-      buf[(2 * line) * LS + p] = V;
-      buf[(2 * line + 1) * LS + p] = cplx<T>{-kk * V.y, kk * V.x};
+    TwiddleRegs<T, LG, kThreads> tr;
+    tr.load(d.tw);
+    // CopyBatch loads per thread in flight together, as in rows_in
+    constexpr int CB = CopyBatch<T>::n;
+    const int n = nl * N;
+    for (int e0 = threadIdx.x; e0 < n; e0 += CB * kThreads) {
+      cplx<T> V[CB];
+#pragma unroll
+      for (int k = 0; k < CB; ++k) {
+        const int e = e0 + k * kThreads;
+        if (e < n) V[k] = SV[e];
+      }
+#pragma unroll
+      for (int k = 0; k < CB; ++k) {
+        const int e = e0 + k * kThreads;
+        if (e < n) {
+          const int line = e >> LG, p = e & (N - 1);
+          const T kk = c * (T)deriv_freq(ufpos<LG>(p), N);
+          buf[(2 * line) * LS + p] = V[k];
+          buf[(2 * line + 1) * LS + p] = cplx<T>{-kk * V[k].y, kk * V[k].x};
+        }
+      }
     }
+    tr.store(tw);
     __syncthreads();
     line_inv<T, LG, true>(buf, 2 * nl, LS, 1, tw);
     cplx<T>* dV = d.SVg + l0 * N;
@@ -938,6 +954,22 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane(Batch<T> bt) {
 }
 
 // ---- zinv ---------------------------------------------------------------------------------
+// Elements per thread of a z inverse block: ZB loads per batch, ZR batches.  The host keeps
+// rows_zinv N within ZR ZB kThreads (2048 in both precisions: float32 blocks of up to 2048
+// nodes; float64 blocks of 1024, and of two 1024-node rows in the 2D form).
+template <typename T> struct ZRounds { static constexpr int n = sizeof(T) == 4 ? 1 : 2; };
+
+// Two half spectra A, B (k3 in [0, N/2]) of real rows a, b into the full spectrum of the
+// complex row a + i b on line rr: A + i B at position fpos(k3) and, for 0 < k3 < N/2,
+// conj(A) + i conj(B) at the mirrored position fpos(N - k3).
+template <typename T, int LG>
+__device__ __forceinline__ void put_pair(cplx<T>* L, int rr, int pk, int pc, bool mirror,
+                                         cplx<T> A, cplx<T> Bv) {
+  constexpr int LS = zy_stride<LG>();
+  L[rr * LS + pk] = cplx<T>{A.x - Bv.y, A.y + Bv.x};
+  if (mirror) L[rr * LS + pc] = cplx<T>{A.x + Bv.y, Bv.x - A.y};
+}
+
 template <typename T, int LG>
 __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* smem, int mode) {
   constexpr int N = 1 << LG;
@@ -945,10 +977,14 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
   const int64_t N2 = d.nrows;  // rows per k3 plane of the spectra (N^2; N in 2D)
   const int64_t r0 = (int64_t)lb * B;
   const int Bh = B >> 1;
+  const int lgBh = __builtin_ctz((unsigned)Bh);  // B is a power of two: no vector division
   constexpr int LS = zy_stride<LG>();
-  cplx<T>* MW = reinterpret_cast<cplx<T>*>(smem);  // B lines: m + i w
-  cplx<T>* GG = MW + B * LS;                      // B lines: d1 v + i d2 v
-  cplx<T>* GZ = GG + B * LS;                      // B/2 lines: d3 v rows 2q + i 2q+1
+  // Two rounds over one LDS area of 1.5 B lines, so that more blocks share a CU: first the
+  // m and w lines (B lines of m + i w), then the gradient lines (B lines of d1 v + i d2 v and
+  // B/2 lines of d3 v, rows 2q + i 2q+1).
+  cplx<T>* MW = reinterpret_cast<cplx<T>*>(smem);
+  cplx<T>* GG = MW;
+  cplx<T>* GZ = GG + B * LS;
   cplx<T>* tw = GZ + Bh * LS;
   const bool freeze_m = d.flags & SIPF_FLAG_FREEZE_M;
   const bool freeze_w = d.flags & SIPF_FLAG_FREEZE_W;
@@ -957,13 +993,17 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
   T* const ub = d.ubar[par];  // holds w* (see zfwd)
   // the gather array of step n + 1, or with grad_only that of step n
   vec4<T>* const gout = d.g4[grad_only ? par : par ^ 1u];
-  constexpr int ZB = ZBatch<T>::n;
+  constexpr int ZB = ZBatch<T>::n, ZR = ZRounds<T>::n;
   const int nel = B * N;
   const int64_t g0 = r0 * N;
-  // w^n, m* (with m frozen, m^n) and w* of the first ZB elements per thread - all of them,
-  // unless a block has more than ZB kThreads elements - are loaded first: they are needed
-  // only after the transforms, so their loads overlap everything before.
-  T wold[ZB], mold[ZB], wst[ZB];
+  constexpr int H = (N >> 1) + 1;
+  const int n1 = H * Bh;  // (k3, row pair) items
+  // spectra of IB items per thread loaded together
+  constexpr int IB = sizeof(T) == 4 ? 2 : 1;
+  // w^n, m* (with m frozen, m^n) and w* of the first ZB elements per thread are loaded
+  // first: they are needed only after the transforms, so their loads overlap everything
+  // before.  wk keeps w of every element of the thread for the gather array.
+  T wold[ZB], mold[ZB], wst[ZB], wk[ZR * ZB];
 #pragma unroll
   for (int k = 0; k < ZB; ++k) {
     const int e = threadIdx.x + k * kThreads;
@@ -977,67 +1017,44 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
   }
   TwiddleRegs<T, LG, kThreads> tr;
   tr.load(d.tw);
-  constexpr int H = (N >> 1) + 1;
-  const T cz = d.gz_scale;  // 2 pi / L over the transforms SV went through (N or N^2)
-  // spectra of IB (k3, row pair) items per thread loaded together: 5 spectra x 2 rows each
-  constexpr int IB = sizeof(T) == 4 ? 2 : 1;
-  const int n1 = H * Bh;
-  const int lgBh = __builtin_ctz((unsigned)Bh);  // B is a power of two: no vector division
-  for (int e0 = threadIdx.x; e0 < n1; e0 += IB * kThreads) {
-    T sv[IB][2][10];  // (M, W, Gx, Gy, V) x (re, im) of rows 2q and 2q + 1
+  // ---- round 1: m and w ----
+  if (!grad_only) {
+    for (int e0 = threadIdx.x; e0 < n1; e0 += IB * kThreads) {
+      cplx<T> sv[IB][2][2];  // (M, W) of rows 2q and 2q + 1
 #pragma unroll
-    for (int ib = 0; ib < IB; ++ib) {
-      const int e = e0 + ib * kThreads;
-      if (e < n1) {
-        const int kz = e >> lgBh, q = e & (Bh - 1);
+      for (int ib = 0; ib < IB; ++ib) {
+        const int e = e0 + ib * kThreads;
+        if (e < n1) {
+          const int kz = e >> lgBh, q = e & (Bh - 1);
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int64_t o = (int64_t)kz * N2 + r0 + 2 * q + h;
-          const cplx<T> M = d.SM[o], W = d.SW[o], Gx = d.SGx[o], Gy = d.SGy[o], V = d.SVg[o];
-          sv[ib][h][0] = M.x;
-          sv[ib][h][1] = M.y;
-          sv[ib][h][2] = W.x;
-          sv[ib][h][3] = W.y;
-          sv[ib][h][4] = Gx.x;
-          sv[ib][h][5] = Gx.y;
-          sv[ib][h][6] = Gy.x;
-          sv[ib][h][7] = Gy.y;
-          sv[ib][h][8] = V.x;
-          sv[ib][h][9] = V.y;
+          for (int h = 0; h < 2; ++h) {
+            const int64_t o = (int64_t)kz * N2 + r0 + 2 * q + h;
+            sv[ib][h][0] = d.SM[o];
+            sv[ib][h][1] = d.SW[o];
+          }
         }
       }
-    }
 #pragma unroll
-    for (int ib = 0; ib < IB; ++ib) {
-      const int e = e0 + ib * kThreads;
-      if (e < n1) {
-        const int kz = e >> lgBh, q = e & (Bh - 1);
-        const bool mirror = kz > 0 && kz < (N >> 1);
-        const int pk = fpos<LG>(kz), pc = fpos<LG>((N - kz) & (N - 1));
-        const T kk = cz * (T)deriv_freq(kz, N);
-        cplx<T> gz[2];
+      for (int ib = 0; ib < IB; ++ib) {
+        const int e = e0 + ib * kThreads;
+        if (e < n1) {
+          const int kz = e >> lgBh, q = e & (Bh - 1);
+          const bool mirror = kz > 0 && kz < (N >> 1);
+          const int pk = fpos<LG>(kz), pc = fpos<LG>((N - kz) & (N - 1));
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const int rr = 2 * q + h;
-          const T* a = sv[ib][h];
-          MW[rr * LS + pk] = cplx<T>{a[0] - a[3], a[1] + a[2]};
-          GG[rr * LS + pk] = cplx<T>{a[4] - a[7], a[5] + a[6]};
-          if (mirror) {
-            MW[rr * LS + pc] = cplx<T>{a[0] + a[3], a[2] - a[1]};
-            GG[rr * LS + pc] = cplx<T>{a[4] + a[7], a[6] - a[5]};
-          }
-          gz[h] = cplx<T>{-kk * a[9], kk * a[8]};
+          for (int h = 0; h < 2; ++h)
+            put_pair<T, LG>(MW, 2 * q + h, pk, pc, mirror, sv[ib][h][0], sv[ib][h][1]);
         }
-        GZ[q * LS + pk] = cplx<T>{gz[0].x - gz[1].y, gz[0].y + gz[1].x};
-        if (mirror) GZ[q * LS + pc] = cplx<T>{gz[0].x + gz[1].y, gz[1].x - gz[0].y};
       }
     }
   }
   tr.store(tw);
   __syncthreads();
-  line_inv<T, LG, true>(MW, 2 * B + Bh, LS, 1, tw);
-  for (int e0 = threadIdx.x; e0 < nel; e0 += ZB * kThreads) {
-    if (e0 != (int)threadIdx.x) {  // elements beyond the first ZB per thread
+  if (!grad_only) line_inv<T, LG, true>(MW, B, LS, 1, tw);
+#pragma unroll
+  for (int r = 0; r < ZR; ++r) {
+    const int e0 = threadIdx.x + r * ZB * kThreads;
+    if (r > 0) {  // elements beyond the first ZB per thread
 #pragma unroll
       for (int k = 0; k < ZB; ++k) {
         const int e = e0 + k * kThreads;
@@ -1053,28 +1070,71 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
 #pragma unroll
     for (int k = 0; k < ZB; ++k) {
       const int e = e0 + k * kThreads;
-      if (e >= nel) continue;
+      wk[r * ZB + k] = wold[k];
+      if (grad_only || e >= nel) continue;
       const int rr = e >> LG, iz = e & (N - 1);
       const int64_t g = g0 + e;
       const cplx<T> mw = MW[rr * LS + iz];
+      if (!freeze_m) d.m[g] = mold[k] + mw.x;  // mold: m* (or, with m frozen, m^n)
+      if (!freeze_w) {
+        const T wn = wst[k] + mw.y;
+        d.w[g] = wn;
+        wk[r * ZB + k] = wn;
+      }
+      ub[g] = (T)0;  // cleared for the deposit of the next step's particle pass
+    }
+  }
+  // ---- round 2: the gradient of v ----
+  const T cz = d.gz_scale;  // 2 pi / L over the transforms SV went through (N or N^2)
+  if (!grad_only) __syncthreads();  // the m and w lines are read
+  for (int e0 = threadIdx.x; e0 < n1; e0 += IB * kThreads) {
+    cplx<T> sv[IB][2][3];  // (Gx, Gy, V) of rows 2q and 2q + 1
+#pragma unroll
+    for (int ib = 0; ib < IB; ++ib) {
+      const int e = e0 + ib * kThreads;
+      if (e < n1) {
+        const int kz = e >> lgBh, q = e & (Bh - 1);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const int64_t o = (int64_t)kz * N2 + r0 + 2 * q + h;
+          sv[ib][h][0] = d.SGx[o];
+          sv[ib][h][1] = d.SGy[o];
+          sv[ib][h][2] = d.SVg[o];
+        }
+      }
+    }
+#pragma unroll
+    for (int ib = 0; ib < IB; ++ib) {
+      const int e = e0 + ib * kThreads;
+      if (e < n1) {
+        const int kz = e >> lgBh, q = e & (Bh - 1);
+        const bool mirror = kz > 0 && kz < (N >> 1);
+        const int pk = fpos<LG>(kz), pc = fpos<LG>((N - kz) & (N - 1));
+        const T kk = cz * (T)deriv_freq(kz, N);
+        cplx<T> gz[2];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          put_pair<T, LG>(GG, 2 * q + h, pk, pc, mirror, sv[ib][h][0], sv[ib][h][1]);
+          gz[h] = cplx<T>{-kk * sv[ib][h][2].y, kk * sv[ib][h][2].x};
+        }
+        put_pair<T, LG>(GZ, q, pk, pc, mirror, gz[0], gz[1]);
+      }
+    }
+  }
+  __syncthreads();
+  line_inv<T, LG, true>(GG, B + Bh, LS, 1, tw);
+#pragma unroll
+  for (int r = 0; r < ZR; ++r) {
+#pragma unroll
+    for (int k = 0; k < ZB; ++k) {
+      const int e = threadIdx.x + (r * ZB + k) * kThreads;
+      if (e >= nel) continue;
+      const int rr = e >> LG, iz = e & (N - 1);
       const cplx<T> gg = GG[rr * LS + iz];
       const cplx<T> gzp = GZ[(rr >> 1) * LS + iz];
       const T gzv = (rr & 1) ? gzp.y : gzp.x;
-      if (grad_only) {
-        gout[g] = vec4<T>{gg.x, gg.y, gzv, wold[k]};
-        continue;
-      }
-      T mn = mold[k], wn = wold[k];  // mold: m* (or, with m frozen, m^n)
-      if (!freeze_m) {
-        mn += mw.x;
-        d.m[g] = mn;
-      }
-      if (!freeze_w) {
-        wn = wst[k] + mw.y;
-        d.w[g] = wn;
-      }
-      gout[g] = vec4<T>{gg.x, gg.y, gzv, wn};  // (grad v^{n+1}, w^{n+1})
-      ub[g] = (T)0;  // cleared for the deposit of the next step's particle pass
+      // (grad v^{n+1}, w^{n+1}), or with grad_only (grad v^n, w^n)
+      gout[g0 + e] = vec4<T>{gg.x, gg.y, gzv, wk[r * ZB + k]};
     }
   }
 }
@@ -1106,7 +1166,7 @@ size_t fft_lds_bytes(int kind, int lg) {
     case K_YFWD: return Bl * LZ * c + tw;
     case K_YINV: return Bl * LZ * c + tw;
     case K_XPASS: return Bx * LK * c + tw;
-    case K_ZINV: return (2 * Bz + Bz / 2) * LZ * c + tw;
+    case K_ZINV: return (Bz + Bz / 2) * LZ * c + tw;
     case K_PLANE: return (size_t)N * (N + 2) * c + tw;  // plane_stride
     default: return 0;
   }
