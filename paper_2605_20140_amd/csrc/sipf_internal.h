@@ -280,12 +280,13 @@ template <typename T> inline int zinv_elems(int N) {
 }
 // Fewest rows per block of the z forward pass (rows come in pairs): two; four for float64
 // rows of 1024 nodes (the 2D form's largest grid), where two rows left most of a block's
-// threads without a sub-transform (row pass 36.7 -> 27.7 us at 1024^2); and eight float64
-// rows at N = 256, so that a block writes 128 bytes of each spectrum row per plane, a whole
-// cache line instead of half of one (z forward pass 285 -> 265 us at 256^3).  Sixteen
-// float32 rows, the same 128 bytes, took it from 139 to 145 us there.
+// threads without a sub-transform (row pass 36.7 -> 27.7 us at 1024^2); and at N = 256 the
+// rows of 128 bytes of spectrum row per plane, so that a block writes whole cache lines
+// instead of halves (float64, eight rows: z forward pass 285 -> 265 us at 256^3; float32,
+// sixteen rows: the pass itself 139.5 -> 144.3 us, but the z inverse pass of the same step
+// 230.3 -> 224.6 us and the step 1317.5 -> 1308.8 us, two runs each).
 template <typename T> inline int zfwd_min_rows(int lg) {
-  if (lg == 8 && sizeof(T) == 8) return 8;
+  if (lg == 8) return 128 / (int)(2 * sizeof(T));
   return lg == 10 && sizeof(T) == 8 ? 4 : 2;
 }
 // Elements per block of the x pass (columns of N points): 2048 in both precisions, so that a
