@@ -247,7 +247,7 @@ void enqueue_fft(const FftGroup<T>* groups, int ng, hipStream_t st, int mode,
 // initialisation) formed and deposits into the other ubar buffer, while the field passes read
 // ubar^n and form the next gather array.  With a fork the two halves run side by side: the
 // field passes on the second stream, the binning (when due) and the particle pass on the
-// first; the finalize kernel (diagnostics, step index) waits for both.  The particle pass
+// first; the finalize kernel (step index) waits for both.  The particle pass
 // starts once the forward z pass is done: the particle blocks take every CU's LDS, and a z
 // pass started beside them ran at a fraction of its speed (128^3 / 2^23 float32: 207.9 ->
 // 202.9 us per step; starting it after the plane pass as well took 209.7).  Without a fork
