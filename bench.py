@@ -43,9 +43,13 @@ def stage_bytes(N, P, s, lowpass=False):
     return {
         # reads ubar, m, v, w; writes v, m* and w* (into ubar's array); 3 half spectra
         "zfwd": G * 4 * s + G * 3 * s + 3 * half,
+        # M, W transformed in place; V read, its y derivative written (with the filter V in
+        # place as well)
         "yfwd": 0 if plane else 6 * half,
-        "xpass": (3 + 4 + (1 if lowpass else 0)) * half if plane else 6 * half,
-        "yinv": 0 if plane else 9 * half,
+        # M, W in place, V read and d1 V written; with the filter also the filtered V
+        "xpass": (3 + 4 + (1 if lowpass else 0)) * half if plane else (8 if lowpass else 6) * half,
+        # M, W in place; with the filter also d1 V in place and the filtered V -> V, d2 V
+        "yinv": 0 if plane else (9 if lowpass else 4) * half,
         # reads 5 half spectra, w^n, m* and w*; writes m, w, the gather array (4 per node)
         # and the cleared ubar
         "zinv": 5 * half + 3 * G * s + G * 7 * s,

@@ -344,7 +344,9 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   d.use_plane = dim == 3 && plane_fits<T>(lg) ? 1 : 0;
   // the z (2D: x2) derivative is formed from V transformed along that axis only (plane and
   // 2D paths) or along y as well (three-pass path)
-  d.gz_scale = (T)(2.0 * M_PI / p.L / (dim == 3 && !d.use_plane ? (double)N * N : (double)N));
+  // V has been transformed along y as well only on the three-pass path with the filter
+  d.gz_scale = (T)(2.0 * M_PI / p.L /
+                   (dim == 3 && !d.use_plane && p.H0 > 0 ? (double)N * N : (double)N));
   if (d.use_plane) launch_plane<T>(Batch<T>{}, 0, lg, nullptr, 1);  // raise its LDS limit
   configure_particles<T>(p.deposit_order, dim);
   configure_fft<T>(lg);

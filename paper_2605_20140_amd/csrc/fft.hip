@@ -12,18 +12,22 @@
 //   zfwd : reaction (eq. g_hat_phy with S of eq. g_t) on (ubar, m, v, w) at time n, writes
 //          v^{n+1}, m* (into m) and w* (into ubar^n's array); real z transforms of m*, w*
 //          (packed as m* + i w*) and of v^{n+1} (two rows packed) -> SM, SW, SV.
-//   yfwd : y transforms of SM, SW, SV (in place).
+//   yfwd : y transforms of SM and SW (in place).  V needs only its three derivatives, each a
+//          round trip along its own axis after the z transform: this pass makes the y one,
+//          SGy = inverse y (i (2 pi/L) q_2 y transform of SV).
 //   xpass: x transforms, the diagonal multipliers of eq. k_q_tilde_update in change form
-//          (m: decay beta, diffusion D_m; w: decay 1, diffusion D_w) and the x-derivative
-//          multiplier of eq. gradv (i (2 pi/L) q_1, Nyquist zeroed), inverse x transforms
-//          -> SM, SW, SGx.
+//          (m: decay beta, diffusion D_m; w: decay 1, diffusion D_w) and, for SV, the
+//          x-derivative multiplier of eq. gradv (i (2 pi/L) q_1, Nyquist zeroed), inverse x
+//          transforms -> SM, SW, SGx.
+//   yinv : inverse y transforms of SM and SW.
 //          With the low-pass filter exp(-2 pi^2 |q|^2 / H0^2) (Alg. p2g text, Alg. sipf-pic)
-//          the filter multiplies the m, w and d1 v spectra, and a fourth job writes the
-//          filtered V (x round trip undone) into a buffer of its own, SVg; without it SVg
-//          is SV itself.
-//   yinv : inverse y transforms of SM, SW, SGx, and of SVg together with the y-derivative
-//          spectrum SGy = i (2 pi/L) q_2 SVg.  SVg is transformed along y and z only (x stays
-//          in physical space), so the derivatives formed from it carry 1/N^2.
+//          V needs its full transform: yfwd transforms SV in place like SM and SW, the filter
+//          multiplies the m, w and d1 v spectra in the x pass, a fourth x-pass job writes the
+//          filtered V (x round trip undone) into a buffer of its own, SVg, and yinv also
+//          transforms SGx back and forms, from SVg, the y-derivative spectrum
+//          SGy = i (2 pi/L) q_2 SVg.  Without the filter SVg is SV itself.  Either way SVg
+//          leaves x (and, without the filter, y) in physical space, which sets the scale of
+//          the derivatives formed from it (gz_scale).
 //   zinv : forms the z-derivative spectrum i (2 pi/L) q_3 SVg, inverse real z transforms of
 //          (SM, SW), (SGx, SGy) and of row pairs of the z derivative; writes m^{n+1} =
 //          m* + change, w^{n+1} = w* + change (the solves in change form, below), the gather
@@ -73,7 +77,8 @@ void block_counts(const SimDev<T>& d, int c[K_COUNT]) {
   } else {
     c[K_YFWD] = d.use_plane ? 0 : (int)(3 * ny);
     c[K_XPASS] = d.use_plane ? 0 : (int)((3 + nlp) * H * (N / d.cols_per_blk));
-    c[K_YINV] = d.use_plane ? 0 : (int)(3 * ny + ny2);
+    // inverse y of M and W; with the filter also of d1 V and of the filtered V (+ d2 V)
+    c[K_YINV] = d.use_plane ? 0 : (int)(nlp ? 3 * ny + ny2 : 2 * ny);
     // plane jobs: M, W and one for both V derivatives; with the filter M, W, d1 V, d2 V, V
     c[K_PLANE] = d.use_plane ? (int)((nlp ? 5 : 3) * H) : 0;
   }
@@ -616,14 +621,28 @@ __device__ __forceinline__ void yfwd_body(SimC<T>& d, int lb, unsigned char* sme
   const int f = lb / nbf;
   const int64_t l0 = (int64_t)(lb - f * nbf) * Bl;
   const int nl = (int)((lines - l0) < Bl ? (lines - l0) : Bl);
-  cplx<T>* S = (f == 0 ? d.SM : (f == 1 ? d.SW : d.SV)) + l0 * N;
+  const cplx<T>* S = (f == 0 ? d.SM : (f == 1 ? d.SW : d.SV)) + l0 * N;
+  // Without the filter V needs no y transform of its own: only its derivative along y,
+  // a y round trip of SV with the multiplier i (2 pi/L) q2 into SGy (1/N^2 undoes the z
+  // and y round trips).  With the filter V is transformed in place like M and W.
+  const bool vround = f == 2 && !d.use_lowpass;
+  cplx<T>* dst = (vround ? d.SGy : (f == 0 ? d.SM : (f == 1 ? d.SW : d.SV))) + l0 * N;
   constexpr int LS = zy_stride<LG>();
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* tw = buf + Bl * LS;
   rows_in<T, LG, kThreads>(buf, LS, S, nl * N, tw, d.tw);
   __syncthreads();
-  line_fwd<T, LG, true>(buf, nl, LS, 1, tw);
-  for (int e = threadIdx.x; e < nl * N; e += kThreads) S[e] = buf[(e >> LG) * LS + (e & (N - 1))];
+  if (vround) {
+    const T c = d.two_pi_over_L * d.inv_n2;
+    const auto deriv = [c](int, int p, cplx<T> v) {
+      const T kk = c * (T)deriv_freq(ufpos<LG>(p), N);
+      return cplx<T>{-kk * v.y, kk * v.x};
+    };
+    line_round_trip<T, LG, true, kThreads>(buf, nl, LS, 1, tw, deriv);
+  } else {
+    line_fwd<T, LG, true>(buf, nl, LS, 1, tw);
+  }
+  for (int e = threadIdx.x; e < nl * N; e += kThreads) dst[e] = buf[(e >> LG) * LS + (e & (N - 1))];
 }
 
 template <typename T, int LG>
@@ -752,7 +771,7 @@ __device__ __forceinline__ void xpass_body(SimC<T>& d, int lb, unsigned char* sm
   const T k0 = d.two_pi_over_L;
   const T D = (T)(f == 0 ? d.D_m : d.D_w);
   const T decay = (T)(f == 0 ? d.beta : 1.0);
-  const T dt = (T)d.dt, inv_n3 = d.inv_n3;
+  const T dt = (T)d.dt, inv_n3 = d.inv_n3, inv_n2 = d.inv_n2;
   const bool use_lp = d.use_lowpass, implicit = d.mult_kind == 0;
   const T* lpt = d.mtab + 2 * N;
   const T* tab = d.mtab + (f < 2 ? f : 0) * N;
@@ -773,7 +792,9 @@ __device__ __forceinline__ void xpass_body(SimC<T>& d, int lb, unsigned char* sm
       }
       return cscale(val, mult * inv_n3);
     } else if (f == 2) {
-      T kk = k0 * (T)deriv_freq(kx, N) * inv_n3;
+      // d1 v: with the filter V went through all three transforms, without it through the
+      // z transform only (this x round trip adds the second N)
+      T kk = k0 * (T)deriv_freq(kx, N) * (use_lp ? inv_n3 : inv_n2);
       if (use_lp) kk *= lpt[kx] * lpt[ky] * lpt[kz];
       return cplx<T>{-kk * val.y, kk * val.x};
     }
