@@ -618,8 +618,12 @@ __device__ __forceinline__ void yfwd_body(SimC<T>& d, int lb, unsigned char* sme
   const int Bl = d.lines_per_blk;
   const int64_t lines = (int64_t)((N >> 1) + 1) * N;
   const int nbf = (int)((lines + Bl - 1) / Bl);
-  const int f = lb / nbf;
-  const int64_t l0 = (int64_t)(lb - f * nbf) * Bl;
+  const int fj = lb / nbf;
+  const int64_t l0 = (int64_t)(lb - fj * nbf) * Bl;
+  // without the filter the V blocks come first, so that the x pass that follows starts on M
+  // and W as the last blocks of this pass left them (x pass at 256^3 float32 117.5 ->
+  // 104.7 us, y inverse 57 -> 54 us; the step unchanged)
+  const int f = d.use_lowpass ? fj : (fj == 0 ? 2 : fj - 1);
   const int nl = (int)((lines - l0) < Bl ? (lines - l0) : Bl);
   const cplx<T>* S = (f == 0 ? d.SM : (f == 1 ? d.SW : d.SV)) + l0 * N;
   // Without the filter V needs no y transform of its own: only its derivative along y,
