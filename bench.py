@@ -50,9 +50,9 @@ def stage_bytes(N, P, s, lowpass=False):
         "xpass": (3 + 4 + (1 if lowpass else 0)) * half if plane else (8 if lowpass else 6) * half,
         # M, W in place; with the filter also d1 V in place and the filtered V -> V, d2 V
         "yinv": 0 if plane else (9 if lowpass else 4) * half,
-        # reads 5 half spectra, w^n, m* and w*; writes m, w, the gather array (4 per node)
-        # and the cleared ubar
-        "zinv": 5 * half + 3 * G * s + G * 7 * s,
+        # reads 5 half spectra, m* and w*; writes m, w, the gather array (4 per node) and the
+        # cleared ubar
+        "zinv": 5 * half + 2 * G * s + G * 7 * s,
         # particles: read x,y,z,a; write x,y,z,a (the 4-byte particle index that keys the
         # noise is not counted) + gather array read once + deposit target written once
         "particles": P * (6 * s + 16) + G * 5 * s,

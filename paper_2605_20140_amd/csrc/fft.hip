@@ -1025,19 +1025,19 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
   const int n1 = H * Bh;  // (k3, row pair) items
   // spectra of IB items per thread loaded together
   constexpr int IB = sizeof(T) == 4 ? 2 : 1;
-  // w^n, m* (with m frozen, m^n) and w* of the first ZB elements per thread are loaded
-  // first: they are needed only after the transforms, so their loads overlap everything
-  // before.  wk keeps w of every element of the thread for the gather array.
+  // m* and w* of the first ZB elements per thread (w^n instead of w* when w is frozen or
+  // only the gradient is formed; m* not at all when m is frozen) are loaded first: they are
+  // needed only after the transforms, so their loads overlap everything before.  wk keeps w
+  // of every element of the thread for the gather array.
+  const bool need_wold = grad_only || freeze_w, need_m = !grad_only && !freeze_m;
   T wold[ZB], mold[ZB], wst[ZB], wk[ZR * ZB];
 #pragma unroll
   for (int k = 0; k < ZB; ++k) {
     const int e = threadIdx.x + k * kThreads;
     if (e < nel) {
-      wold[k] = d.w[g0 + e];
-      if (!grad_only) {
-        mold[k] = d.m[g0 + e];
-        wst[k] = ub[g0 + e];
-      }
+      if (need_wold) wold[k] = d.w[g0 + e];
+      if (need_m) mold[k] = d.m[g0 + e];
+      if (!need_wold) wst[k] = ub[g0 + e];
     }
   }
   TwiddleRegs<T, LG, kThreads> tr;
@@ -1084,23 +1084,21 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
       for (int k = 0; k < ZB; ++k) {
         const int e = e0 + k * kThreads;
         if (e < nel) {
-          wold[k] = d.w[g0 + e];
-          if (!grad_only) {
-            mold[k] = d.m[g0 + e];
-            wst[k] = ub[g0 + e];
-          }
+          if (need_wold) wold[k] = d.w[g0 + e];
+          if (need_m) mold[k] = d.m[g0 + e];
+          if (!need_wold) wst[k] = ub[g0 + e];
         }
       }
     }
 #pragma unroll
     for (int k = 0; k < ZB; ++k) {
       const int e = e0 + k * kThreads;
-      wk[r * ZB + k] = wold[k];
+      if (need_wold) wk[r * ZB + k] = wold[k];
       if (grad_only || e >= nel) continue;
       const int rr = e >> LG, iz = e & (N - 1);
       const int64_t g = g0 + e;
       const cplx<T> mw = MW[rr * LS + iz];
-      if (!freeze_m) d.m[g] = mold[k] + mw.x;  // mold: m* (or, with m frozen, m^n)
+      if (need_m) d.m[g] = mold[k] + mw.x;  // m^{n+1} = m* + change (frozen m: unchanged)
       if (!freeze_w) {
         const T wn = wst[k] + mw.y;
         d.w[g] = wn;
