@@ -223,6 +223,31 @@ def test_order4_fp32():
     compare_state(out, ref, TOL32)
 
 
+# ---- the three-pass FFT path (planes too large for the LDS) without the filter ----
+
+def test_three_pass_path_several_steps():
+    """Float64 at N = 128, where a plane of a half spectrum no longer fits the LDS: the
+    three-pass path, which forms grad v as one round trip per axis after the z transform
+    (eq. gradv): y in the forward y pass, x in the x pass, z in the inverse z pass.  Three
+    steps, so that gradients formed by the step's own field passes (not only by the
+    initialisation's) drive the push."""
+    ic = W.make_initial_state("modes64", N=128, P=20000)
+    sim = gpu_sim(ic, precision=0)
+    sim.step(3)
+    out = sim.fields()
+    _, g = sim.aux()
+    sim.close()
+    prm = oracle_params(ic["params"])
+    st = oracle_state(ic)
+    ref, aux = None, None
+    for _ in range(3):
+        ref, aux = S.step(st, prm, return_aux=True)
+        st = ref
+    compare_state(out, ref, TOL64)
+    for j in range(3):
+        assert max(rel_errors(g[j], aux["grad"][j])) < 1e-11, j
+
+
 # ---- low-pass filter exp(-2 pi^2 |q|^2 / H0^2) (Alg. p2g text, Alg. sipf-pic) ----
 
 @pytest.mark.parametrize("N,P,steps,precision", [(16, 4096, 20, 0), (64, 30000, 3, 0),
