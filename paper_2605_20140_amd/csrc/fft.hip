@@ -666,6 +666,8 @@ __device__ __forceinline__ void yinv_body(SimC<T>& d, int lb, unsigned char* sme
   constexpr int LS = zy_stride<LG>();
   cplx<T>* buf = reinterpret_cast<cplx<T>*>(smem);
   cplx<T>* tw = buf + Bl * LS;
+  // jobs M and W; with the filter also d1 V (SGx) and, below, the filtered V lines (the
+  // launch has 2 nb1 blocks without the filter)
   if (lb < 3 * nb1) {
     const int f = lb / nb1;
     const int64_t l0 = (int64_t)(lb - f * nb1) * Bl;
@@ -677,8 +679,9 @@ __device__ __forceinline__ void yinv_body(SimC<T>& d, int lb, unsigned char* sme
     for (int e = threadIdx.x; e < nl * N; e += kThreads)
       S[e] = buf[(e >> LG) * LS + (e & (N - 1))];
   } else {
-    // SV lines: transform SV and form + transform SGy = i (2 pi/L) q2 SV / N^2 (SV is never
-    // transformed along x, so its round trip scales by N^2 only)
+    // filtered V lines (with the filter only): transform SVg and form + transform
+    // SGy = i (2 pi/L) q2 SVg / N^2 (SVg is never transformed along x, so its round trip
+    // scales by N^2 only)
     const int Bh = Bl >> 1;
     const int64_t l0 = (int64_t)(lb - 3 * nb1) * Bh;
     const int nl = (int)((lines - l0) < Bh ? (lines - l0) : Bh);
