@@ -330,6 +330,8 @@ int init_t(sipf_sim* sim, const double* X0, const double* a0, const double* v0,
   const int E = elems_per_block<T>();
   d.rows_per_blk = (int)std::min<int64_t>(d.nrows, std::max(zfwd_min_rows<T>(lg), E / N));
   d.rows_zinv = (int)std::min<int64_t>(d.nrows, std::max(2, zinv_elems<T>(N) / N));
+  if ((int64_t)d.rows_zinv * N > zinv_max_elems())  // the z inverse pass's registers
+    return fail(SIPF_EINVAL, "grid too large for the z inverse pass's blocks");
   d.lines_per_blk = E / N;
   d.cols_per_blk = std::min(N, xpass_elems(lg) / N);
   d.flags = (int)p.flags;

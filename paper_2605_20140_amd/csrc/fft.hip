@@ -982,10 +982,14 @@ __global__ void __launch_bounds__(kPlaneThreads) k_plane(Batch<T> bt) {
 }
 
 // ---- zinv ---------------------------------------------------------------------------------
-// Elements per thread of a z inverse block: ZB loads per batch, ZR batches.  The host keeps
-// rows_zinv N within ZR ZB kThreads (2048 in both precisions: float32 blocks of up to 2048
-// nodes; float64 blocks of 1024, and of two 1024-node rows in the 2D form).
-template <typename T> struct ZRounds { static constexpr int n = sizeof(T) == 4 ? 1 : 2; };
+// Elements per thread of a z inverse block: ZB loads per batch, ZR batches, ZR ZB = 8 in
+// both precisions, so a block holds up to zinv_max_elems() = 2048 nodes (float32 blocks of
+// up to 2048 nodes; float64 blocks of 1024, and of two 1024-node rows in the 2D form); the
+// host checks rows_zinv N against it.
+template <typename T> struct ZBatches { static constexpr int n = sizeof(T) == 4 ? 1 : 2; };
+static_assert(ZBatch<float>::n * ZBatches<float>::n * kThreads == zinv_max_elems() &&
+                  ZBatch<double>::n * ZBatches<double>::n * kThreads == zinv_max_elems(),
+              "z inverse elements per block");
 
 // Two half spectra A, B (k3 in [0, N/2]) of real rows a, b into the full spectrum of the
 // complex row a + i b on line rr: A + i B at position fpos(k3) and, for 0 < k3 < N/2,
@@ -1007,7 +1011,7 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
   const int Bh = B >> 1;
   const int lgBh = __builtin_ctz((unsigned)Bh);  // B is a power of two: no vector division
   constexpr int LS = zy_stride<LG>();
-  // Two rounds over one LDS area of 1.5 B lines, so that more blocks share a CU: first the
+  // Two phases over one LDS area of 1.5 B lines, so that more blocks share a CU: first the
   // m and w lines (B lines of m + i w), then the gradient lines (B lines of d1 v + i d2 v and
   // B/2 lines of d3 v, rows 2q + i 2q+1).
   cplx<T>* MW = reinterpret_cast<cplx<T>*>(smem);
@@ -1021,7 +1025,7 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
   T* const ub = d.ubar[par];  // holds w* (see zfwd)
   // the gather array of step n + 1, or with grad_only that of step n
   vec4<T>* const gout = d.g4[grad_only ? par : par ^ 1u];
-  constexpr int ZB = ZBatch<T>::n, ZR = ZRounds<T>::n;
+  constexpr int ZB = ZBatch<T>::n, ZR = ZBatches<T>::n;
   const int nel = B * N;
   const int64_t g0 = r0 * N;
   constexpr int H = (N >> 1) + 1;
@@ -1045,7 +1049,7 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
   }
   TwiddleRegs<T, LG, kThreads> tr;
   tr.load(d.tw);
-  // ---- round 1: m and w ----
+  // ---- first phase: m and w ----
   if (!grad_only) {
     for (int e0 = threadIdx.x; e0 < n1; e0 += IB * kThreads) {
       cplx<T> sv[IB][2][2];  // (M, W) of rows 2q and 2q + 1
@@ -1110,7 +1114,7 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
       ub[g] = (T)0;  // cleared for the deposit of the next step's particle pass
     }
   }
-  // ---- round 2: the gradient of v ----
+  // ---- second phase: the gradient of v ----
   const T cz = d.gz_scale;  // 2 pi / L over the transforms SV went through (N or N^2)
   if (!grad_only) __syncthreads();  // the m and w lines are read
   for (int e0 = threadIdx.x; e0 < n1; e0 += IB * kThreads) {

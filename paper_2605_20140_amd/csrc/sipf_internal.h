@@ -275,6 +275,9 @@ template <typename T> int elems_per_block();
 // N <= 128 float32 blocks of 1024 elements (half the forward pass's) let five blocks share
 // a CU instead of three, which pays while a block's runs along a spectrum row stay a full
 // 64 bytes (8 rows); at N >= 256 they would be shorter, so the pass keeps 2048.
+// Most elements a z inverse block holds: its threads keep every element's w (and, before the
+// transforms, m* and w*) in registers, 8 per thread (ZBatch x ZBatches in fft.hip).
+constexpr int zinv_max_elems() { return 8 * kThreads; }
 template <typename T> inline int zinv_elems(int N) {
   return sizeof(T) == 4 && N <= 128 ? 1024 : elems_per_block<T>();
 }
