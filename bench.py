@@ -57,9 +57,9 @@ def stage_bytes(N, P, s, lowpass=False):
         # noise is not counted) + gather array read once + deposit target written once
         "particles": P * (6 * s + 16) + G * 5 * s,
         "finalize": 0,
-        # binning, per binning: count reads x,y,z and writes (tile, rank); scatter reads the
-        # keys and one particle set and writes the other
-        "binning": P * (3 * s + 8) + P * (8 + 2 * (3 * s + 8 + 4)),
+        # binning, per binning: count reads x,y,z and writes the rank within the tile;
+        # scatter reads the ranks and one particle set and writes the other
+        "binning": P * (3 * s + 4) + P * (4 + 2 * (3 * s + 8 + 4)),
     }
 
 

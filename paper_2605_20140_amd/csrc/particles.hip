@@ -878,6 +878,22 @@ __device__ __forceinline__ uint32_t hash_slot(uint32_t* hkey, uint32_t t) {
   return kEmpty;
 }
 
+// Tile of a particle (row-major tile index, z fastest; a cell index N - 1 beyond the last
+// full tile joins the last tile).  The count and the scatter compute it from the same
+// positions, so the binning keys hold only the rank within the tile.
+template <typename T, int DIM>
+__device__ __forceinline__ uint32_t tile_of(T x, T y, T z, T inv_h, int N, int nt) {
+  if (DIM == 2) {
+    const Stencil<T> st = make_stencil2(x, y, inv_h, N);
+    const int tx = st.c[0] / kTile2, ty = st.c[1] / kTile2;
+    return (uint32_t)((tx < nt ? tx : nt - 1) * nt + (ty < nt ? ty : nt - 1));
+  }
+  const Stencil<T> st = make_stencil(x, y, z, inv_h, N);
+  const int tx = st.c[0] / kTile, ty = st.c[1] / kTile, tz = st.c[2] / kTile;
+  return (uint32_t)(((tx < nt ? tx : nt - 1) * nt + (ty < nt ? ty : nt - 1)) * nt +
+                    (tz < nt ? tz : nt - 1));
+}
+
 template <typename T, int DIM>
 __global__ void __launch_bounds__(kThreads) k_bin_count(Batch<T> bt) {
   int lb;
@@ -892,7 +908,7 @@ __global__ void __launch_bounds__(kThreads) k_bin_count(Batch<T> bt) {
   const int N = d.N, nt = d.ntile1;
   const int lane = threadIdx.x & 63;
   const int64_t i0 = (int64_t)lb * kBinChunk + threadIdx.x;
-  uint32_t tiles[kBinPer], slot[kBinPer], lrank[kBinPer];
+  uint32_t slot[kBinPer], lrank[kBinPer];
   // positions of all kBinPer particles loaded before the first tile is aggregated (the
   // aggregation loop would otherwise put one memory round trip between consecutive loads)
   T px[kBinPer], py[kBinPer], pz[kBinPer];
@@ -909,20 +925,8 @@ __global__ void __launch_bounds__(kThreads) k_bin_count(Batch<T> bt) {
   for (int j = 0; j < kBinPer; ++j) {
     const int64_t i = i0 + (int64_t)j * kThreads;
     const bool valid = i < d.P;
-    uint32_t tile = 0;
-    if (valid) {
-      if (DIM == 2) {
-        const Stencil<T> st = make_stencil2(px[j], py[j], d.inv_h, N);
-        const int tx = st.c[0] / kTile2, ty = st.c[1] / kTile2;
-        tile = (uint32_t)((tx < nt ? tx : nt - 1) * nt + (ty < nt ? ty : nt - 1));
-      } else {
-        const Stencil<T> st = make_stencil(px[j], py[j], pz[j], d.inv_h, N);
-        const int tx = st.c[0] / kTile, ty = st.c[1] / kTile, tz = st.c[2] / kTile;
-        tile = (uint32_t)(((tx < nt ? tx : nt - 1) * nt + (ty < nt ? ty : nt - 1)) * nt +
-                          (tz < nt ? tz : nt - 1));
-      }
-    }
-    tiles[j] = tile;
+    const uint32_t tile =
+        valid ? tile_of<T, DIM>(px[j], py[j], DIM == 3 ? pz[j] : (T)0, d.inv_h, N, nt) : 0u;
     slot[j] = kEmpty;
     lrank[j] = 0;
     // The wavefront's first tile (usually shared by most lanes: set 0 is tile-ordered) is
@@ -971,8 +975,7 @@ __global__ void __launch_bounds__(kThreads) k_bin_count(Batch<T> bt) {
     const int64_t i = i0 + (int64_t)j * kThreads;
     if (i < d.P) {
       const uint32_t r = slot[j] == kGlobalFlag ? lrank[j] : hbase[slot[j]] + lrank[j];
-      d.key[2 * i] = tiles[j];
-      d.key[2 * i + 1] = r;
+      d.key[i] = r;  // rank within the tile
     }
   }
 }
@@ -1171,10 +1174,11 @@ __global__ void __launch_bounds__(kThreads) k_bin_scatter(Batch<T> bt) {
   // tile counts cleared for the next binning (the scan has read them all)
   if (i < d.ntiles) d.tcount[i] = 0;
   if (i >= d.P) return;
-  const uint32_t dst = d.toff[d.key[2 * i]] + d.key[2 * i + 1];
-  d.xs[1][dst] = d.xs[0][i];
-  d.ys[1][dst] = d.ys[0][i];
-  if (DIM == 3) d.zs[1][dst] = d.zs[0][i];
+  const T x = d.xs[0][i], y = d.ys[0][i], z = DIM == 3 ? d.zs[0][i] : (T)0;
+  const uint32_t dst = d.toff[tile_of<T, DIM>(x, y, z, d.inv_h, d.N, d.ntile1)] + d.key[i];
+  d.xs[1][dst] = x;
+  d.ys[1][dst] = y;
+  if (DIM == 3) d.zs[1][dst] = z;
   d.as[1][dst] = d.as[0][i];
   d.ids[1][dst] = d.ids[0][i];
 }

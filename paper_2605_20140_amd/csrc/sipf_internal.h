@@ -137,7 +137,8 @@ struct SimDesc {
   Ptr<uint4> cinfo;      // max_chunks: (first particle, end, tile, -) of each chunk (set at
                          // binning, so a particle-pass block needs one lookup)
   int max_chunks;     // bound on the number of chunks: ceil(P / kChunk) + ntiles
-  Ptr<uint32_t> key;     // 2P: (tile, rank within tile) per particle
+  Ptr<uint32_t> key;     // 2P words: the binning's rank within the tile of each particle
+                         // (first P), resampling's 64-bit prefix sums (all 2P)
   // grid (real, N^3 row-major)
   Ptr<T> v, m, w;
   // Deposited density and gather array, two buffers each, chosen by the parity of the step
