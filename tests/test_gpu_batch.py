@@ -35,3 +35,28 @@ def test_batch_equals_solo(precision, tol):
         assert np.abs(out["a"] / solo[k]["a"] - 1).max() < tol
         assert out["diag"]["step"] == 7
         s.close()
+
+
+def test_batch_mixes_fft_paths():
+    """A float64 batch holding a 128^3 simulation (three-pass FFT path: grad v as one round
+    trip per axis) and a 16^3 one (plane path): each equals its solo run."""
+    from paper_2605_20140_amd import sipf
+    ics = [W.make_initial_state("modes64", N=128, P=20000),
+           W.make_initial_state("blob16", N=16, P=3000, ic_seed=3)]
+    solo = []
+    for k, ic in enumerate(ics):
+        s = gpu_sim(ic, precision=0, sim_id=k)
+        s.step(4)
+        solo.append(s.fields())
+        s.close()
+    sims = [gpu_sim(ic, precision=0, sim_id=k) for k, ic in enumerate(ics)]
+    sipf.step_batch(sims, 4)
+    for k, s in enumerate(sims):
+        out = s.fields()
+        for f in ("v", "m", "w"):
+            assert max(rel_errors(out[f], solo[k][f])) < 1e-12, (k, f)
+        d = out["X"] - solo[k]["X"]
+        assert np.abs(d - np.round(d)).max() < 1e-12
+        assert np.abs(out["a"] / solo[k]["a"] - 1).max() < 1e-12
+        assert out["diag"]["step"] == 4
+        s.close()
