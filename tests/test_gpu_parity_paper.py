@@ -5,9 +5,9 @@ workloads do not reach.
   simulation): L = 6, chi = 0.4, D_u = D_m = D_w = 0.01, alpha = 5, beta = 0.01, gamma = 5, a
   ball (3D) or paraboloid (2D) of cells, a non-periodic v0.  These exercise every
   L-dependent quantity of the kernels (1/h, 2 pi / L, the wrap at L, the cell volume).
-* Particles drifting past the one-cell margin of their tile's LDS region (Alg. g2p and
-  Alg. p2g for every particle): the gather and deposit of such particles go through global
-  memory from a block that uses a region.
+* Particles drifting past the margin of their tile's LDS region (one cell in 3D, four in
+  2D; Alg. g2p and Alg. p2g for every particle): the gather and deposit of such particles go
+  through global memory from a block that uses a region.
 * The strict positivity check (positivity lemma): a state with v = 0 at one node makes
   sipf_fields return SIPF_EPOS.
 """
@@ -57,34 +57,35 @@ def test_paper2d_example(precision, tol):
     print("paper2d precision", precision, errs)
 
 
-def _past_margin_fraction(traj, N, L, period, tile=8):
-    """Fraction of (particle, step) pairs whose trilinear stencil, for the gather at X^n or
-    the deposit at X^{n+1}, leaves the LDS region of the tile the particle was binned into.
-    Binning happens at initialisation and then on every step with since_bin >= period, i.e.
-    at steps 0, period, 2 period, ...; the region of a tile covers cells tile*8 - 1 ..
-    tile*8 + 8 on each axis (one cell of margin below, the stencil's reach and one cell of
-    margin above)."""
+def _past_margin_fraction(traj, N, L, period, tile=8, margin=1):
+    """Fraction of (particle, step) pairs whose stencil, for the gather at X^n or the deposit
+    at X^{n+1}, leaves the LDS region of the tile the particle was binned into.  Binning
+    happens at initialisation and then on every step with since_bin >= period, i.e. at steps
+    0, period, 2 period, ...; the region of a tile holds the stencils of the cells
+    tile*T - margin .. tile*T + T - 1 + margin on each axis (T = tile cells per axis: 8 with
+    a one-cell margin in 3D, 16 with a four-cell margin in 2D)."""
     h = L / N
     cells = [np.floor(X / h).astype(np.int64) % N for X in traj]
     out = []
     for n in range(len(traj) - 1):
         b = (n // period) * period
-        origin = (cells[b] // tile) * tile - 1
+        origin = (cells[b] // tile) * tile - margin
         for c in (cells[n], cells[n + 1]):
             lrel = (c - origin) % N
-            out.append(np.any(lrel > tile + 1, axis=1))
+            out.append(np.any(lrel > tile + 2 * margin - 1, axis=1))
     return float(np.mean(out))
 
 
-def test_particles_past_the_drift_margin():
+@pytest.mark.parametrize("precision,tol", [(0, TOL64), (1, TOL32)])
+def test_particles_past_the_drift_margin(precision, tol):
     """N = 32, D_u raised to 0.044 (a diffusive step of 0.3 cell), binning every 8 steps, 24
     steps: about 1.4 % of the particle-steps (some 8000 gathers and deposits) go through global
-    memory."""
+    memory (float32: after the early region loads of the same particle)."""
     D_u, period, nsteps = 0.044, 8, 24
     ic = W.make_initial_state("blob16", N=32, P=4096 * 3 + 77, D_u=D_u)
     prm = oracle_params(ic["params"])
     assert abs(np.sqrt(2 * D_u * prm.dt) * prm.N - 0.3) < 0.01
-    sim = gpu_sim(ic, resort_every=period)
+    sim = gpu_sim(ic, precision=precision, resort_every=period)
     sim.step(nsteps)
     out = sim.fields()
     sim.close()
@@ -96,7 +97,31 @@ def test_particles_past_the_drift_margin():
     frac = _past_margin_fraction(traj, prm.N, prm.L, period)
     print(f"particle-steps past the region margin: {frac:.4f}")
     assert frac > 0.005
-    compare_state(out, st, TOL64)
+    compare_state(out, st, tol)
+
+
+@pytest.mark.parametrize("precision,tol", [(0, TOL64), (1, TOL32)])
+def test_2d_particles_past_the_drift_margin(precision, tol):
+    """The 2D pass (16 x 16 tiles, four-cell margins): N = 64, D_u = 0.2 (a diffusive step of
+    1.3 cells), binning every 8 steps, 24 steps; the particles that leave their tile's region
+    gather and deposit through global memory."""
+    D_u, period, nsteps = 0.2, 8, 24
+    ic = W.blob2d_initial_state(N=64, P=20000, D_u=D_u)
+    prm = oracle_params(ic["params"])
+    assert abs(np.sqrt(2 * D_u * prm.dt) * prm.N - 1.28) < 0.01
+    sim = gpu_sim(ic, precision=precision, resort_every=period)
+    sim.step(nsteps)
+    out = sim.fields()
+    sim.close()
+    st = oracle_state(ic)
+    traj = [st.X]
+    for _ in range(nsteps):
+        st = S.step(st, prm)
+        traj.append(st.X)
+    frac = _past_margin_fraction(traj, prm.N, prm.L, period, tile=16, margin=4)
+    print(f"particle-steps past the region margin: {frac:.4f}")
+    assert frac > 0.005
+    compare_state(out, st, tol)
 
 
 def test_strict_flag_reports_violated_positivity():
