@@ -76,16 +76,19 @@ def _past_margin_fraction(traj, N, L, period, tile=8, margin=1):
     return float(np.mean(out))
 
 
-@pytest.mark.parametrize("precision,tol", [(0, TOL64), (1, TOL32)])
-def test_particles_past_the_drift_margin(precision, tol):
+@pytest.mark.parametrize("precision,tol,order", [(0, TOL64, 2), (1, TOL32, 2), (0, TOL64, 4),
+                                                 (1, TOL32, 4)])
+def test_particles_past_the_drift_margin(precision, tol, order):
     """N = 32, D_u raised to 0.044 (a diffusive step of 0.3 cell), binning every 8 steps, 24
     steps: about 1.4 % of the particle-steps (some 8000 gathers and deposits) go through global
-    memory (float32: after the early region loads of the same particle)."""
+    memory (float32: after the early region loads of the same particle).  The fourth-order
+    deposit's region holds the 4^3 stencils of the same cells (two nodes of margin below the
+    tile, three above), so the same particles deposit through global memory."""
     D_u, period, nsteps = 0.044, 8, 24
     ic = W.make_initial_state("blob16", N=32, P=4096 * 3 + 77, D_u=D_u)
-    prm = oracle_params(ic["params"])
+    prm = oracle_params(ic["params"], deposit_order=order)
     assert abs(np.sqrt(2 * D_u * prm.dt) * prm.N - 0.3) < 0.01
-    sim = gpu_sim(ic, precision=precision, resort_every=period)
+    sim = gpu_sim(ic, precision=precision, resort_every=period, deposit_order=order)
     sim.step(nsteps)
     out = sim.fields()
     sim.close()
