@@ -66,3 +66,20 @@ def compare_state(out, ref, tol, L=1.0, fields=("v", "m", "w")):
     bad = {k: v for k, v in errs.items() if (max(v) if isinstance(v, tuple) else v) > tol}
     assert not bad, f"errors above {tol}: {bad}"
     return errs
+
+
+def gradient_tolerance(v, grad, L, precision):
+    """Tolerance of the spectral gradient, an intermediate the state tolerances do not cover.
+    Rounding in the working precision (unit u = 2^-24 or 2^-53: the stored v and the
+    transforms, whose rms error grows like sqrt(log2 N^d)) is white across the spectrum, and
+    the derivative multiplies each frequency by (2 pi / L) |q_j|, whose rms over the grid is
+    (2 pi / L) N / (2 sqrt 3); relative to |grad v| that noise is
+    u sqrt(log2 N^d) (2 pi / L) N / (2 sqrt 3) |v| / |grad v|.  Twice that, and never below
+    the state tolerance (1e-4 float32, 1e-10 float64), is the bound: it grows linearly with N
+    (float32 at 512^3: 1.3e-3)."""
+    N, d = v.shape[0], v.ndim
+    u = 2.0 ** -24 if precision else 2.0 ** -53
+    amp = (2.0 * np.pi / L) * N / (2.0 * np.sqrt(3.0))
+    ratio = np.linalg.norm(v) / np.linalg.norm(np.stack(grad))
+    return max(1e-4 if precision else 1e-10,
+               2.0 * u * np.sqrt(np.log2(float(N) ** d)) * amp * ratio)

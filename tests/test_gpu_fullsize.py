@@ -26,7 +26,8 @@ from oracle import pic, spectral
 from oracle import step as S
 from paper_2605_20140_amd import workloads as W
 
-from _parity import gpu_sim, min_image, oracle_params, oracle_state, rel_errors
+from _parity import (gpu_sim, gradient_tolerance, min_image, oracle_params, oracle_state,
+                     rel_errors)
 
 pytestmark = pytest.mark.gpu
 
@@ -55,21 +56,6 @@ def _oracle_first_step(name, **over):
     ref = dict(ic=ic, prm=prm, ubar=ubar, grad=grad, v=v1, m=m1, w=w1, ids=ids, X=X1, a=a1)
     _cache[key] = ref
     return ref
-
-
-def gradient_tolerance(v, grad, L, precision):
-    """Tolerance of the spectral gradient, an intermediate the state tolerances do not cover.
-    Rounding in the working precision (unit u = 2^-24 or 2^-53: the stored v and the
-    transforms, whose rms error grows like sqrt(log2 N^d)) is white across the spectrum, and
-    the derivative multiplies each frequency by (2 pi / L) |q_j|, whose rms over the grid is
-    (2 pi / L) N / (2 sqrt 3); relative to |grad v| that noise is
-    u sqrt(log2 N^d) (2 pi / L) N / (2 sqrt 3) |v| / |grad v|.  Twice that, and never below
-    the state tolerance, is the bound: it grows linearly with N (float32 at 512^3: 1.3e-3)."""
-    N, d = v.shape[0], v.ndim
-    u = 2.0 ** -24 if precision else 2.0 ** -53
-    amp = (2.0 * np.pi / L) * N / (2.0 * np.sqrt(3.0))
-    ratio = np.linalg.norm(v) / np.linalg.norm(np.stack(grad))
-    return max(TOL[precision], 2.0 * u * np.sqrt(np.log2(float(N) ** d)) * amp * ratio)
 
 
 def _check_fields(got, ref, tol, what):

@@ -10,7 +10,8 @@ from oracle import pic, spectral
 from oracle import step as S
 from paper_2605_20140_amd import workloads as W
 
-from _parity import compare_state, flags_of, gpu_sim, oracle_params, oracle_state, rel_errors
+from _parity import (compare_state, flags_of, gpu_sim, gradient_tolerance, oracle_params,
+                     oracle_state, rel_errors)
 
 pytestmark = pytest.mark.gpu
 
@@ -246,6 +247,36 @@ def test_three_pass_path_several_steps():
     compare_state(out, ref, TOL64)
     for j in range(3):
         assert max(rel_errors(g[j], aux["grad"][j])) < 1e-11, j
+
+
+_ic256 = {}
+
+
+@pytest.mark.parametrize("H0", [0.0, 128.0])
+def test_three_pass_path_float32(H0):
+    """Float32 at N = 256, the smallest grid whose planes no longer fit the LDS in float32:
+    two steps of the three-pass path without the filter (grad v as per-axis round trips) and
+    with it (full transforms of v, eq. gradv with the low-pass factor), state at the float32
+    bound and each gradient component within the bound of its rounding (gradient_tolerance)."""
+    if not _ic256:
+        _ic256["ic"] = W.make_initial_state("modes64", N=256, P=1 << 15)
+    ic = _ic256["ic"]
+    sim = gpu_sim(ic, precision=1, H0=H0)
+    sim.step(2)
+    out = sim.fields()
+    _, g = sim.aux()
+    sim.close()
+    prm = oracle_params(ic["params"], H0=H0)
+    st = oracle_state(ic)
+    ref, aux = None, None
+    for _ in range(2):
+        ref, aux = S.step(st, prm, return_aux=True)
+        st = ref
+    errs = compare_state(out, ref, TOL32)
+    tol_g = gradient_tolerance(ref.v, aux["grad"], prm.L, 1)
+    gerr = [max(rel_errors(g[j], aux["grad"][j])) for j in range(3)]
+    print(f"three-pass float32 H0 {H0}: state {errs}, gradient {gerr} (bound {tol_g:.3g})")
+    assert max(gerr) < tol_g, (gerr, tol_g)
 
 
 # ---- low-pass filter exp(-2 pi^2 |q|^2 / H0^2) (Alg. p2g text, Alg. sipf-pic) ----
