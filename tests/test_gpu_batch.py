@@ -60,3 +60,28 @@ def test_batch_mixes_fft_paths():
         assert np.abs(out["a"] / solo[k]["a"] - 1).max() < 1e-12
         assert out["diag"]["step"] == 4
         s.close()
+
+
+def test_batch_fourth_order():
+    """A float64 batch with the fourth-order deposit (an 8^3 and a 32^3 simulation: the
+    global-atomic and LDS region paths of that deposit): each equals its solo run."""
+    from paper_2605_20140_amd import sipf
+    ics = [W.make_initial_state("blob16", N=8, P=700, ic_seed=5),
+           W.make_initial_state("blob16", N=32, P=20000, ic_seed=6)]
+    solo = []
+    for k, ic in enumerate(ics):
+        s = gpu_sim(ic, precision=0, sim_id=k, deposit_order=4)
+        s.step(5)
+        solo.append(s.fields())
+        s.close()
+    sims = [gpu_sim(ic, precision=0, sim_id=k, deposit_order=4) for k, ic in enumerate(ics)]
+    sipf.step_batch(sims, 5)
+    for k, s in enumerate(sims):
+        out = s.fields()
+        for f in ("v", "m", "w"):
+            assert max(rel_errors(out[f], solo[k][f])) < 1e-12, (k, f)
+        d = out["X"] - solo[k]["X"]
+        assert np.abs(d - np.round(d)).max() < 1e-12
+        assert np.abs(out["a"] / solo[k]["a"] - 1).max() < 1e-12
+        assert out["diag"]["step"] == 5
+        s.close()
