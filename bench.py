@@ -40,9 +40,13 @@ def stage_bytes(N, P, s, lowpass=False):
     G = N ** 3
     half = (N // 2 + 1) * N * N * 2 * s  # one half spectrum
     plane = plane_path(N, s)
+    # float32 takes the m and w solves in change form (m* and w* stored by the forward z pass
+    # and read back by the inverse one); float64 in plain form
+    change = s == 4
     return {
-        # reads ubar, m, v, w; writes v, m* and w* (into ubar's array); 3 half spectra
-        "zfwd": G * 4 * s + G * 3 * s + 3 * half,
+        # reads ubar, m, v, w; writes v, and m* and w* (into ubar's array) in change form, or
+        # clears ubar's array; 3 half spectra
+        "zfwd": G * 4 * s + G * (3 if change else 2) * s + 3 * half,
         # M, W transformed in place; V read, its y derivative written (with the filter V in
         # place as well)
         "yfwd": 0 if plane else 6 * half,
@@ -50,9 +54,9 @@ def stage_bytes(N, P, s, lowpass=False):
         "xpass": (3 + 4 + (1 if lowpass else 0)) * half if plane else (8 if lowpass else 6) * half,
         # M, W in place; with the filter also d1 V in place and the filtered V -> V, d2 V
         "yinv": 0 if plane else (9 if lowpass else 4) * half,
-        # reads 5 half spectra, m* and w*; writes m, w, the gather array (4 per node) and the
-        # cleared ubar
-        "zinv": 5 * half + 2 * G * s + G * 7 * s,
+        # reads 5 half spectra (and m*, w* in change form); writes m, w, the gather array (4
+        # per node) and, in change form, the cleared ubar
+        "zinv": 5 * half + (9 if change else 6) * G * s,
         # particles: read x,y,z,a; write x,y,z,a (the 4-byte particle index that keys the
         # noise is not counted) + gather array read once + deposit target written once
         "particles": P * (6 * s + 16) + G * 5 * s,

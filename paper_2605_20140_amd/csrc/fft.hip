@@ -10,13 +10,14 @@
 //
 // Passes per step (each one kernel):
 //   zfwd : reaction (eq. g_hat_phy with S of eq. g_t) on (ubar, m, v, w) at time n, writes
-//          v^{n+1}, m* (into m) and w* (into ubar^n's array); real z transforms of m*, w*
+//          v^{n+1} and, for the solves in change form (float32), m* (into m) and w* (into
+//          ubar^n's array; float64 clears that array here); real z transforms of m*, w*
 //          (packed as m* + i w*) and of v^{n+1} (two rows packed) -> SM, SW, SV.
 //   yfwd : y transforms of SM and SW (in place).  V needs only its three derivatives, each a
 //          round trip along its own axis after the z transform: this pass makes the y one,
 //          SGy = inverse y (i (2 pi/L) q_2 y transform of SV).
-//   xpass: x transforms, the diagonal multipliers of eq. k_q_tilde_update in change form
-//          (m: decay beta, diffusion D_m; w: decay 1, diffusion D_w) and, for SV, the
+//   xpass: x transforms, the diagonal multipliers of eq. k_q_tilde_update (M - 1 in change
+//          form; m: decay beta, diffusion D_m; w: decay 1, diffusion D_w) and, for SV, the
 //          x-derivative multiplier of eq. gradv (i (2 pi/L) q_1, Nyquist zeroed), inverse x
 //          transforms -> SM, SW, SGx.
 //   yinv : inverse y transforms of SM and SW.
@@ -29,10 +30,10 @@
 //          leaves x (and, without the filter, y) in physical space, which sets the scale of
 //          the derivatives formed from it (gz_scale).
 //   zinv : forms the z-derivative spectrum i (2 pi/L) q_3 SVg, inverse real z transforms of
-//          (SM, SW), (SGx, SGy) and of row pairs of the z derivative; writes m^{n+1} =
-//          m* + change, w^{n+1} = w* + change (the solves in change form, below), the gather
-//          array of the next step g4 = (d1 v^{n+1}, d2 v^{n+1}, d3 v^{n+1}, w^{n+1}), and
-//          clears ubar^n's array for the next step's deposit.
+//          (SM, SW), (SGx, SGy) and of row pairs of the z derivative; writes m^{n+1} and
+//          w^{n+1} (in change form m* + change and w* + change, then clearing ubar^n's array
+//          for the next step's deposit; see the solves below), and the gather array of the
+//          next step g4 = (d1 v^{n+1}, d2 v^{n+1}, d3 v^{n+1}, w^{n+1}).
 // The particle pass of step n gathers (grad v^n, w^n) from the array the previous step's
 // passes formed (at initialisation, these passes run once in gradient-only mode on v^0, w^0),
 // so the field passes and the particle pass of one step are independent and run side by
@@ -483,18 +484,23 @@ __device__ __forceinline__ int deriv_freq(int k, int N) {
 // signed frequency for |q|^2 (Nyquist kept as -N/2)
 __device__ __forceinline__ int lap_freq(int k, int N) { return k < (N >> 1) ? k : k - N; }
 
-// The diffusion-decay solves (eq. k_q_tilde_update) in change form: for f = m, w,
-// f^{n+1} = f* + IFFT((M - 1) FFT(f*)), M the solve's multiplier of one Fourier mode times
-// the low-pass factor lp (1 without the filter).  The inverse pass adds f* back, so that the
-// rounding of the transforms, relative to the transformed values, is scaled by the small
-// M - 1 instead of reaching f^{n+1} in full at every step (with float32 transforms it would
-// accumulate in m and w, and through v' = v exp(-alpha tau m) in v).
-// Implicit multiplier, c = tau (R + D |k|^2): M - 1 = lp / (1 + c) - 1 = (lp - 1 - c) / (1 + c).
-// In float32 the quotient takes the hardware reciprocal (within 1 ulp; 1 + c >= 1) instead of
-// the correctly rounded division sequence: about ten instructions less per mode.
+// The diffusion-decay solves (eq. k_q_tilde_update), for f = m, w, with M the solve's
+// multiplier of one Fourier mode times the low-pass factor lp (1 without the filter).
+// Float32 takes them in change form, f^{n+1} = f* + IFFT((M - 1) FFT(f*)): the inverse pass
+// adds f* back, so that the rounding of the transforms, relative to the transformed values,
+// is scaled by the small M - 1 instead of reaching f^{n+1} in full at every step (it would
+// accumulate in m and w, and through v' = v exp(-alpha tau m) in v).  Float64, whose
+// transforms round five hundred million times finer, takes the plain form
+// f^{n+1} = IFFT(M FFT(f*)), so that m* and w* need not go through HBM between the passes.
+template <typename T> constexpr bool change_form() { return sizeof(T) == 4; }
+// Implicit multiplier, c = tau (R + D |k|^2): M = lp / (1 + c); in change form
+// M - 1 = (lp - 1 - c) / (1 + c).  In float32 the quotient takes the hardware reciprocal
+// (within 1 ulp; 1 + c >= 1) instead of the correctly rounded division sequence: about ten
+// instructions less per mode.
 template <typename T>
 __device__ __forceinline__ T solve_multiplier(T c, T lp) {
-  return (lp - (T)1 - c) / ((T)1 + c);
+  static_assert(!change_form<T>(), "float32 is specialised below");
+  return lp / ((T)1 + c);
 }
 template <>
 __device__ __forceinline__ float solve_multiplier<float>(float c, float lp) {
@@ -503,7 +509,7 @@ __device__ __forceinline__ float solve_multiplier<float>(float c, float lp) {
 // the same for a tabulated multiplier M (exponential or aliased kernel)
 template <typename T>
 __device__ __forceinline__ T table_multiplier(T M, T lp) {
-  return M * lp - (T)1;
+  return change_form<T>() ? M * lp - (T)1 : M * lp;
 }
 
 // ---- zfwd ---------------------------------------------------------------------------------
@@ -554,7 +560,8 @@ __device__ __forceinline__ void zfwd_body(SimC<T>& d, int lb, unsigned char* sme
       } else if (e < nel) {
         const int rr = e >> LG, iz = e & (N - 1);
         const T ms = mm[k] + dt * u[k];
-        if (!freeze_m) d.m[g0 + e] = ms;  // m*: the inverse pass adds the solve's change
+        // change form: m* in place of m, for the inverse pass to add the solve's change to
+        if (change_form<T>() && !freeze_m) d.m[g0 + e] = ms;
         const T eta = (T)2 * u[k] / ((T)1 + u[k]);
         const T wsr = ww[k] + dt * (gam * vv[k] - eta * ww[k]);
         T vn = vv[k];
@@ -566,9 +573,10 @@ __device__ __forceinline__ void zfwd_body(SimC<T>& d, int lb, unsigned char* sme
           vn = impl_v ? vv[k] - vv[k] * (y / ((T)1 + y)) : fma(vv[k], expm1(-y), vv[k]);
           d.v[g0 + e] = vn;
         }
-        // w* goes into ubar^n's array, which this step needs no more: the inverse pass adds
-        // it to the solve's change and clears the array for the next step's deposit
-        ub[g0 + e] = wsr;
+        // ubar^n's array, which this step needs no more, is the next step's deposit target: in
+        // change form it holds w* until the inverse pass has added it to the solve's change
+        // and cleared the array; in plain form it is cleared here
+        ub[g0 + e] = change_form<T>() ? wsr : (T)0;
         A[rr * LS + iz] = cplx<T>{ms, wsr};
         // v^{n+1}: its gradient is the next step's gather array
         T* vp = reinterpret_cast<T*>(&Vp[(rr >> 1) * LS + iz]);
@@ -1022,7 +1030,7 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
   const bool freeze_w = d.flags & SIPF_FLAG_FREEZE_W;
   const bool grad_only = mode == kGradOnly;
   const uint32_t par = (uint32_t)(*d.step) & 1u;
-  T* const ub = d.ubar[par];  // holds w* (see zfwd)
+  T* const ub = d.ubar[par];  // holds w* in change form (see zfwd)
   // the gather array of step n + 1, or with grad_only that of step n
   vec4<T>* const gout = d.g4[grad_only ? par : par ^ 1u];
   constexpr int ZB = ZBatch<T>::n, ZR = ZBatches<T>::n;
@@ -1032,11 +1040,13 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
   const int n1 = H * Bh;  // (k3, row pair) items
   // spectra of IB items per thread loaded together
   constexpr int IB = sizeof(T) == 4 ? 2 : 1;
-  // m* and w* of the first ZB elements per thread (w^n instead of w* when w is frozen or
-  // only the gradient is formed; m* not at all when m is frozen) are loaded first: they are
-  // needed only after the transforms, so their loads overlap everything before.  wk keeps w
-  // of every element of the thread for the gather array.
-  const bool need_wold = grad_only || freeze_w, need_m = !grad_only && !freeze_m;
+  // m* and w* of the first ZB elements per thread (change form only; w^n instead of w* when
+  // w is frozen or only the gradient is formed, in both forms; m* not at all when m is
+  // frozen) are loaded first: they are needed only after the transforms, so their loads
+  // overlap everything before.  wk keeps w of every element of the thread for the gather
+  // array.
+  const bool need_wold = grad_only || freeze_w, write_m = !grad_only && !freeze_m;
+  const bool need_m = change_form<T>() && write_m, need_wst = change_form<T>() && !need_wold;
   T wold[ZB], mold[ZB], wst[ZB], wk[ZR * ZB];
 #pragma unroll
   for (int k = 0; k < ZB; ++k) {
@@ -1044,7 +1054,7 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
     if (e < nel) {
       if (need_wold) wold[k] = d.w[g0 + e];
       if (need_m) mold[k] = d.m[g0 + e];
-      if (!need_wold) wst[k] = ub[g0 + e];
+      if (need_wst) wst[k] = ub[g0 + e];
     }
   }
   TwiddleRegs<T, LG, kThreads> tr;
@@ -1093,7 +1103,7 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
         if (e < nel) {
           if (need_wold) wold[k] = d.w[g0 + e];
           if (need_m) mold[k] = d.m[g0 + e];
-          if (!need_wold) wst[k] = ub[g0 + e];
+          if (need_wst) wst[k] = ub[g0 + e];
         }
       }
     }
@@ -1105,13 +1115,14 @@ __device__ __forceinline__ void zinv_body(SimC<T>& d, int lb, unsigned char* sme
       const int rr = e >> LG, iz = e & (N - 1);
       const int64_t g = g0 + e;
       const cplx<T> mw = MW[rr * LS + iz];
-      if (need_m) d.m[g] = mold[k] + mw.x;  // m^{n+1} = m* + change (frozen m: unchanged)
+      // m^{n+1} = m* + change, or the transform itself in plain form (frozen m: unchanged)
+      if (write_m) d.m[g] = change_form<T>() ? mold[k] + mw.x : mw.x;
       if (!freeze_w) {
-        const T wn = wst[k] + mw.y;
+        const T wn = change_form<T>() ? wst[k] + mw.y : mw.y;
         d.w[g] = wn;
         wk[r * ZB + k] = wn;
       }
-      ub[g] = (T)0;  // cleared for the deposit of the next step's particle pass
+      if (change_form<T>()) ub[g] = (T)0;  // cleared for the next step's deposit
     }
   }
   // ---- second phase: the gradient of v ----
