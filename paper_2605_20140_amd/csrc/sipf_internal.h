@@ -272,12 +272,13 @@ __device__ __forceinline__ unsigned long long order_key(double d) {
 
 // ---- launchers (defined in fft.hip, particles.hip, diag.hip) ------------------------------
 template <typename T> int elems_per_block();
-// Elements per block of the z inverse pass.  Its LDS holds 2.5 lines per row, so at
-// N <= 128 float32 blocks of 1024 elements (half the forward pass's) let five blocks share
-// a CU instead of three, which pays while a block's runs along a spectrum row stay a full
-// 64 bytes (8 rows); at N >= 256 they would be shorter, so the pass keeps 2048.
-// Most elements a z inverse block holds: its threads keep every element's w (and, before the
-// transforms, m* and w*) in registers, 8 per thread (ZBatch x ZBatches in fft.hip).
+// Elements per block of the z inverse pass: at N <= 128 float32 blocks of 1024 elements (half
+// the forward pass's; more blocks share a CU), which pays while a block's runs along a
+// spectrum row stay a full 64 bytes (8 rows); at N >= 256 they would be shorter, so the pass
+// keeps 2048.
+// Most elements a z inverse block holds: its threads keep every element's w (and, for the
+// float32 solves in change form, m* and w* before the transforms) in registers, 8 per thread
+// (ZBatch x ZBatches in fft.hip).
 constexpr int zinv_max_elems() { return 8 * kThreads; }
 template <typename T> inline int zinv_elems(int N) {
   return sizeof(T) == 4 && N <= 128 ? 1024 : elems_per_block<T>();
