@@ -531,12 +531,16 @@ int capture_t(sipf_sim* sim) {
   HIPCHK(hipStreamEndCapture(sim->cap, &sim->graph));
   HIPCHK(hipGetLastError());
   HIPCHK(hipGraphInstantiate(&sim->exec, sim->graph, nullptr, nullptr, 0));
+  // uploaded now, so that no step pays for it: a graph's first launch would otherwise carry
+  // its upload (the binning step's falls in whatever run first re-bins)
+  HIPCHK(hipGraphUpload(sim->exec, sim->stream));
   HIPCHK(hipStreamBeginCapture(sim->cap, hipStreamCaptureModeThreadLocal));
   enqueue_step<T>(b, sim->counts, 1, groups.data(), (int)groups.size(), 1, p.deposit_order,
                   dim, sim->cap, &sim->fork);
   HIPCHK(hipStreamEndCapture(sim->cap, &sim->graph_bin));
   HIPCHK(hipGetLastError());
   HIPCHK(hipGraphInstantiate(&sim->exec_bin, sim->graph_bin, nullptr, nullptr, 0));
+  HIPCHK(hipGraphUpload(sim->exec_bin, sim->stream));
   return SIPF_OK;
 }
 
@@ -811,6 +815,8 @@ int build_batch_graph(sipf_sim* const* sims, int nsims, int dev, BatchGraph** ou
     if (rc == SIPF_OK)
       chk(hipGraphInstantiate(&e->exec[bin], e->graph[bin], nullptr, nullptr, 0),
           "hipGraphInstantiate");
+    // uploaded on the stream the batch steps on, so that its first step does not carry it
+    if (rc == SIPF_OK) chk(hipGraphUpload(e->exec[bin], sims[0]->stream), "hipGraphUpload");
   }
   if (rc != SIPF_OK) {
     free_batch_graph(e);
