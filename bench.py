@@ -16,6 +16,7 @@ import hashlib
 import math
 import json
 import os
+import re
 import sys
 import time
 
@@ -90,11 +91,19 @@ KERNEL_SOURCES = ("paper_2605_20140_amd/csrc/particles.hip",
 COPY_CAL_BYTES = 512 << 20
 
 
+def _code_text(src):
+    """Source text without comments and with whitespace runs collapsed: what the compiler sees
+    of it, so that an edit of a comment does not invalidate a measurement of the kernel."""
+    src = re.sub(r"/\*.*?\*/", " ", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", " ", src)
+    return " ".join(src.split())
+
+
 def sources_digest():
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f), "r", encoding="utf-8") as fh:
+            h.update(_code_text(fh.read()).encode())
     return h.hexdigest()[:16]
 
 

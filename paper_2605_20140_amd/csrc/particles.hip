@@ -241,9 +241,10 @@ constexpr int kWaitVmcnt0 = 0x0F70;
 template <typename T> struct LdsAccT { using type = double; };
 template <typename T> using LdsAcc = typename LdsAccT<T>::type;
 
-// Particles per load batch.  3D float32: six, which with a cap of 96 VGPRs lets five waves
-// per SIMD run (the LDS region of 32 KB allows five blocks per CU): 154.5 us against 158-161 us
-// with eight particles at four waves.  The 2D pass keeps eight (LoadBatch2).
+// Particles per load batch: four in the 3D pass of both forms.  The float32 pass issues the
+// batch's gather loads before its noise is drawn and fits in 84 VGPRs, so that five waves per
+// SIMD run, as many as the 32-KB LDS region of a 4-wave block allows on one CU.  The 2D pass
+// keeps eight in float32 (LoadBatch2).
 template <typename T> struct LoadBatch { static constexpr int n = 4; };
 // float32 3D pass: gather loads issued before the noise is drawn
 constexpr bool kEarlyGather = true;
